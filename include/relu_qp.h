@@ -1,0 +1,159 @@
+/*
+ * relu_qp.h -- C ABI of the MI355X (gfx950) ReLU-QP solver.
+ *
+ * Solves the convex QP of arXiv 2311.18056, Sec. II-A (eq. qp_def):
+ *
+ *     minimise 1/2 x'Px + q'x   subject to   l <= A x <= u,
+ *
+ * with the ADMM iteration recast as a weight-tied layer (Sec. III-A, eq. gpu_update) and run
+ * as in Algorithm 1: an offline stage that forms the KKT inverse
+ * D_j = (P + sigma I + A' diag(rho_j) A)^-1 for every penalty value rho_j of a fixed grid
+ * (Sec. III-C, penalty heuristics), and an online stage that repeats "matvec, clamp, dual
+ * update" with a residual check (eqs. primal, dual) and a penalty switch (eq. rho_update)
+ * every check_interval iterations (Sec. III-C, convergence checking).
+ *
+ * Letters follow OSQP: the paper's (H, g, G, c, d) are (P, q, A, l, u); its primal y is x, its
+ * constraint copy z is z, and its multiplier lambda is y.
+ *
+ * Conventions for every function:
+ *   - return value: RQP_OK (0) or a negative RQP_E* code; nothing else crosses the ABI;
+ *     relu_qp_last_error() gives a message for the calling thread's last failure;
+ *   - matrices are dense, row-major, FP64, on the HOST unless the name says "device";
+ *   - inputs are borrowed for the duration of the call only (the library copies them);
+ *   - a handle owns all device memory it allocates and is not thread-safe; distinct handles
+ *     are independent;
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ */
+#ifndef RELU_QP_H
+#define RELU_QP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+enum {
+  RQP_OK = 0,
+  RQP_EINVAL = -1, /* bad argument: sizes, non-finite P or A, asymmetric P, l > u, settings */
+  RQP_ENOMEM = -2, /* device allocation failed */
+  RQP_EHIP = -3,   /* a HIP runtime call failed (message from relu_qp_last_error) */
+  RQP_ENOTPD = -4, /* P + sigma I + A' diag(rho) A is not positive definite for some rho */
+  RQP_ESTATE = -5  /* NULL handle, or a call out of order */
+};
+
+/* per-instance solver status written by relu_qp_solve (Algorithm 1's loop exits) */
+enum {
+  RQP_RUNNING = 0,
+  RQP_SOLVED = 1,    /* r_p <= eps_p and r_d <= eps_d at a check (eqs. primal, dual) */
+  RQP_MAX_ITER = 2,  /* max_iter reached (also for infeasible problems: no detection) */
+  RQP_NONFINITE = 3, /* a residual norm was NaN or infinite */
+  RQP_ABORTED = 4,   /* relu_qp_abort() was seen at a check */
+  RQP_INTERNAL = 5   /* the in-kernel exchange timed out (a library fault, never expected) */
+};
+
+/* arithmetic of the online iteration */
+enum {
+  RQP_FP64 = 0, /* FP64 weights, iterates and residuals */
+  RQP_FP32 = 1  /* FP32 weights and iterates; residual products accumulated in FP64 */
+};
+
+typedef struct {
+  double sigma;        /* proximal weight sigma > 0 (Sec. II-B); default 1e-6 */
+  double alpha;        /* over-relaxation in (0, 2); 1 gives the paper's iteration; default 1.6 */
+  double rho0;         /* initial penalty (Sec. III-C: 0.1); the grid value nearest in log */
+  int n_rho;           /* 1: fixed penalty rho0; >1: log grid rho_min..rho_max (default 1) */
+  double rho_min;      /* default 1e-3 */
+  double rho_max;      /* default 1e3 */
+  double rho_eq_scale; /* penalty factor on rows with l_i == u_i (Sec. II-B: 1000) */
+  double eps_abs;      /* eps = eps_abs + eps_rel * max(norms); both 0: run exactly max_iter */
+  double eps_rel;
+  int max_iter;        /* default 4000 */
+  int check_interval;  /* default 25 (Sec. III-C); a check also runs at max_iter */
+  int precision;       /* RQP_FP64 or RQP_FP32 */
+  int batch;           /* instances sharing P and A (>= 1); the multi-workgroup path needs 1 */
+} relu_qp_settings;
+
+typedef struct relu_qp_handle relu_qp_handle; /* opaque, library-owned */
+
+/* Caller-owned DEVICE buffers the solve writes, asynchronously on its stream.
+ * x: batch*n, y (dual) and z: batch*m, in the iterate precision (double for RQP_FP64,
+ * float for RQP_FP32), instance-major. iterations, status, rho_index: batch ints.
+ * rho_hist (ints), prim_res and dual_res (doubles): batch * relu_qp_max_checks() entries,
+ * one per check (grid index in force after the check, r_p, r_d); each may be NULL. */
+typedef struct {
+  void* x;
+  void* y;
+  void* z;
+  int* iterations;
+  int* status;
+  int* rho_index;
+  int* rho_hist;
+  double* prim_res;
+  double* dual_res;
+} relu_qp_result;
+
+/* Fills *s with the defaults above. */
+void relu_qp_default_settings(relu_qp_settings* s);
+
+/* Offline stage of Algorithm 1 (Sec. III-B): validates the problem, copies it to the device
+ * and forms, in FP64 on the GPU, the layer weights of every grid penalty.
+ *   P: n*n symmetric positive semidefinite; A: m*n; q: batch*n; l, u: batch*m, -/+INFINITY
+ *   allowed, l <= u. The equality-row pattern (l_i == u_i) is taken from the first instance.
+ * Synchronises before returning (it must report RQP_ENOTPD). On success *h is a new handle;
+ * on failure *h is NULL and nothing is leaked. */
+int relu_qp_setup(relu_qp_handle** h, int n, int m, const double* P, const double* q, const double* A,
+                  const double* l, const double* u, const relu_qp_settings* s, void* stream);
+
+/* Online stage, "update b, c~, d~" of Algorithm 1: new q (batch*n), l, u (batch*m) from the
+ * host; NULL leaves a vector unchanged. RQP_EINVAL if l > u or the equality-row pattern
+ * changes (the weights depend on it). Synchronous. */
+int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const double* u);
+
+/* Same, from DEVICE FP64 buffers, asynchronously on stream; no validation of l <= u. */
+int relu_qp_update_device(relu_qp_handle* h, const double* q, const double* l, const double* u, void* stream);
+
+/* Parametric (MPC) data, Sec. IV: q = F x0, l = lo - E x0, u = hi - E x0 with F (n*nx) and
+ * E (m*nx) row-major. Copies F, E, lo, hi to the device. Synchronous. */
+int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const double* E, const double* lo,
+                           const double* hi);
+
+/* Online update from initial states: x0 is a DEVICE FP64 array of batch*nx values; computes
+ * q, l, u of every instance on the GPU, asynchronously on stream. */
+int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream);
+
+/* Warm start (Sec. II-B): the next solve starts from x (n), y (m) and grid index rho_index,
+ * with z = A x. Host FP64 arrays for instance 0 (batch must be 1). Synchronous. */
+int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int rho_index);
+
+/* enabled != 0: every later solve starts from the previous solve's x, y and penalty, with
+ * z = A x (the receding-horizon use of Sec. V-B). 0 (the default): cold starts. */
+int relu_qp_set_warm(relu_qp_handle* h, int enabled);
+
+/* Online loop of Algorithm 1, asynchronously on stream: one persistent kernel launch runs
+ * every iteration, check and penalty switch. Results go to out (caller-owned device buffers);
+ * read them after a stream synchronisation. */
+int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out);
+
+/* Ask a running solve to stop at its next check with status RQP_ABORTED (any thread). */
+int relu_qp_abort(relu_qp_handle* h);
+
+/* Sizes of the result arrays and the grid. */
+int relu_qp_max_checks(const relu_qp_handle* h);
+int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid /* n_rho */, int* n_rho);
+
+/* Launch shape of the persistent kernel: grid = number of workgroups (one per compute unit
+ * by default; 0 restores the default); it must lie in [ceil((n+m)/64), min(n+m, the
+ * cooperative limit)]. relu_qp_get_launch reports the grid and the workgroup size. */
+int relu_qp_set_launch(relu_qp_handle* h, int grid);
+int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block);
+
+/* Frees everything the handle owns; NULL is a no-op. Synchronises the device. */
+int relu_qp_cleanup(relu_qp_handle* h);
+
+/* Message of the calling thread's last failed call ("" if none). Never NULL. */
+const char* relu_qp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RELU_QP_H */

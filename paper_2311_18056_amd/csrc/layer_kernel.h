@@ -1,0 +1,58 @@
+// Online-stage kernel of the ReLU-QP solver: the whole loop of Algorithm 1 in one launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rqp {
+
+// Arguments of one persistent solve. Vectors are in the iterate precision T unless noted.
+struct LayerArgs {
+  int n, m, L;          // L = n + m rows of the compact layer
+  long ldw;             // leading dimension of the layer and check matrices (elements)
+  const void* W;        // n_rho layer matrices [D, DA'; AD, ADA'] (L x ldw each, T)
+  long w_stride;        // elements between consecutive penalty matrices
+  const void* C;        // check matrix [P, A'; A, 0] (L x ldw, T)
+  const void* q;        // n
+  const void* l;        // m
+  const void* u;        // m
+  const unsigned char* eq;  // m flags: l_i == u_i
+  const double* grid;   // n_rho penalty values
+  const double* mid;    // n_rho - 1 geometric midpoints between neighbouring grid values
+  int n_rho;
+  double sigma, alpha, eps_abs, eps_rel, rho_eq_scale;
+  int max_iter, check_interval, terminate, warm, j0;
+  void* xs;             // handle state x (n), z (m), y (m): read on a warm start, written at exit
+  void* zs;
+  void* ys;
+  int* js;              // handle state penalty index
+  void* xo;             // caller outputs (device)
+  void* zo;
+  void* yo;
+  int* iterations;
+  int* status;
+  int* rho_index;
+  int* rho_hist;        // per check, may be null
+  double* prim_res;     // per check, may be null
+  double* dual_res;     // per check, may be null
+  uint64_t* xw;         // exchange words: layer input, 2 parities x L x words
+  uint64_t* xc;         // exchange words: check vector [x; y], 2 x L x words
+  uint64_t* xn;         // exchange words: norm partials, 2 x G x 8 x 2
+  uint32_t tag;         // first tag of this solve (tags tag .. tag + max_iter + 1 are used)
+  const int* abort_flag;  // host-mapped int, polled at checks
+  unsigned* err;        // device word: set when an exchange times out
+};
+
+// Rows per workgroup are at most kMaxRows; the host picks the grid accordingly.
+constexpr int kLayerBlock = 1024;
+constexpr int kMaxRows = 64;
+
+// Launch the persistent solve as a cooperative grid of `grid` workgroups of kLayerBlock threads.
+// T = float or double. Returns the HIP error of the launch.
+template <typename T>
+hipError_t launch_layer(const LayerArgs& a, int grid, hipStream_t st);
+
+// Largest grid the cooperative launch accepts for this precision and problem size.
+template <typename T>
+int max_layer_grid(int L);
+
+}  // namespace rqp

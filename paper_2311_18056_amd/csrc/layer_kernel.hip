@@ -1,0 +1,538 @@
+// Persistent ReLU-QP layer kernel for gfx950: every iteration, check and penalty switch of
+// Algorithm 1 (online stage) in one cooperative launch.
+//
+// Iteration (Sec. III-A; OSQP over-relaxation alpha; alpha = 1 is the paper's layer). With
+// w = [sigma x - q ; rho z - y] and the compact layer matrix
+//     Wc_j = [I; A] D_j [I, A'] = [D_j, D_j A'; A D_j, A D_j A'],   D_j = (P + sigma I + A' rho_j A)^-1,
+// one matvec gives both xt = D_j (sigma x - q + A'(rho z - y)) and s = A xt. Then
+//     x <- alpha xt + (1 - alpha) x
+//     t  = alpha s + (1 - alpha) z + y / rho,   z <- clamp(t, l, u),   y <- rho (t - z)
+// are row-local, and the next w is row-local too. This is the paper's "v <- clamp(W v + b)"
+// (eq. gpu_update) with an (n+m)^2 weight instead of its (n+2m)^2 one: the paper's W also
+// precomputes the products of D with A.
+//
+// Parallel layout: workgroup g owns a contiguous block of rows of Wc (row-parallel, Sec.
+// III-A). Lane t of a workgroup owns the columns c = t + 1024 k of every row of the block and
+// keeps the first NRS rows of its columns in registers for the whole solve (reloaded only
+// when the penalty changes); further rows stream from memory. After the row-local update each
+// row owner publishes its entry of the next w as an 8-byte {value, tag} word; every lane polls
+// the words of its own columns until the tags match. That single round trip is both the data
+// exchange and the synchronisation: there is no grid barrier.
+//
+// Every check_interval iterations (Sec. III-C) the owners publish [x; y], every workgroup
+// forms its rows of [P, A'; A, 0][x; y] with FP64 accumulation, reduces seven inf-norms as
+// ordered bit patterns (exact and order-independent, NaN-propagating), publishes them, and
+// every workgroup reduces all partials itself. All workgroups therefore take bit-identical
+// decisions (eqs. primal, dual and rho_update) without a broadcast.
+#include "layer_kernel.h"
+
+#include "device_common.h"
+
+namespace rqp {
+namespace {
+
+constexpr int BS = kLayerBlock;
+constexpr int NWAVE = BS / kWave;
+constexpr unsigned kSpinLimit = 1u << 22;
+constexpr int RC = 1;  // rows per chunk for streamed rows and check rows
+
+enum { ST_RUNNING = 0, ST_SOLVED = 1, ST_MAX_ITER = 2, ST_NONFINITE = 3, ST_ABORTED = 4, ST_INTERNAL = 5 };
+enum { N_RP = 0, N_RD, N_AX, N_Z, N_PX, N_ATY, N_Q, N_FLAGS };
+
+// The error word holds the tag of the solve that failed, so a failure never leaks into a later
+// solve (each solve has its own tag range).
+__device__ __forceinline__ bool err_set(const unsigned* err, uint32_t tag) {
+  return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag;
+}
+__device__ __forceinline__ void err_raise(unsigned* err, uint32_t tag) {
+  __hip_atomic_store(err, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Poll the exchange words of this lane's columns until every tag equals `tag`.
+template <typename T, int NC>
+__device__ __forceinline__ bool gather(const uint64_t* buf, int L, uint32_t tag, T (&v)[NC], const unsigned* err,
+                                       uint32_t etag) {
+  constexpr int NW = LLWords<T>::kWords;
+  uint64_t w[NC][NW];
+  const int tid = threadIdx.x;
+  const uint64_t dummy = (uint64_t)tag << 32;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int c = tid + BS * k;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) w[k][q] = (c < L) ? ll_load_word(buf + (long)c * NW + q) : dummy;
+  }
+  unsigned spins = 0;
+  bool ok = true;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int c = tid + BS * k;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        if (ll_tag(w[k][q]) != tag) {
+          all = false;
+          w[k][q] = ll_load_word(buf + (long)c * NW + q);
+        }
+      }
+    }
+    if (all) break;
+    if ((++spins & 255u) == 0u && (spins > kSpinLimit || err_set(err, etag))) {
+      ok = false;
+      break;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    if constexpr (NW == 1)
+      v[k] = ll_value_f(w[k][0]);
+    else
+      v[k] = bits_to_double(ll_bits64(w[k][0], w[k][1]));
+  }
+  return ok;
+}
+
+// Poll the 2-word FP64 norm partials of all workgroups; lane t reduces entries t + BS*i,
+// which all carry the same norm index t % 8.
+__device__ __forceinline__ bool gather_norms(const uint64_t* buf, int count, uint32_t tag, uint64_t& mx,
+                                             const unsigned* err, uint32_t etag) {
+  const int tid = threadIdx.x;
+  mx = 0;
+  bool ok = true;
+  for (int e = tid; e < count; e += BS) {
+    uint64_t lo = ll_load_word(buf + 2L * e), hi = ll_load_word(buf + 2L * e + 1);
+    unsigned spins = 0;
+    while (ll_tag(lo) != tag || ll_tag(hi) != tag) {
+      if (ll_tag(lo) != tag) lo = ll_load_word(buf + 2L * e);
+      if (ll_tag(hi) != tag) hi = ll_load_word(buf + 2L * e + 1);
+      if ((++spins & 255u) == 0u && (spins > kSpinLimit || err_set(err, etag))) {
+        ok = false;
+        break;
+      }
+    }
+    if (!ok) break;
+    uint64_t v = ll_bits64(lo, hi);
+    mx = v > mx ? v : mx;
+  }
+  return ok;
+}
+
+template <typename T, int NC>
+struct Cols {
+  T v[NC];
+};
+
+// Per-thread view of the row it owns (thread tid owns row r0 + tid of the block).
+template <typename T>
+struct RowState {
+  T sx, sz, sy, sq;
+  int R;
+  bool own, xrow;
+};
+
+// Rows of [P, A'; A, 0] [x; y] for the block, FP64 accumulation. Returns, for the owner
+// thread, the product with the x part (P x or A x) in p_out and with the y part (A'y) in a_out.
+template <typename T, int NC>
+__device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows, Cols<T, NC> cv, double& p_out,
+                                        double& a_out) {
+  __shared__ double redd[NWAVE][2 * kMaxRows];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int n = a.n, L = a.L;
+  const long ldw = a.ldw;
+  const T* Cm = static_cast<const T*>(a.C);
+  for (int rr = 0; rr < nrows; rr += RC) {
+    T cr[RC][NC];
+#pragma unroll
+    for (int b = 0; b < RC; ++b) {
+      const int Rr = r0 + rr + b;
+      const bool rv = rr + b < nrows;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int c = tid + BS * k;
+        const bool ld = rv && c < L && (Rr < n || c < n);
+        cr[b][k] = ld ? Cm[(long)Rr * ldw + c] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < RC; ++b) {
+      double p = 0.0, q2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int c = tid + BS * k;
+        const double v = (double)cr[b][k] * (double)cv.v[k];
+        if (c < n)
+          p += v;
+        else
+          q2 += v;
+      }
+      p = wave_sum(p);
+      q2 = wave_sum(q2);
+      if (lane == 0 && rr + b < nrows) {
+        redd[wave][2 * (rr + b)] = p;
+        redd[wave][2 * (rr + b) + 1] = q2;
+      }
+    }
+  }
+  __syncthreads();
+  p_out = 0.0;
+  a_out = 0.0;
+  if (tid < nrows) {
+    for (int w = 0; w < NWAVE; ++w) {
+      p_out += redd[w][2 * tid];
+      a_out += redd[w][2 * tid + 1];
+    }
+  }
+  __syncthreads();
+}
+
+struct CheckOut {
+  int status;  // ST_* (ST_RUNNING: continue)
+  int jn;      // grid index for the next iterations
+  bool ok;     // false: an exchange timed out
+};
+
+// Residual check (eqs. primal, dual), stopping test and penalty rule (eq. rho_update; nearest
+// grid value, Sec. III-C) at iteration k, check number nchk. Every workgroup returns the same
+// result.
+template <typename T, int NC>
+__device__ __forceinline__ CheckOut run_check(const LayerArgs& a, RowState<T> rs, int r0, int nrows, int k, int nchk,
+                                           int j) {
+  __shared__ uint64_t nred[NWAVE][8];
+  __shared__ uint64_t nfin[8];
+  constexpr int NW = LLWords<T>::kWords;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid % kWave, wave = tid / kWave;
+  const int L = a.L;
+  CheckOut out{ST_RUNNING, j, true};
+
+  // [x; y] to every workgroup
+  const uint32_t ctag = a.tag + (uint32_t)k;
+  uint64_t* xc = a.xc + (long)(nchk & 1) * L * NW;
+  if (rs.own) ll_store(xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, ctag);
+  Cols<T, NC> cv;
+  const bool ok2 = gather<T, NC>(xc, L, ctag, cv.v, a.err, a.tag);
+  if (__syncthreads_or(!ok2)) {
+    out.ok = false;
+    return out;
+  }
+  double pr, ar;
+  check_rows<T, NC>(a, r0, nrows, cv, pr, ar);
+  uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (rs.own) {
+    if (rs.xrow) {
+      nb[N_RD] = abs_bits(pr + (double)rs.sq + ar);
+      nb[N_PX] = abs_bits(pr);
+      nb[N_ATY] = abs_bits(ar);
+      nb[N_Q] = abs_bits((double)rs.sq);
+    } else {
+      nb[N_RP] = abs_bits(pr - (double)rs.sz);
+      nb[N_AX] = abs_bits(pr);
+      nb[N_Z] = abs_bits((double)rs.sz);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const uint64_t v = wave_max_u64(nb[i]);
+    if (lane == 0) nred[wave][i] = v;
+  }
+  __syncthreads();
+  if (tid < 8) {
+    uint64_t v = 0;
+    if (tid < 7) {
+      for (int w = 0; w < NWAVE; ++w) v = nred[w][tid] > v ? nred[w][tid] : v;
+    } else {
+      const bool ab = a.abort_flag && __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      v = err_set(a.err, a.tag) ? 2u : (ab ? 1u : 0u);
+    }
+    ll_store_bits64(a.xn + ((long)(nchk & 1) * G * 8 + (long)g * 8 + tid) * 2, v, ctag);
+  }
+  __syncthreads();
+  uint64_t mx;
+  const bool ok3 = gather_norms(a.xn + (long)(nchk & 1) * G * 8 * 2, G * 8, ctag, mx, a.err, a.tag);
+  // lanes with equal tid % 8 hold the same norm index
+#pragma unroll
+  for (int off = 8; off < kWave; off <<= 1) {
+    const uint64_t o = __shfl_xor(mx, off, kWave);
+    mx = o > mx ? o : mx;
+  }
+  if (lane < 8) nred[wave][lane] = mx;
+  if (__syncthreads_or(!ok3)) {
+    out.ok = false;
+    return out;
+  }
+  if (tid < 8) {
+    uint64_t v = 0;
+    for (int w = 0; w < NWAVE; ++w) v = nred[w][tid] > v ? nred[w][tid] : v;
+    nfin[tid] = v;
+  }
+  __syncthreads();
+
+  bool nonfinite = false;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) nonfinite |= nfin[i] >= kInfBits;
+  const double rp = bits_to_double(nfin[N_RP]), rd = bits_to_double(nfin[N_RD]);
+  const double nax = bits_to_double(nfin[N_AX]), nz = bits_to_double(nfin[N_Z]);
+  const double npx = bits_to_double(nfin[N_PX]), naty = bits_to_double(nfin[N_ATY]);
+  const double nq = bits_to_double(nfin[N_Q]);
+  const uint64_t flags = nfin[N_FLAGS];
+  __syncthreads();  // nfin and nred are reused by the next check
+  int st = ST_RUNNING;
+  if (nonfinite) {
+    st = ST_NONFINITE;
+  } else if (a.terminate) {
+    const double eps_p = a.eps_abs + a.eps_rel * fmax(nax, nz);
+    const double eps_d = a.eps_abs + a.eps_rel * fmax(fmax(npx, naty), nq);
+    if (rp <= eps_p && rd <= eps_d) st = ST_SOLVED;
+  }
+  if (st == ST_RUNNING && k == a.max_iter) st = ST_MAX_ITER;
+  if (st == ST_RUNNING && flags >= 2) st = ST_INTERNAL;
+  if (st == ST_RUNNING && flags == 1) st = ST_ABORTED;
+  int jn = j;
+  if (st == ST_RUNNING && a.n_rho > 1 && rp > 0.0 && rd > 0.0) {
+    const double num = rp * fmax(fmax(npx, naty), fmax(nq, 1e-4));
+    const double den = rd * fmax(fmax(nax, nz), 1e-4);
+    const double rh = a.grid[j] * sqrt(num / den);
+    jn = 0;
+    while (jn < a.n_rho - 1 && rh > a.mid[jn]) ++jn;
+  }
+  if (g == 0 && tid == 0) {
+    if (a.rho_hist) a.rho_hist[nchk] = jn;
+    if (a.prim_res) a.prim_res[nchk] = rp;
+    if (a.dual_res) a.dual_res[nchk] = rd;
+  }
+  out.status = st;
+  out.jn = jn;
+  return out;
+}
+
+template <typename T>
+__device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int k, int st, int j) {
+  if (rs.own) {
+    if (rs.xrow) {
+      static_cast<T*>(a.xs)[rs.R] = rs.sx;
+      static_cast<T*>(a.xo)[rs.R] = rs.sx;
+    } else {
+      const int i = rs.R - a.n;
+      static_cast<T*>(a.zs)[i] = rs.sz;
+      static_cast<T*>(a.ys)[i] = rs.sy;
+      static_cast<T*>(a.zo)[i] = rs.sz;
+      static_cast<T*>(a.yo)[i] = rs.sy;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *a.iterations = k;
+    *a.status = st;
+    *a.rho_index = j;
+    *a.js = j;
+  }
+}
+
+template <typename T, int NC, int NRS>
+__device__ __forceinline__ void load_stationary(const LayerArgs& a, int j, int r0, int nstat, T (&wst)[NRS][NC]) {
+  const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int rr = 0; rr < NRS; ++rr)
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int c = tid + BS * k;
+      wst[rr][k] = (rr < nstat && c < a.L) ? Wj[(long)(r0 + rr) * a.ldw + c] : (T)0;
+    }
+}
+
+template <typename T, int NC, int NRS>
+__global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
+  constexpr int NW = LLWords<T>::kWords;
+  __shared__ T red[NWAVE][kMaxRows];
+
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid % kWave, wave = tid / kWave;
+  const int n = a.n, L = a.L;
+  const int rbase = L / G, rextra = L % G;
+  const int nrows = rbase + (g < rextra ? 1 : 0);
+  const int r0 = g * rbase + (g < rextra ? g : rextra);
+  const int nstat = nrows < NRS ? nrows : NRS;
+  const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
+
+  // row-owner state
+  RowState<T> rs;
+  rs.own = tid < nrows;
+  rs.R = r0 + tid;
+  rs.xrow = rs.R < n;
+  rs.sx = rs.sz = rs.sy = rs.sq = (T)0;
+  T sl = 0, su = 0;
+  bool seq = false;
+  if (rs.own) {
+    if (rs.xrow) {
+      rs.sq = static_cast<const T*>(a.q)[rs.R];
+      if (a.warm) rs.sx = static_cast<const T*>(a.xs)[rs.R];
+    } else {
+      const int i = rs.R - n;
+      sl = static_cast<const T*>(a.l)[i];
+      su = static_cast<const T*>(a.u)[i];
+      seq = a.eq[i] != 0;
+      if (a.warm) rs.sy = static_cast<const T*>(a.ys)[i];
+    }
+  }
+  int j = a.warm ? *a.js : a.j0;
+  T srho = (T)(a.grid[j] * (seq ? a.rho_eq_scale : 1.0));
+
+  T wst[NRS][NC];
+  load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+
+  const uint32_t tag = a.tag;
+  int nchk = 0;
+
+  // warm start: z = A x (Sec. II-B, warm starting)
+  if (a.warm) {
+    if (rs.own) ll_store(a.xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, tag);
+    Cols<T, NC> cv;
+    const bool ok = gather<T, NC>(a.xc, L, tag, cv.v, a.err, tag);
+    if (__syncthreads_or(!ok)) {
+      if (tid == 0) err_raise(a.err, tag);
+      finish<T>(a, rs, 0, ST_INTERNAL, j);
+      return;
+    }
+    double ax, unused;
+    check_rows<T, NC>(a, r0, nrows, cv, ax, unused);
+    if (rs.own && !rs.xrow) rs.sz = (T)ax;
+  }
+
+  // first layer input w_1
+  {
+    const T w1 = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
+    if (rs.own) ll_store(a.xw + ((long)L + rs.R) * NW, w1, tag + 1u);
+  }
+
+  for (int k = 1; k <= a.max_iter; ++k) {
+    // layer matvec: rows of Wc_j times w_k
+    T wv[NC];
+    const bool ok = gather<T, NC>(a.xw + (long)(k & 1) * L * NW, L, tag + (uint32_t)k, wv, a.err, tag);
+    if (__syncthreads_or(!ok)) {
+      if (tid == 0) err_raise(a.err, tag);
+      finish<T>(a, rs, k, ST_INTERNAL, j);
+      return;
+    }
+#pragma unroll
+    for (int rr = 0; rr < NRS; ++rr) {
+      if (rr < nstat) {
+        T acc = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < NC; ++k2) acc += wst[rr][k2] * wv[k2];
+        acc = wave_sum(acc);
+        if (lane == 0) red[wave][rr] = acc;
+      }
+    }
+    if (nrows > NRS) {
+      const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
+      for (int rr = NRS; rr < nrows; rr += RC) {
+        T wr[RC][NC];
+#pragma unroll
+        for (int b = 0; b < RC; ++b)
+#pragma unroll
+          for (int k2 = 0; k2 < NC; ++k2) {
+            const int c = tid + BS * k2;
+            wr[b][k2] = (rr + b < nrows && c < L) ? Wj[(long)(r0 + rr + b) * a.ldw + c] : (T)0;
+          }
+#pragma unroll
+        for (int b = 0; b < RC; ++b) {
+          T acc = 0;
+#pragma unroll
+          for (int k2 = 0; k2 < NC; ++k2) acc += wr[b][k2] * wv[k2];
+          acc = wave_sum(acc);
+          if (lane == 0 && rr + b < nrows) red[wave][rr + b] = acc;
+        }
+      }
+    }
+    __syncthreads();
+
+    // row-local update: relaxation, clamp (eq. clamp), dual update
+    if (rs.own) {
+      T v = 0;
+      for (int w = 0; w < NWAVE; ++w) v += red[w][tid];
+      if (rs.xrow) {
+        rs.sx = alpha * v + oma * rs.sx;
+      } else {
+        const T t = alpha * v + oma * rs.sz + rs.sy / srho;
+        const T zn = box_clamp(t, sl, su);
+        rs.sy = srho * (t - zn);
+        rs.sz = zn;
+      }
+    }
+    __syncthreads();
+
+    if ((k % a.check_interval == 0) || (k == a.max_iter)) {
+      const CheckOut co = run_check<T, NC>(a, rs, r0, nrows, k, nchk, j);
+      ++nchk;
+      if (!co.ok) {
+        if (tid == 0) err_raise(a.err, tag);
+        finish<T>(a, rs, k, ST_INTERNAL, j);
+        return;
+      }
+      if (co.status != ST_RUNNING) {
+        finish<T>(a, rs, k, co.status, j);
+        return;
+      }
+      if (co.jn != j) {
+        j = co.jn;
+        srho = (T)(a.grid[j] * (seq ? a.rho_eq_scale : 1.0));
+        load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+      }
+    }
+
+    // next layer input
+    const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
+    if (rs.own) ll_store(a.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
+  }
+}
+
+template <typename T>
+constexpr int words() {
+  return LLWords<T>::kWords;
+}
+
+template <typename T, int NC>
+const void* pick_kernel() {
+  constexpr int nrs0 = 32 / (NC * words<T>());
+  constexpr int nrs = nrs0 > kMaxRows ? kMaxRows : nrs0;
+  return reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs>);
+}
+
+template <typename T>
+const void* kernel_for(int L) {
+  if (L <= BS) return pick_kernel<T, 1>();
+  if (L <= 2 * BS) return pick_kernel<T, 2>();
+  if (L <= 4 * BS) return pick_kernel<T, 4>();
+  if (L <= 8 * BS) return pick_kernel<T, 8>();
+  return nullptr;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_layer(const LayerArgs& a, int grid, hipStream_t st) {
+  const void* k = kernel_for<T>(a.L);
+  if (!k) return hipErrorInvalidValue;
+  LayerArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BS), args, 0, st);
+}
+
+template <typename T>
+int max_layer_grid(int L) {
+  const void* k = kernel_for<T>(L);
+  if (!k) return 0;
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BS, 0) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+template hipError_t launch_layer<float>(const LayerArgs&, int, hipStream_t);
+template hipError_t launch_layer<double>(const LayerArgs&, int, hipStream_t);
+template int max_layer_grid<float>(int);
+template int max_layer_grid<double>(int);
+
+}  // namespace rqp

@@ -1,0 +1,552 @@
+// Host side of the C ABI declared in include/relu_qp.h: validation, device memory, the offline
+// stage (Algorithm 1, "Offline") and the launch of the online stage.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/relu_qp.h"
+#include "layer_kernel.h"
+#include "setup_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_OR_FAIL(expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(RQP_EHIP, "%s: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+// RAII device buffer used during setup
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 8); }
+  double* d() const { return static_cast<double*>(p); }
+};
+
+}  // namespace
+
+struct relu_qp_handle {
+  int n = 0, m = 0, L = 0, batch = 1;
+  long ldw = 0;
+  relu_qp_settings s{};
+  size_t esize = 8;  // bytes per iterate element
+  std::vector<double> grid, mid;
+  std::vector<unsigned char> eq;
+  int j0 = 0;
+  int grid_wg = 0;   // workgroups of the persistent launch
+  int max_grid = 0;  // largest cooperative grid
+  // device
+  void* W = nullptr;
+  long w_stride = 0;
+  void* C = nullptr;
+  void* q = nullptr;
+  void* l = nullptr;
+  void* u = nullptr;
+  unsigned char* eq_d = nullptr;
+  double* grid_d = nullptr;
+  double* mid_d = nullptr;
+  void* xs = nullptr;
+  void* zs = nullptr;
+  void* ys = nullptr;
+  int* js = nullptr;
+  uint64_t* xw = nullptr;
+  uint64_t* xc = nullptr;
+  uint64_t* xn = nullptr;
+  size_t xw_words = 0, xn_words = 0;
+  unsigned* err = nullptr;
+  int* abort_h = nullptr;  // host-mapped
+  int* abort_d = nullptr;
+  uint32_t tag = 1;
+  bool warm_mode = false, warm_pending = false, have_prev = false;
+  // parametric data (Sec. IV): q = F x0, l = lo - E x0, u = hi - E x0
+  int nx = 0;
+  double* F_d = nullptr;
+  double* E_d = nullptr;
+  double* lo_d = nullptr;
+  double* hi_d = nullptr;
+  double* qlu64 = nullptr;  // staging for update_device / update_x0 (n + 2m doubles)
+};
+
+namespace {
+
+void free_handle(relu_qp_handle* h) {
+  if (!h) return;
+  void* ptrs[] = {h->W, h->C, h->q, h->l, h->u, h->eq_d, h->grid_d, h->mid_d, h->xs, h->zs, h->ys, h->js, h->xw,
+                  h->xc, h->xn, h->err, h->F_d, h->E_d, h->lo_d, h->hi_d, h->qlu64};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (h->abort_h) (void)hipHostFree(h->abort_h);
+  delete h;
+}
+
+int validate_settings(const relu_qp_settings* s) {
+  if (!s) return fail(RQP_EINVAL, "settings is NULL");
+  if (!(s->sigma > 0.0) || !std::isfinite(s->sigma)) return fail(RQP_EINVAL, "sigma must be finite and > 0");
+  if (!(s->alpha > 0.0 && s->alpha < 2.0)) return fail(RQP_EINVAL, "alpha must be in (0, 2)");
+  if (s->n_rho < 1 || s->n_rho > 64) return fail(RQP_EINVAL, "n_rho must be in [1, 64]");
+  if (s->n_rho == 1 && !(s->rho0 > 0.0 && std::isfinite(s->rho0))) return fail(RQP_EINVAL, "rho0 must be > 0");
+  if (s->n_rho > 1 && !(s->rho_min > 0.0 && s->rho_max > s->rho_min && std::isfinite(s->rho_max)))
+    return fail(RQP_EINVAL, "need 0 < rho_min < rho_max");
+  if (s->n_rho > 1 && !(s->rho0 > 0.0)) return fail(RQP_EINVAL, "rho0 must be > 0");
+  if (!(s->rho_eq_scale > 0.0) || !std::isfinite(s->rho_eq_scale)) return fail(RQP_EINVAL, "rho_eq_scale must be > 0");
+  if (!(s->eps_abs >= 0.0) || !(s->eps_rel >= 0.0)) return fail(RQP_EINVAL, "eps_abs and eps_rel must be >= 0");
+  if (s->max_iter < 1 || s->max_iter > (1 << 28)) return fail(RQP_EINVAL, "max_iter must be in [1, 2^28]");
+  if (s->check_interval < 1) return fail(RQP_EINVAL, "check_interval must be >= 1");
+  if (s->precision != RQP_FP64 && s->precision != RQP_FP32) return fail(RQP_EINVAL, "unknown precision");
+  if (s->batch != 1) return fail(RQP_EINVAL, "this build solves batch == 1 per handle");
+  return RQP_OK;
+}
+
+// Penalty grid (Sec. III-C): {rho0}, or n_rho log-spaced values; start at the value nearest
+// rho0 in log distance (ties to the smaller value); geometric midpoints for the rounding rule.
+void make_grid(const relu_qp_settings& s, std::vector<double>& grid, std::vector<double>& mid, int& j0) {
+  grid.clear();
+  mid.clear();
+  if (s.n_rho == 1) {
+    grid.push_back(s.rho0);
+    j0 = 0;
+  } else {
+    const double lo = std::log10(s.rho_min), hi = std::log10(s.rho_max);
+    for (int i = 0; i < s.n_rho; ++i) grid.push_back(std::pow(10.0, lo + i * (hi - lo) / (s.n_rho - 1)));
+    j0 = 0;
+    double best = std::fabs(std::log(grid[0]) - std::log(s.rho0));
+    for (int i = 1; i < s.n_rho; ++i) {
+      const double d = std::fabs(std::log(grid[i]) - std::log(s.rho0));
+      if (d < best) {
+        best = d;
+        j0 = i;
+      }
+    }
+  }
+  for (size_t i = 0; i + 1 < grid.size(); ++i) mid.push_back(std::sqrt(grid[i] * grid[i + 1]));
+  if (mid.empty()) mid.push_back(0.0);
+}
+
+int validate_bounds(int m, const double* l, const double* u) {
+  for (int i = 0; i < m; ++i) {
+    if (std::isnan(l[i]) || std::isnan(u[i])) return fail(RQP_EINVAL, "l[%d] or u[%d] is NaN", i, i);
+    if (l[i] > u[i]) return fail(RQP_EINVAL, "l[%d] > u[%d]", i, i);
+    if (l[i] == INFINITY || u[i] == -INFINITY) return fail(RQP_EINVAL, "row %d has an empty box", i);
+  }
+  return RQP_OK;
+}
+
+template <typename T>
+int upload_vec(void* dst, const double* src, size_t count) {
+  std::vector<T> tmp(count);
+  for (size_t i = 0; i < count; ++i) tmp[i] = (T)src[i];
+  HIP_OR_FAIL(hipMemcpy(dst, tmp.data(), count * sizeof(T), hipMemcpyHostToDevice));
+  return RQP_OK;
+}
+
+int upload(relu_qp_handle* h, void* dst, const double* src, size_t count) {
+  return h->esize == 8 ? upload_vec<double>(dst, src, count) : upload_vec<float>(dst, src, count);
+}
+
+hipError_t cast_dev(relu_qp_handle* h, long count, const double* x, void* y, hipStream_t st) {
+  return h->esize == 8 ? rqp::cast_from_f64<double>(count, x, static_cast<double*>(y), st)
+                       : rqp::cast_from_f64<float>(count, x, static_cast<float*>(y), st);
+}
+
+// Forms the compact layer matrices [D_j, D_j A'; A D_j, A D_j A'] for every grid value and the
+// check matrix [P, A'; A, 0] (Algorithm 1, "compute KKT inverse, W and b for each rho").
+template <typename T>
+int build_weights(relu_qp_handle* h, const double* P, const double* A, hipStream_t st) {
+  const int n = h->n, m = h->m;
+  DevBuf P_d, A_d, Gw, K, DAt, ADAt, work, omega, info;
+  const size_t nn = (size_t)n * n, mn = (size_t)m * n, mm = (size_t)m * m;
+  if (P_d.alloc(nn * 8) || A_d.alloc(mn * 8) || Gw.alloc(nn * 8) || K.alloc(nn * 8) || DAt.alloc(mn * 8) ||
+      ADAt.alloc(mm * 8) || work.alloc((2 * 32 * (size_t)n + 32 * 32) * 8) || omega.alloc((size_t)m * 8) ||
+      info.alloc(sizeof(int)))
+    return fail(RQP_ENOMEM, "setup workspace allocation failed (n=%d, m=%d)", n, m);
+  HIP_OR_FAIL(hipMemcpyAsync(P_d.p, P, nn * 8, hipMemcpyHostToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(A_d.p, A, mn * 8, hipMemcpyHostToDevice, st));
+  std::vector<double> om(m);
+  for (int i = 0; i < m; ++i) om[i] = h->eq[i] ? h->s.rho_eq_scale : 1.0;
+  HIP_OR_FAIL(hipMemcpyAsync(omega.p, om.data(), (size_t)m * 8, hipMemcpyHostToDevice, st));
+  HIP_OR_FAIL(hipMemsetAsync(info.p, 0, sizeof(int), st));
+  // Gw = A' diag(omega) A
+  HIP_OR_FAIL(rqp::gemm_f64(n, n, m, 1.0, A_d.d(), 1, n, omega.d(), A_d.d(), n, 1, 0.0, Gw.d(), n, st));
+  T* W = static_cast<T*>(h->W);
+  for (size_t j = 0; j < h->grid.size(); ++j) {
+    HIP_OR_FAIL(rqp::kkt_form_f64(n, P_d.d(), Gw.d(), h->s.sigma, h->grid[j], K.d(), st));
+    HIP_OR_FAIL(rqp::spd_inverse_f64(n, K.d(), work.d(), static_cast<int*>(info.p), st));
+    // D A'  (n x m) and A D A' (m x m)
+    HIP_OR_FAIL(rqp::gemm_f64(n, m, n, 1.0, K.d(), n, 1, nullptr, A_d.d(), 1, n, 0.0, DAt.d(), m, st));
+    HIP_OR_FAIL(rqp::gemm_f64(m, m, n, 1.0, A_d.d(), n, 1, nullptr, DAt.d(), m, 1, 0.0, ADAt.d(), m, st));
+    HIP_OR_FAIL(rqp::assemble_layer<T>(n, m, K.d(), DAt.d(), ADAt.d(), W + (long)j * h->w_stride, h->ldw, st));
+  }
+  HIP_OR_FAIL(rqp::assemble_check<T>(n, m, P_d.d(), A_d.d(), static_cast<T*>(h->C), h->ldw, st));
+  int hinfo = 0;
+  HIP_OR_FAIL(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OR_FAIL(hipStreamSynchronize(st));
+  if (hinfo) return fail(RQP_ENOTPD, "P + sigma I + A' diag(rho) A is not positive definite");
+  return RQP_OK;
+}
+
+int choose_grid(relu_qp_handle* h) {
+  int cus = 0, dev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev));
+  HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  h->max_grid = h->esize == 8 ? rqp::max_layer_grid<double>(h->L) : rqp::max_layer_grid<float>(h->L);
+  const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
+  if (h->max_grid < need) return fail(RQP_EINVAL, "problem too large for one cooperative launch (L=%d)", h->L);
+  int g = cus < h->L ? cus : h->L;
+  if (g > h->max_grid) g = h->max_grid;
+  if (g < need) g = need;
+  h->grid_wg = g;
+  return RQP_OK;
+}
+
+int alloc_exchange(relu_qp_handle* h) {
+  const size_t words = h->esize == 8 ? 2 : 1;
+  h->xw_words = 2 * (size_t)h->L * words;
+  h->xn_words = 2 * (size_t)(h->max_grid > 0 ? h->max_grid : 1) * 8 * 2;
+  HIP_OR_FAIL(hipMalloc(&h->xw, h->xw_words * 8));
+  HIP_OR_FAIL(hipMalloc(&h->xc, h->xw_words * 8));
+  HIP_OR_FAIL(hipMalloc(&h->xn, h->xn_words * 8));
+  HIP_OR_FAIL(hipMemset(h->xw, 0, h->xw_words * 8));
+  HIP_OR_FAIL(hipMemset(h->xc, 0, h->xw_words * 8));
+  HIP_OR_FAIL(hipMemset(h->xn, 0, h->xn_words * 8));
+  h->tag = 1;
+  return RQP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void relu_qp_default_settings(relu_qp_settings* s) {
+  if (!s) return;
+  s->sigma = 1e-6;
+  s->alpha = 1.6;
+  s->rho0 = 0.1;
+  s->n_rho = 1;
+  s->rho_min = 1e-3;
+  s->rho_max = 1e3;
+  s->rho_eq_scale = 1e3;
+  s->eps_abs = 1e-3;
+  s->eps_rel = 1e-3;
+  s->max_iter = 4000;
+  s->check_interval = 25;
+  s->precision = RQP_FP32;
+  s->batch = 1;
+}
+
+const char* relu_qp_last_error(void) { return g_last_error.c_str(); }
+
+int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const double* q, const double* A,
+                  const double* l, const double* u, const relu_qp_settings* s, void* stream) {
+  if (!hp) return fail(RQP_EINVAL, "handle pointer is NULL");
+  *hp = nullptr;
+  int rc = validate_settings(s);
+  if (rc) return rc;
+  if (n < 1 || m < 1) return fail(RQP_EINVAL, "need n >= 1 and m >= 1 (n=%d, m=%d)", n, m);
+  if (!P || !q || !A || !l || !u) return fail(RQP_EINVAL, "NULL problem array");
+  if ((long)n + m > 8L * rqp::kLayerBlock) return fail(RQP_EINVAL, "n + m = %ld exceeds %d", (long)n + m, 8 * rqp::kLayerBlock);
+  double pmax = 0.0;
+  for (long i = 0; i < (long)n * n; ++i) {
+    if (!std::isfinite(P[i])) return fail(RQP_EINVAL, "P has a non-finite entry");
+    pmax = std::fmax(pmax, std::fabs(P[i]));
+  }
+  for (int i = 0; i < n; ++i)
+    for (int k = i + 1; k < n; ++k)
+      if (std::fabs(P[(long)i * n + k] - P[(long)k * n + i]) > 1e-12 * (pmax > 0 ? pmax : 1.0))
+        return fail(RQP_EINVAL, "P is not symmetric (%d, %d)", i, k);
+  for (long i = 0; i < (long)m * n; ++i)
+    if (!std::isfinite(A[i])) return fail(RQP_EINVAL, "A has a non-finite entry");
+  rc = validate_bounds(m, l, u);
+  if (rc) return rc;
+
+  relu_qp_handle* h = new relu_qp_handle();
+  h->n = n;
+  h->m = m;
+  h->L = n + m;
+  h->s = *s;
+  h->batch = s->batch;
+  h->esize = s->precision == RQP_FP64 ? 8 : 4;
+  h->ldw = (h->L + 3) / 4 * 4;  // 16-byte aligned rows
+  h->w_stride = (long)h->L * h->ldw;
+  make_grid(*s, h->grid, h->mid, h->j0);
+  h->eq.resize(m);
+  for (int i = 0; i < m; ++i) h->eq[i] = (l[i] == u[i]) ? 1 : 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  auto bail = [&](int code) {
+    free_handle(h);
+    return code;
+  };
+  const size_t nr = h->grid.size();
+  if (hipMalloc(&h->W, nr * h->w_stride * h->esize) != hipSuccess ||
+      hipMalloc(&h->C, (size_t)h->w_stride * h->esize) != hipSuccess ||
+      hipMalloc(&h->q, (size_t)n * h->esize) != hipSuccess || hipMalloc(&h->l, (size_t)m * h->esize) != hipSuccess ||
+      hipMalloc(&h->u, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->eq_d, (size_t)m) != hipSuccess ||
+      hipMalloc(&h->grid_d, nr * 8) != hipSuccess || hipMalloc(&h->mid_d, h->mid.size() * 8) != hipSuccess ||
+      hipMalloc(&h->xs, (size_t)n * h->esize) != hipSuccess || hipMalloc(&h->zs, (size_t)m * h->esize) != hipSuccess ||
+      hipMalloc(&h->ys, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->js, sizeof(int)) != hipSuccess ||
+      hipMalloc(&h->err, sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&h->qlu64, ((size_t)n + 2 * m) * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(RQP_ENOMEM, "device allocation failed (n=%d, m=%d, %zu penalties)", n, m, nr));
+  }
+  if (hipHostMalloc(&h->abort_h, sizeof(int), hipHostMallocMapped) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(RQP_ENOMEM, "pinned allocation failed"));
+  }
+  *h->abort_h = 0;
+  if (hipHostGetDevicePointer((void**)&h->abort_d, h->abort_h, 0) != hipSuccess)
+    return bail(fail(RQP_EHIP, "hipHostGetDevicePointer failed"));
+
+  if ((rc = upload(h, h->q, q, n)) || (rc = upload(h, h->l, l, m)) || (rc = upload(h, h->u, u, m))) return bail(rc);
+  if (hipMemcpy(h->eq_d, h->eq.data(), m, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->grid_d, h->grid.data(), nr * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->mid_d, h->mid.data(), h->mid.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->xs, 0, (size_t)n * h->esize) != hipSuccess || hipMemset(h->zs, 0, (size_t)m * h->esize) != hipSuccess ||
+      hipMemset(h->ys, 0, (size_t)m * h->esize) != hipSuccess || hipMemset(h->js, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(h->err, 0, sizeof(unsigned)) != hipSuccess)
+    return bail(fail(RQP_EHIP, "initial copies failed"));
+
+  rc = h->esize == 8 ? build_weights<double>(h, P, A, st) : build_weights<float>(h, P, A, st);
+  if (rc) return bail(rc);
+  if ((rc = choose_grid(h)) || (rc = alloc_exchange(h))) return bail(rc);
+  *hp = h;
+  return RQP_OK;
+}
+
+int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const double* u) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  std::vector<double> lv, uv;
+  if (l || u) {
+    lv.resize(h->m);
+    uv.resize(h->m);
+    std::vector<double> tmp(h->m);
+    const size_t es = h->esize;
+    // unchanged side comes from the device copy
+    for (int side = 0; side < 2; ++side) {
+      const double* src = side == 0 ? l : u;
+      std::vector<double>& dst = side == 0 ? lv : uv;
+      if (src) {
+        std::memcpy(dst.data(), src, h->m * 8);
+      } else {
+        void* dev = side == 0 ? h->l : h->u;
+        if (es == 8) {
+          HIP_OR_FAIL(hipMemcpy(dst.data(), dev, h->m * 8, hipMemcpyDeviceToHost));
+        } else {
+          std::vector<float> f(h->m);
+          HIP_OR_FAIL(hipMemcpy(f.data(), dev, h->m * 4, hipMemcpyDeviceToHost));
+          for (int i = 0; i < h->m; ++i) dst[i] = f[i];
+        }
+      }
+    }
+    int rc = validate_bounds(h->m, lv.data(), uv.data());
+    if (rc) return rc;
+    for (int i = 0; i < h->m; ++i)
+      if ((lv[i] == uv[i]) != (h->eq[i] != 0))
+        return fail(RQP_EINVAL, "update changes the equality-row pattern at row %d", i);
+  }
+  int rc;
+  // a non-finite q is accepted: the solve reports RQP_NONFINITE
+  if (q && (rc = upload(h, h->q, q, h->n))) return rc;
+  if (l && (rc = upload(h, h->l, lv.data(), h->m))) return rc;
+  if (u && (rc = upload(h, h->u, uv.data(), h->m))) return rc;
+  return RQP_OK;
+}
+
+int relu_qp_update_device(relu_qp_handle* h, const double* q, const double* l, const double* u, void* stream) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (q) HIP_OR_FAIL(cast_dev(h, h->n, q, h->q, st));
+  if (l) HIP_OR_FAIL(cast_dev(h, h->m, l, h->l, st));
+  if (u) HIP_OR_FAIL(cast_dev(h, h->m, u, h->u, st));
+  return RQP_OK;
+}
+
+int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const double* E, const double* lo,
+                           const double* hi) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (nx < 1 || !F || !E || !lo || !hi) return fail(RQP_EINVAL, "bad parametric data");
+  int rc = validate_bounds(h->m, lo, hi);
+  if (rc) return rc;
+  for (int i = 0; i < h->m; ++i)
+    if ((lo[i] == hi[i]) != (h->eq[i] != 0)) return fail(RQP_EINVAL, "equality pattern of lo/hi differs at %d", i);
+  for (void** p : {(void**)&h->F_d, (void**)&h->E_d, (void**)&h->lo_d, (void**)&h->hi_d})
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  h->nx = nx;
+  HIP_OR_FAIL(hipMalloc(&h->F_d, (size_t)h->n * nx * 8));
+  HIP_OR_FAIL(hipMalloc(&h->E_d, (size_t)h->m * nx * 8));
+  HIP_OR_FAIL(hipMalloc(&h->lo_d, (size_t)h->m * 8));
+  HIP_OR_FAIL(hipMalloc(&h->hi_d, (size_t)h->m * 8));
+  HIP_OR_FAIL(hipMemcpy(h->F_d, F, (size_t)h->n * nx * 8, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(hipMemcpy(h->E_d, E, (size_t)h->m * nx * 8, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(hipMemcpy(h->lo_d, lo, (size_t)h->m * 8, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(hipMemcpy(h->hi_d, hi, (size_t)h->m * 8, hipMemcpyHostToDevice));
+  return RQP_OK;
+}
+
+int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
+  if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* qd = h->qlu64;
+  double* ld = qd + h->n;
+  double* ud = ld + h->m;
+  HIP_OR_FAIL(rqp::mpc_vectors_f64(h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0, qd, ld, ud, st));
+  HIP_OR_FAIL(cast_dev(h, h->n, qd, h->q, st));
+  HIP_OR_FAIL(cast_dev(h, h->m, ld, h->l, st));
+  HIP_OR_FAIL(cast_dev(h, h->m, ud, h->u, st));
+  return RQP_OK;
+}
+
+int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int rho_index) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!x || !y) return fail(RQP_EINVAL, "x or y is NULL");
+  if (rho_index < 0 || rho_index >= (int)h->grid.size()) return fail(RQP_EINVAL, "rho_index out of range");
+  int rc;
+  if ((rc = upload(h, h->xs, x, h->n)) || (rc = upload(h, h->ys, y, h->m))) return rc;
+  HIP_OR_FAIL(hipMemcpy(h->js, &rho_index, sizeof(int), hipMemcpyHostToDevice));
+  h->warm_pending = true;
+  return RQP_OK;
+}
+
+int relu_qp_set_warm(relu_qp_handle* h, int enabled) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  h->warm_mode = enabled != 0;
+  return RQP_OK;
+}
+
+int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
+    return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t span = (uint32_t)h->s.max_iter + 2u;
+  if ((uint64_t)h->tag + span >= 0xffffffffull) {
+    // restart the tag sequence: clear every exchange word so no stale tag can match
+    HIP_OR_FAIL(hipMemsetAsync(h->xw, 0, h->xw_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xc, 0, h->xw_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xn, 0, h->xn_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->err, 0, sizeof(unsigned), st));
+    h->tag = 1;
+  }
+  __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
+  rqp::LayerArgs a{};
+  a.n = h->n;
+  a.m = h->m;
+  a.L = h->L;
+  a.ldw = h->ldw;
+  a.W = h->W;
+  a.w_stride = h->w_stride;
+  a.C = h->C;
+  a.q = h->q;
+  a.l = h->l;
+  a.u = h->u;
+  a.eq = h->eq_d;
+  a.grid = h->grid_d;
+  a.mid = h->mid_d;
+  a.n_rho = (int)h->grid.size();
+  a.sigma = h->s.sigma;
+  a.alpha = h->s.alpha;
+  a.eps_abs = h->s.eps_abs;
+  a.eps_rel = h->s.eps_rel;
+  a.rho_eq_scale = h->s.rho_eq_scale;
+  a.max_iter = h->s.max_iter;
+  a.check_interval = h->s.check_interval;
+  a.terminate = !(h->s.eps_abs == 0.0 && h->s.eps_rel == 0.0);
+  a.warm = (h->warm_pending || (h->warm_mode && h->have_prev)) ? 1 : 0;
+  a.j0 = h->j0;
+  a.xs = h->xs;
+  a.zs = h->zs;
+  a.ys = h->ys;
+  a.js = h->js;
+  a.xo = out->x;
+  a.zo = out->z;
+  a.yo = out->y;
+  a.iterations = out->iterations;
+  a.status = out->status;
+  a.rho_index = out->rho_index;
+  a.rho_hist = out->rho_hist;
+  a.prim_res = out->prim_res;
+  a.dual_res = out->dual_res;
+  a.xw = h->xw;
+  a.xc = h->xc;
+  a.xn = h->xn;
+  a.tag = h->tag;
+  a.abort_flag = h->abort_d;
+  a.err = h->err;
+  hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->grid_wg, st) : rqp::launch_layer<float>(a, h->grid_wg, st);
+  if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
+  h->tag += span;
+  h->warm_pending = false;
+  h->have_prev = true;
+  return RQP_OK;
+}
+
+int relu_qp_abort(relu_qp_handle* h) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  __atomic_store_n(h->abort_h, 1, __ATOMIC_SEQ_CST);
+  return RQP_OK;
+}
+
+int relu_qp_max_checks(const relu_qp_handle* h) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  return h->s.max_iter / h->s.check_interval + (h->s.max_iter % h->s.check_interval ? 1 : 0);
+}
+
+int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid, int* n_rho) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (n_rho) *n_rho = (int)h->grid.size();
+  if (grid) std::memcpy(grid, h->grid.data(), h->grid.size() * 8);
+  return RQP_OK;
+}
+
+int relu_qp_set_launch(relu_qp_handle* h, int grid) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (grid == 0) return choose_grid(h);
+  const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
+  if (grid < need || grid > h->max_grid || grid > h->L)
+    return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, h->max_grid < h->L ? h->max_grid : h->L);
+  h->grid_wg = grid;
+  return RQP_OK;
+}
+
+int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (grid) *grid = h->grid_wg;
+  if (block) *block = rqp::kLayerBlock;
+  return RQP_OK;
+}
+
+int relu_qp_cleanup(relu_qp_handle* h) {
+  if (!h) return RQP_OK;
+  (void)hipDeviceSynchronize();
+  free_handle(h);
+  return RQP_OK;
+}
+
+}  // extern "C"

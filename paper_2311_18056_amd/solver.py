@@ -1,0 +1,176 @@
+"""Python face of the C ABI: a QP handle whose results live in torch device tensors.
+
+Every step of the solve runs in the HIP library; this module only marshals arguments. torch
+provides the device memory of the result buffers and the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int, c_void_p
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import RQP_FP32, RQP_FP64, Result, Settings, check, lib
+
+STATUS_NAMES = {0: "running", 1: "solved", 2: "max_iter", 3: "nonfinite", 4: "aborted", 5: "internal"}
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _stream_handle(stream) -> c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def default_settings(**overrides) -> Settings:
+    s = Settings()
+    lib().relu_qp_default_settings(byref(s))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": RQP_FP64, "fp32": RQP_FP32}[v]
+        if not hasattr(s, k):
+            raise AttributeError(k)
+        setattr(s, k, v)
+    return s
+
+
+class Solver:
+    """One QP family (fixed P and A) with its device-resident layer weights.
+
+    Parameters follow ``relu_qp_settings``; ``precision`` is "fp64" or "fp32".
+    """
+
+    def __init__(self, P, q, A, l, u, *, device="cuda:0", stream=None, **settings):
+        L = lib()
+        P = _f64(P)
+        n = P.shape[0]
+        A = _f64(A)
+        m = A.shape[0]
+        q, l, u = _f64(q, (n,)), _f64(l, (m,)), _f64(u, (m,))
+        if P.shape != (n, n) or A.shape != (m, n):
+            raise ValueError("P must be n x n and A m x n")
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.settings = default_settings(**settings)
+        self.n, self.m = n, m
+        self.fp64 = self.settings.precision == RQP_FP64
+        self.dtype = torch.float64 if self.fp64 else torch.float32
+        self._h = c_void_p()
+        check(L.relu_qp_setup(byref(self._h), n, m, _ptr(P), _ptr(q), _ptr(A), _ptr(l), _ptr(u),
+                              byref(self.settings), _stream_handle(stream)))
+        self.max_checks = check(L.relu_qp_max_checks(self._h))
+        dev = self.device
+        self.x = torch.zeros(n, dtype=self.dtype, device=dev)
+        self.y = torch.zeros(m, dtype=self.dtype, device=dev)
+        self.z = torch.zeros(m, dtype=self.dtype, device=dev)
+        self.iterations = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.rho_index = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.rho_hist = torch.full((self.max_checks,), -1, dtype=torch.int32, device=dev)
+        self.prim_res = torch.zeros(self.max_checks, dtype=torch.float64, device=dev)
+        self.dual_res = torch.zeros(self.max_checks, dtype=torch.float64, device=dev)
+        self._res = Result(
+            self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(), self.iterations.data_ptr(),
+            self.status.data_ptr(), self.rho_index.data_ptr(), self.rho_hist.data_ptr(),
+            self.prim_res.data_ptr(), self.dual_res.data_ptr(),
+        )
+
+    # ------------------------------------------------------------------ online stage
+    def update(self, q=None, l=None, u=None):
+        n, m = self.n, self.m
+        args = [None if v is None else _f64(v, s) for v, s in ((q, (n,)), (l, (m,)), (u, (m,)))]
+        self._keep = args
+        check(lib().relu_qp_update(self._h, *[None if a is None else _ptr(a) for a in args]))
+
+    def update_device(self, q=None, l=None, u=None, stream=None):
+        ptrs = []
+        for v in (q, l, u):
+            if v is None:
+                ptrs.append(None)
+            else:
+                if v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous():
+                    raise ValueError("device updates take contiguous float64 cuda tensors")
+                ptrs.append(c_void_p(v.data_ptr()))
+        check(lib().relu_qp_update_device(self._h, *ptrs, _stream_handle(stream)))
+
+    def set_parametric(self, F, E, lo, hi):
+        F = _f64(F)
+        nx = F.shape[1]
+        E, lo, hi = _f64(E, (self.m, nx)), _f64(lo, (self.m,)), _f64(hi, (self.m,))
+        check(lib().relu_qp_set_parametric(self._h, nx, _ptr(F), _ptr(E), _ptr(lo), _ptr(hi)))
+        self.nx = nx
+
+    def update_x0_device(self, x0: torch.Tensor, stream=None):
+        if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
+            raise ValueError("x0 must be a contiguous float64 cuda tensor")
+        check(lib().relu_qp_update_x0_device(self._h, c_void_p(x0.data_ptr()), _stream_handle(stream)))
+
+    def warm_start(self, x, y, rho_index: int):
+        x, y = _f64(x, (self.n,)), _f64(y, (self.m,))
+        check(lib().relu_qp_warm_start(self._h, _ptr(x), _ptr(y), int(rho_index)))
+
+    def set_warm(self, enabled: bool):
+        check(lib().relu_qp_set_warm(self._h, 1 if enabled else 0))
+
+    def solve(self, stream=None):
+        """Launch the whole online loop (asynchronous on the stream)."""
+        check(lib().relu_qp_solve(self._h, _stream_handle(stream), byref(self._res)))
+
+    def abort(self):
+        check(lib().relu_qp_abort(self._h))
+
+    def set_launch(self, grid: int):
+        check(lib().relu_qp_set_launch(self._h, int(grid)))
+
+    def launch(self):
+        g, b = c_int(), c_int()
+        check(lib().relu_qp_get_launch(self._h, byref(g), byref(b)))
+        return g.value, b.value
+
+    def rho_grid(self):
+        k = c_int()
+        check(lib().relu_qp_get_rho_grid(self._h, None, byref(k)))
+        g = np.zeros(k.value)
+        check(lib().relu_qp_get_rho_grid(self._h, _ptr(g), byref(k)))
+        return g
+
+    def result(self) -> dict:
+        """Synchronise and copy the last solve's outputs to the host."""
+        torch.cuda.synchronize(self.device)
+        it = int(self.iterations.item())
+        nck = min(self.max_checks, -(-it // self.settings.check_interval)) if it > 0 else 0
+        return dict(
+            x=self.x.double().cpu().numpy(),
+            y=self.y.double().cpu().numpy(),
+            z=self.z.double().cpu().numpy(),
+            iterations=it,
+            status=int(self.status.item()),
+            rho_index=int(self.rho_index.item()),
+            rho_hist=self.rho_hist[:nck].cpu().numpy().tolist(),
+            prim_res=self.prim_res[:nck].cpu().numpy(),
+            dual_res=self.dual_res[:nck].cpu().numpy(),
+        )
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().relu_qp_cleanup(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

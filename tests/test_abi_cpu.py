@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every declared symbol,
+and the header and the binding agree on the settings defaults."""
+
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "relu_qp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(relu_qp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_list_the_same_symbols():
+    from paper_2311_18056_amd._lib import EXPORTS
+
+    assert sorted(EXPORTS) == _declared_functions()
+
+
+def test_library_exports_every_symbol():
+    import paper_2311_18056_amd as rq
+
+    lib = rq.lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_default_settings():
+    import paper_2311_18056_amd as rq
+
+    s = rq.default_settings()
+    assert (s.sigma, s.alpha, s.rho0, s.n_rho) == (1e-6, 1.6, 0.1, 1)
+    assert (s.rho_min, s.rho_max, s.rho_eq_scale) == (1e-3, 1e3, 1e3)
+    assert (s.eps_abs, s.eps_rel, s.max_iter, s.check_interval) == (1e-3, 1e-3, 4000, 25)
+    assert s.batch == 1
+    with pytest.raises(AttributeError):
+        rq.default_settings(no_such_field=1)
+
+
+def test_null_handle_is_rejected_without_a_gpu():
+    import ctypes
+
+    import paper_2311_18056_amd as rq
+
+    lib = rq.lib()
+    assert lib.relu_qp_cleanup(None) == 0
+    assert lib.relu_qp_abort(None) == rq._lib.RQP_ESTATE
+    assert b"NULL handle" in lib.relu_qp_last_error()
+    assert lib.relu_qp_solve(None, None, None) == rq._lib.RQP_ESTATE
+    s = rq.default_settings(alpha=2.5)
+    h = ctypes.c_void_p()
+    z = (ctypes.c_double * 4)()
+    rc = lib.relu_qp_setup(ctypes.byref(h), 2, 2, z, z, z, z, z, ctypes.byref(s), None)
+    assert rc == rq._lib.RQP_EINVAL and h.value is None
+    assert b"alpha" in lib.relu_qp_last_error()

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same inputs.
+
+Tolerances (per vector v in x, z, y): ||v_gpu - v_oracle||_inf <= tol * max(||v_oracle||_inf, 1),
+tol = 1e-9 for FP64 and 1e-4 for FP32, over fixed iteration counts, with the penalty schedule
+the GPU chose replayed in the oracle.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import admm
+from oracle.mpc_update import qp_vectors
+from workloads import make_config, random_qp, x0_batch
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2311_18056_amd as rq
+
+    rq.lib()
+    return rq
+
+
+@pytest.fixture(scope="module")
+def c0():
+    prob = make_config("c0")
+    x0 = x0_batch(prob.nx, 4, 1000)
+    return prob, x0
+
+
+def _oracle_settings(**kw):
+    s = admm.Settings()
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _close(a, b, tol, what=""):
+    err = np.max(np.abs(a - b)) if a.size else 0.0
+    scale = max(np.max(np.abs(b)) if b.size else 0.0, 1.0)
+    assert err <= tol * scale, f"{what}: |diff|={err:.3e} > {tol:.1e} * {scale:.3e}"
+
+
+def _compare(res, ref, tol):
+    _close(res["x"], ref.x, tol, "x")
+    _close(res["z"], ref.z, tol, "z")
+    _close(res["y"], ref.y, tol, "y")
+
+
+def _fixed_run(rq, P, q, A, l, u, prec, iters, grid=None, **kw):
+    s = dict(eps_abs=0.0, eps_rel=0.0, max_iter=iters, precision=prec, **kw)
+    sol = rq.Solver(P, q, A, l, u, **s)
+    if grid is not None:
+        sol.set_launch(grid)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    return res
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("iters", [1, 2, 3, 24, 25, 26, 57, 200])
+def test_c0_fixed_rho_per_iterate(rq, c0, prec, iters):
+    prob, x0 = c0
+    q, l, u = prob.instance(5.0 * x0[0])  # scaled so that limits bind
+    res = _fixed_run(rq, prob.P, q, prob.A, l, u, prec, iters)
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=iters))
+    assert res["status"] == rq.RQP_MAX_ITER and res["iterations"] == iters
+    _compare(res, ref, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c0_adaptive_rho_replayed(rq, c0, prec):
+    prob, x0 = c0
+    q, l, u = prob.instance(5.0 * x0[1])
+    res = _fixed_run(rq, prob.P, q, prob.A, l, u, prec, 300, n_rho=8)
+    assert len(res["rho_hist"]) == 12
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=300, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    assert res["rho_index"] == ref.rho_index
+    _compare(res, ref, TOL[prec])
+    if prec == "fp64":
+        # the FP64 path takes the oracle's own decisions
+        own = oracle.solve(prob.P, q, prob.A, l, u,
+                           _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=300, n_rho=8))
+        assert own.rho_hist == res["rho_hist"]
+        np.testing.assert_allclose(res["prim_res"], own.prim_res, rtol=1e-7, atol=1e-12)
+        np.testing.assert_allclose(res["dual_res"], own.dual_res, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid", [1, 3, 7, 64])
+def test_launch_shapes_and_streamed_rows(rq, prec, grid):
+    """Same result for any number of workgroups; few workgroups put many rows (register and
+    streamed) on each, so every path of the row loop runs."""
+    P, q, A, l, u = random_qp(120, 20, 40, seed=11)  # L = 180 rows, equality rows included
+    res = _fixed_run(rq, P, q, A, l, u, prec, 60, grid=grid, n_rho=8)
+    ref = oracle.solve(P, q, A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=60, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    _compare(res, ref, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c0_solves_to_tolerance(rq, c0, prec):
+    prob, x0 = c0
+    for i in range(3):
+        q, l, u = prob.instance(5.0 * x0[i])
+        sol = rq.Solver(prob.P, q, prob.A, l, u, precision=prec, n_rho=8)
+        sol.solve()
+        res = sol.result()
+        sol.close()
+        assert res["status"] == rq.RQP_SOLVED
+        assert res["iterations"] % 25 == 0
+        nm = admm.residual_norms(prob.P, q, prob.A, res["x"], res["z"], res["y"])
+        slack = 1.01 if prec == "fp64" else 1.5
+        assert nm["r_p"] <= slack * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
+        assert nm["r_d"] <= slack * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+        xs = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=1e-10, eps_rel=1e-10, n_rho=8,
+                                                                    max_iter=40000)).x
+        err = np.max(np.abs(res["x"] - xs)) / max(np.max(np.abs(xs)), 1.0)
+        assert err < 5e-2, f"solution error {err:.2e}"
+
+
+def test_c1_full_size_fp32_replayed(rq):
+    """Config 1 shape (n = m = 1600, 8 penalties) in the launch configuration the benchmark
+    times, 150 fixed iterations with the GPU's schedule replayed."""
+    prob = make_config("c1")
+    x0 = x0_batch(prob.nx, 1, 1001, scale=20.0)[0]
+    q, l, u = prob.instance(x0)
+    res = _fixed_run(rq, prob.P, q, prob.A, l, u, "fp32", 150, n_rho=8)
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=150, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    _compare(res, ref, TOL["fp32"])
+
+
+def test_c1_solution_quality_fp32(rq):
+    prob = make_config("c1")
+    x0 = x0_batch(prob.nx, 1, 1002, scale=20.0)[0]
+    q, l, u = prob.instance(x0)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp32", n_rho=8)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    assert res["status"] == rq.RQP_SOLVED
+    nm = admm.residual_norms(prob.P, q, prob.A, res["x"], res["z"], res["y"])
+    assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
+    assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+
+
+def test_nonfinite_status(rq, c0):
+    prob, x0 = c0
+    q, l, u = prob.instance(x0[0])
+    q = q.copy()
+    q[3] = np.nan
+    for prec in ("fp64", "fp32"):
+        sol = rq.Solver(prob.P, q, prob.A, l, u, precision=prec)
+        sol.solve()
+        res = sol.result()
+        sol.close()
+        assert res["status"] == rq.RQP_NONFINITE and res["iterations"] == 25
+
+
+def test_warm_start_and_update(rq, c0):
+    prob, x0 = c0
+    q, l, u = prob.instance(5.0 * x0[2])
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp64", n_rho=8)
+    sol.solve()
+    r1 = sol.result()
+    assert r1["status"] == rq.RQP_SOLVED
+    # warm start from the solution: converged at the first check (Sec. II-B warm starting)
+    sol.warm_start(r1["x"], r1["y"], r1["rho_index"])
+    sol.solve()
+    r2 = sol.result()
+    assert r2["status"] == rq.RQP_SOLVED and r2["iterations"] == 25
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(n_rho=8), warm=(r1["x"], r1["y"], r1["rho_index"]))
+    assert ref.iterations == 25
+    _compare(r2, ref, 1e-9)
+    # new data through the host update, cold start again
+    q2, l2, u2 = prob.instance(5.0 * x0[3])
+    sol.update(q2, l2, u2)
+    sol.solve()
+    r3 = sol.result()
+    ref3 = oracle.solve(prob.P, q2, prob.A, l2, u2, _oracle_settings(n_rho=8))
+    assert r3["iterations"] == ref3.iterations and r3["rho_hist"] == ref3.rho_hist
+    _compare(r3, ref3, 1e-9)
+    sol.close()
+
+
+def test_parametric_update_matches_oracle(rq, c0):
+    import torch
+
+    prob, x0s = c0
+    q, l, u = prob.instance(x0s[0])
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp64", eps_abs=0.0, eps_rel=0.0, max_iter=40)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    x0 = 5.0 * x0s[1]
+    sol.update_x0_device(torch.tensor(x0, dtype=torch.float64, device="cuda"))
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    q2, l2, u2 = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, x0)
+    ref = oracle.solve(prob.P, q2, prob.A, l2, u2, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=40))
+    _compare(res, ref, 1e-9)
+
+
+def test_setup_errors(rq):
+    P, q, A, l, u = random_qp(10, 2, 3, seed=0)
+    with pytest.raises(rq.ReluQPError) as e:
+        rq.Solver(-P, q, A, l, u, precision="fp64")
+    assert "RQP_ENOTPD" in str(e.value)
+    with pytest.raises(rq.ReluQPError) as e:
+        rq.Solver(P, q, A, u + 1.0, u, precision="fp64")
+    assert "RQP_EINVAL" in str(e.value)
+    Pa = P.copy()
+    Pa[0, 1] += 1.0
+    with pytest.raises(rq.ReluQPError):
+        rq.Solver(Pa, q, A, l, u)
+
+
+def test_abort(rq):
+    import time
+
+    P, q, A, l, u = random_qp(200, 10, 50, seed=5)
+    sol = rq.Solver(P, q, A, l, u, precision="fp32", eps_abs=0.0, eps_rel=0.0, max_iter=2_000_000)
+    sol.solve()
+    time.sleep(0.05)
+    sol.abort()
+    res = sol.result()
+    sol.close()
+    assert res["status"] == rq.RQP_ABORTED
+    assert 0 < res["iterations"] < 2_000_000 and res["iterations"] % 25 == 0
