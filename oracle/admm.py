@@ -279,7 +279,8 @@ def _validate(P, q, A, l, u, s):
         raise ValueError("bad settings")
 
 
-def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=None, record=False) -> Result:
+def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=None, record=False,
+          cache: dict | None = None) -> Result:
     """ReLU-QP solve (Algorithm 1, online part), in FP64.
 
     ``warm``: None for a cold start (x = z = y = 0), or (x, y, rho_index): the previous primal,
@@ -287,6 +288,8 @@ def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=
     ``rho_replay``: optional list of grid indices; at check number c the solver takes
     rho_replay[c] instead of evaluating the penalty rule (used to replay another solver's
     schedule).
+    ``cache``: optional dict that keeps the factorisations of the offline stage between calls
+    on the same P, A, settings and equality pattern (Algorithm 1 computes them once).
     """
     P = np.asarray(P, np.float64)
     q = np.asarray(q, np.float64)
@@ -308,11 +311,13 @@ def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=
         j = int(warm[2])
         z = A @ x
 
-    cache = {}
+    if cache is None:
+        cache = {}
 
     def op(jj):
+        jj = (form, jj)
         if jj not in cache:
-            rv = rho_vector(grid[jj], eq, s)
+            rv = rho_vector(grid[jj[1]], eq, s)
             if form == "R":
                 cache[jj] = (kkt_inverse(P, A, s.sigma, rv), rv)
             elif form == "T":

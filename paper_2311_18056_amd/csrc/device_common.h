@@ -59,6 +59,34 @@ __device__ __forceinline__ uint64_t abs_bits(double v) {
 __device__ __forceinline__ double bits_to_double(uint64_t b) { return __longlong_as_double((long long)b); }
 constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
 
+// Wave-wide sum with DPP lane permutations (VALU, no LDS round trip): quad swaps, half-row
+// and row mirrors give 16-lane sums in every lane, then the two row broadcasts fold the four
+// rows so that lane 63 holds the total. Only lane 63's result is meaningful.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int t = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(float, t);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  const uint64_t r = (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+  return v + __builtin_bit_cast(double, r);
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_to_last(T v) {
+  v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+constexpr int kLastLane = kWave - 1;
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

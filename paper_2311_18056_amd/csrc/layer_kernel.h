@@ -39,20 +39,28 @@ struct LayerArgs {
   uint64_t* xn;         // exchange words: norm partials, 2 x G x 8 x 2
   uint32_t tag;         // first tag of this solve (tags tag .. tag + max_iter + 1 are used)
   const int* abort_flag;  // host-mapped int, polled at checks
-  unsigned* err;        // device word: set when an exchange times out
+  unsigned* err;        // device word: holds the tag of a solve whose exchange timed out
+  int lds_rows;         // rows per block kept in LDS (set by launch_layer from the plan)
 };
 
 // Rows per workgroup are at most kMaxRows; the host picks the grid accordingly.
 constexpr int kLayerBlock = 1024;
 constexpr int kMaxRows = 64;
 
-// Launch the persistent solve as a cooperative grid of `grid` workgroups of kLayerBlock threads.
-// T = float or double. Returns the HIP error of the launch.
+// Kernel choice and resources for a problem with L = n + m rows on `grid` workgroups: the
+// first reg_rows rows of each block stay in registers and the next lds_rows in LDS for the
+// whole solve; further rows stream from memory every iteration.
+struct LaunchPlan {
+  const void* fn;
+  int reg_rows, lds_rows;
+  size_t dyn_bytes;
+  int max_grid;  // largest cooperative grid with these resources
+};
 template <typename T>
-hipError_t launch_layer(const LayerArgs& a, int grid, hipStream_t st);
+LaunchPlan plan_layer(int L, int grid);
 
-// Largest grid the cooperative launch accepts for this precision and problem size.
+// Launch the persistent solve as a cooperative grid of `grid` workgroups of kLayerBlock threads.
 template <typename T>
-int max_layer_grid(int L);
+hipError_t launch_layer(const LayerArgs& a, const LaunchPlan& p, int grid, hipStream_t st);
 
 }  // namespace rqp

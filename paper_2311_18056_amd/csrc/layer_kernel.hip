@@ -166,9 +166,9 @@ __device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows
         else
           q2 += v;
       }
-      p = wave_sum(p);
-      q2 = wave_sum(q2);
-      if (lane == 0 && rr + b < nrows) {
+      p = wave_sum_to_last(p);
+      q2 = wave_sum_to_last(q2);
+      if (lane == kLastLane && rr + b < nrows) {
         redd[wave][2 * (rr + b)] = p;
         redd[wave][2 * (rr + b) + 1] = q2;
       }
@@ -341,10 +341,27 @@ __device__ __forceinline__ void load_stationary(const LayerArgs& a, int j, int r
     }
 }
 
+// Rows NRS .. NRS + nlds - 1 of the block live in LDS for the whole solve, laid out
+// [row][k][lane] so that every lane reads and writes only its own words (no barrier needed,
+// no bank conflicts).
+template <typename T, int NC>
+__device__ __forceinline__ void load_lds_rows(const LayerArgs& a, int j, int r0, int first, int nlds, T* wl) {
+  const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
+  const int tid = threadIdx.x;
+  for (int rr = 0; rr < nlds; ++rr)
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int c = tid + BS * k;
+      wl[(rr * NC + k) * BS + tid] = (c < a.L) ? Wj[(long)(r0 + first + rr) * a.ldw + c] : (T)0;
+    }
+}
+
 template <typename T, int NC, int NRS>
 __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   constexpr int NW = LLWords<T>::kWords;
   __shared__ T red[NWAVE][kMaxRows];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* wl = reinterpret_cast<T*>(dyn_lds);
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -353,6 +370,8 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   const int nrows = rbase + (g < rextra ? 1 : 0);
   const int r0 = g * rbase + (g < rextra ? g : rextra);
   const int nstat = nrows < NRS ? nrows : NRS;
+  const int nlds = nrows - nstat < a.lds_rows ? nrows - nstat : a.lds_rows;
+  const int nres = nstat + nlds;  // rows held on chip; rows nres..nrows-1 stream from memory
   const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
 
   // row-owner state
@@ -380,6 +399,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
 
   T wst[NRS][NC];
   load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+  load_lds_rows<T, NC>(a, j, r0, NRS, nlds, wl);
 
   const uint32_t tag = a.tag;
   int nchk = 0;
@@ -419,14 +439,22 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       if (rr < nstat) {
         T acc = 0;
 #pragma unroll
-        for (int k2 = 0; k2 < NC; ++k2) acc += wst[rr][k2] * wv[k2];
-        acc = wave_sum(acc);
-        if (lane == 0) red[wave][rr] = acc;
+        for (int k2 = 0; k2 < NC; ++k2) acc = fma(wst[rr][k2], wv[k2], acc);
+        acc = wave_sum_to_last(acc);
+        if (lane == kLastLane) red[wave][rr] = acc;
       }
     }
-    if (nrows > NRS) {
+
+    for (int rr = 0; rr < nlds; ++rr) {
+      T acc = 0;
+#pragma unroll
+      for (int k2 = 0; k2 < NC; ++k2) acc = fma(wl[(rr * NC + k2) * BS + tid], wv[k2], acc);
+      acc = wave_sum_to_last(acc);
+      if (lane == kLastLane) red[wave][NRS + rr] = acc;
+    }
+    if (nrows > nres) {
       const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
-      for (int rr = NRS; rr < nrows; rr += RC) {
+      for (int rr = nres; rr < nrows; rr += RC) {
         T wr[RC][NC];
 #pragma unroll
         for (int b = 0; b < RC; ++b)
@@ -439,9 +467,9 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         for (int b = 0; b < RC; ++b) {
           T acc = 0;
 #pragma unroll
-          for (int k2 = 0; k2 < NC; ++k2) acc += wr[b][k2] * wv[k2];
-          acc = wave_sum(acc);
-          if (lane == 0 && rr + b < nrows) red[wave][rr + b] = acc;
+          for (int k2 = 0; k2 < NC; ++k2) acc = fma(wr[b][k2], wv[k2], acc);
+          acc = wave_sum_to_last(acc);
+          if (lane == kLastLane && rr + b < nrows) red[wave][rr + b] = acc;
         }
       }
     }
@@ -460,7 +488,8 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         rs.sz = zn;
       }
     }
-    __syncthreads();
+    // No barrier here: a wave can only pass the next gather after every row of this block
+    // was published, and each owner publishes after it has read red[][].
 
     if ((k % a.check_interval == 0) || (k == a.max_iter)) {
       const CheckOut co = run_check<T, NC>(a, rs, r0, nrows, k, nchk, j);
@@ -478,6 +507,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         j = co.jn;
         srho = (T)(a.grid[j] * (seq ? a.rho_eq_scale : 1.0));
         load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+        load_lds_rows<T, NC>(a, j, r0, NRS, nlds, wl);
       }
     }
 
@@ -499,40 +529,72 @@ const void* pick_kernel() {
   return reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs>);
 }
 
+struct KernelChoice {
+  const void* fn;
+  int nc, nrs;
+};
+
 template <typename T>
-const void* kernel_for(int L) {
-  if (L <= BS) return pick_kernel<T, 1>();
-  if (L <= 2 * BS) return pick_kernel<T, 2>();
-  if (L <= 4 * BS) return pick_kernel<T, 4>();
-  if (L <= 8 * BS) return pick_kernel<T, 8>();
-  return nullptr;
+KernelChoice kernel_for(int L) {
+  auto mk = [](const void* f, int nc) {
+    int nrs0 = 32 / (nc * words<T>());
+    return KernelChoice{f, nc, nrs0 > kMaxRows ? kMaxRows : nrs0};
+  };
+  if (L <= BS) return mk(pick_kernel<T, 1>(), 1);
+  if (L <= 2 * BS) return mk(pick_kernel<T, 2>(), 2);
+  if (L <= 4 * BS) return mk(pick_kernel<T, 4>(), 4);
+  if (L <= 8 * BS) return mk(pick_kernel<T, 8>(), 8);
+  return KernelChoice{nullptr, 0, 0};
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_layer(const LayerArgs& a, int grid, hipStream_t st) {
-  const void* k = kernel_for<T>(a.L);
-  if (!k) return hipErrorInvalidValue;
-  LayerArgs copy = a;
-  void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(BS), args, 0, st);
+LaunchPlan plan_layer(int L, int grid) {
+  LaunchPlan p{};
+  const KernelChoice kc = kernel_for<T>(L);
+  if (!kc.fn || grid < 1) return p;
+  int dev = 0, smem_max = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return p;
+  if (hipDeviceGetAttribute(&smem_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return p;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return p;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, kc.fn) != hipSuccess) return p;
+  const long row_bytes = (long)kc.nc * BS * sizeof(T);
+  const int rows_max = (L + grid - 1) / grid;  // rows of the largest block
+  const int want = rows_max > kc.nrs ? rows_max - kc.nrs : 0;
+  const long room = (long)smem_max - (long)fa.sharedSizeBytes - 256;
+  int lds_rows = room > 0 ? (int)(room / row_bytes) : 0;
+  if (lds_rows > want) lds_rows = want;
+  p.fn = kc.fn;
+  p.lds_rows = lds_rows;
+  p.dyn_bytes = (size_t)lds_rows * row_bytes;
+  if (hipFuncSetAttribute(kc.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.dyn_bytes) != hipSuccess) {
+    p.fn = nullptr;
+    return p;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kc.fn, BS, p.dyn_bytes) != hipSuccess) {
+    p.fn = nullptr;
+    return p;
+  }
+  p.max_grid = per_cu * cus;
+  p.reg_rows = kc.nrs;
+  return p;
 }
 
 template <typename T>
-int max_layer_grid(int L) {
-  const void* k = kernel_for<T>(L);
-  if (!k) return 0;
-  int dev = 0, per_cu = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, BS, 0) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  return per_cu * cus;
+hipError_t launch_layer(const LayerArgs& a, const LaunchPlan& p, int grid, hipStream_t st) {
+  if (!p.fn) return hipErrorInvalidValue;
+  LayerArgs copy = a;
+  copy.lds_rows = p.lds_rows;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(p.fn, dim3(grid), dim3(BS), args, p.dyn_bytes, st);
 }
 
-template hipError_t launch_layer<float>(const LayerArgs&, int, hipStream_t);
-template hipError_t launch_layer<double>(const LayerArgs&, int, hipStream_t);
-template int max_layer_grid<float>(int);
-template int max_layer_grid<double>(int);
+template LaunchPlan plan_layer<float>(int, int);
+template LaunchPlan plan_layer<double>(int, int);
+template hipError_t launch_layer<float>(const LayerArgs&, const LaunchPlan&, int, hipStream_t);
+template hipError_t launch_layer<double>(const LayerArgs&, const LaunchPlan&, int, hipStream_t);
 
 }  // namespace rqp

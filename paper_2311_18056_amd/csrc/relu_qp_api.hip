@@ -56,7 +56,7 @@ struct relu_qp_handle {
   std::vector<unsigned char> eq;
   int j0 = 0;
   int grid_wg = 0;   // workgroups of the persistent launch
-  int max_grid = 0;  // largest cooperative grid
+  rqp::LaunchPlan plan{};
   // device
   void* W = nullptr;
   long w_stride = 0;
@@ -206,24 +206,37 @@ int build_weights(relu_qp_handle* h, const double* P, const double* A, hipStream
   return RQP_OK;
 }
 
+rqp::LaunchPlan make_plan(const relu_qp_handle* h, int grid) {
+  return h->esize == 8 ? rqp::plan_layer<double>(h->L, grid) : rqp::plan_layer<float>(h->L, grid);
+}
+
+// Launch shape: one workgroup per compute unit (at most one per row), at most kMaxRows rows
+// per workgroup.
+int set_grid(relu_qp_handle* h, int grid) {
+  const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
+  if (grid < need || grid > h->L) return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, h->L);
+  rqp::LaunchPlan p = make_plan(h, grid);
+  if (!p.fn) return fail(RQP_EHIP, "no kernel resources for n + m = %d", h->L);
+  if (grid > p.max_grid) return fail(RQP_EINVAL, "grid %d exceeds the cooperative limit %d", grid, p.max_grid);
+  h->plan = p;
+  h->grid_wg = grid;
+  return RQP_OK;
+}
+
 int choose_grid(relu_qp_handle* h) {
   int cus = 0, dev = 0;
   HIP_OR_FAIL(hipGetDevice(&dev));
   HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  h->max_grid = h->esize == 8 ? rqp::max_layer_grid<double>(h->L) : rqp::max_layer_grid<float>(h->L);
   const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
-  if (h->max_grid < need) return fail(RQP_EINVAL, "problem too large for one cooperative launch (L=%d)", h->L);
   int g = cus < h->L ? cus : h->L;
-  if (g > h->max_grid) g = h->max_grid;
   if (g < need) g = need;
-  h->grid_wg = g;
-  return RQP_OK;
+  return set_grid(h, g);
 }
 
 int alloc_exchange(relu_qp_handle* h) {
   const size_t words = h->esize == 8 ? 2 : 1;
   h->xw_words = 2 * (size_t)h->L * words;
-  h->xn_words = 2 * (size_t)(h->max_grid > 0 ? h->max_grid : 1) * 8 * 2;
+  h->xn_words = 2 * (size_t)h->L * 8 * 2;  // any grid has at most L workgroups
   HIP_OR_FAIL(hipMalloc(&h->xw, h->xw_words * 8));
   HIP_OR_FAIL(hipMalloc(&h->xc, h->xw_words * 8));
   HIP_OR_FAIL(hipMalloc(&h->xn, h->xn_words * 8));
@@ -499,7 +512,8 @@ int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
   a.tag = h->tag;
   a.abort_flag = h->abort_d;
   a.err = h->err;
-  hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->grid_wg, st) : rqp::launch_layer<float>(a, h->grid_wg, st);
+  hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->plan, h->grid_wg, st)
+                               : rqp::launch_layer<float>(a, h->plan, h->grid_wg, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
   h->tag += span;
   h->warm_pending = false;
@@ -527,12 +541,7 @@ int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid, int* n_rho) {
 
 int relu_qp_set_launch(relu_qp_handle* h, int grid) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
-  if (grid == 0) return choose_grid(h);
-  const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
-  if (grid < need || grid > h->max_grid || grid > h->L)
-    return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, h->max_grid < h->L ? h->max_grid : h->L);
-  h->grid_wg = grid;
-  return RQP_OK;
+  return grid == 0 ? choose_grid(h) : set_grid(h, grid);
 }
 
 int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block) {

@@ -125,9 +125,31 @@ class Solver:
     def set_warm(self, enabled: bool):
         check(lib().relu_qp_set_warm(self._h, 1 if enabled else 0))
 
-    def solve(self, stream=None):
-        """Launch the whole online loop (asynchronous on the stream)."""
-        check(lib().relu_qp_solve(self._h, _stream_handle(stream), byref(self._res)))
+    def solve(self, stream=None, out: Result | None = None):
+        """Launch the whole online loop (asynchronous on the stream). ``out`` optionally names
+        other device result buffers (a ``Result`` from ``result_slots``)."""
+        check(lib().relu_qp_solve(self._h, _stream_handle(stream), byref(out if out is not None else self._res)))
+
+    def result_slots(self, count: int):
+        """Device buffers for ``count`` solves (one slot each) and their ``Result`` structs.
+
+        Returns (tensors, results): tensors is a dict of batched tensors (x: count x n, ...).
+        """
+        dev = self.device
+        t = dict(
+            x=torch.zeros(count, self.n, dtype=self.dtype, device=dev),
+            y=torch.zeros(count, self.m, dtype=self.dtype, device=dev),
+            z=torch.zeros(count, self.m, dtype=self.dtype, device=dev),
+            iterations=torch.zeros(count, dtype=torch.int32, device=dev),
+            status=torch.zeros(count, dtype=torch.int32, device=dev),
+            rho_index=torch.zeros(count, dtype=torch.int32, device=dev),
+        )
+        res = [
+            Result(t["x"][i].data_ptr(), t["y"][i].data_ptr(), t["z"][i].data_ptr(), t["iterations"][i].data_ptr(),
+                   t["status"][i].data_ptr(), t["rho_index"][i].data_ptr(), None, None, None)
+            for i in range(count)
+        ]
+        return t, res
 
     def abort(self):
         check(lib().relu_qp_abort(self._h))
