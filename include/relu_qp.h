@@ -53,8 +53,19 @@ enum {
 
 /* arithmetic of the online iteration */
 enum {
-  RQP_FP64 = 0, /* FP64 weights, iterates and residuals */
-  RQP_FP32 = 1  /* FP32 weights and iterates; residual products accumulated in FP64 */
+  RQP_FP64 = 0,  /* FP64 weights, iterates and residuals (single-instance engine) */
+  RQP_FP32 = 1,  /* FP32 weights and iterates; single-instance engine: residual products
+                    accumulated in FP64; batched engine: FP32 matrix-core products */
+  RQP_BF16X3 = 2 /* batched engine: weights and layer inputs split into BF16 high + low parts,
+                    three BF16 matrix-core products (hi*hi + lo*hi + hi*lo) accumulated in FP32,
+                    FP32 iterates, FP64 residual norms */
+};
+
+/* which kernel runs the online stage */
+enum {
+  RQP_ENGINE_AUTO = 0,   /* single-instance for batch == 1 with FP64/FP32, else batched */
+  RQP_ENGINE_SINGLE = 1, /* one instance spread over the whole GPU (batch must be 1) */
+  RQP_ENGINE_BATCH = 2   /* many instances as one GEMM per iteration (FP32 or BF16X3) */
 };
 
 typedef struct {
@@ -69,8 +80,9 @@ typedef struct {
   double eps_rel;
   int max_iter;        /* default 4000 */
   int check_interval;  /* default 25 (Sec. III-C); a check also runs at max_iter */
-  int precision;       /* RQP_FP64 or RQP_FP32 */
-  int batch;           /* instances sharing P and A (>= 1); the multi-workgroup path needs 1 */
+  int precision;       /* RQP_FP64, RQP_FP32 or RQP_BF16X3 */
+  int batch;           /* instances sharing P and A (>= 1) */
+  int engine;          /* RQP_ENGINE_* (default AUTO) */
 } relu_qp_settings;
 
 typedef struct relu_qp_handle relu_qp_handle; /* opaque, library-owned */
@@ -121,8 +133,8 @@ int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const dou
  * q, l, u of every instance on the GPU, asynchronously on stream. */
 int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream);
 
-/* Warm start (Sec. II-B): the next solve starts from x (n), y (m) and grid index rho_index,
- * with z = A x. Host FP64 arrays for instance 0 (batch must be 1). Synchronous. */
+/* Warm start (Sec. II-B): the next solve starts from x (batch*n), y (batch*m) and grid index
+ * rho_index (the same for every instance), with z = A x. Host FP64 arrays. Synchronous. */
 int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int rho_index);
 
 /* enabled != 0: every later solve starts from the previous solve's x, y and penalty, with

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "librelu_qp.so")
 
 RQP_OK, RQP_EINVAL, RQP_ENOMEM, RQP_EHIP, RQP_ENOTPD, RQP_ESTATE = 0, -1, -2, -3, -4, -5
 RQP_RUNNING, RQP_SOLVED, RQP_MAX_ITER, RQP_NONFINITE, RQP_ABORTED, RQP_INTERNAL = 0, 1, 2, 3, 4, 5
-RQP_FP64, RQP_FP32 = 0, 1
+RQP_FP64, RQP_FP32, RQP_BF16X3 = 0, 1, 2
+RQP_ENGINE_AUTO, RQP_ENGINE_SINGLE, RQP_ENGINE_BATCH = 0, 1, 2
 
 ERROR_NAMES = {
     RQP_EINVAL: "RQP_EINVAL",
@@ -61,6 +62,7 @@ class Settings(Structure):
         ("check_interval", c_int),
         ("precision", c_int),
         ("batch", c_int),
+        ("engine", c_int),
     ]
 
 

@@ -14,8 +14,9 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "librelu_qp.so")
-SOURCES = ["setup_kernels.hip", "layer_kernel.hip", "relu_qp_api.hip"]
+SOURCES = ["setup_kernels.hip", "layer_kernel.hip", "batch_kernel.hip", "relu_qp_api.hip"]
 ARCH = os.environ.get("RELU_QP_ARCH", "gfx950")
 
 HIP_FLAGS = [
@@ -45,7 +46,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIP_FLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in ln]
         if r.returncode != 0:

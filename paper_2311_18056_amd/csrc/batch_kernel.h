@@ -1,0 +1,70 @@
+// Batched online stage: many instances that share P and A (so the layer matrices), each with
+// its own q, l, u, state, penalty index and termination, in one persistent launch. The layer
+// product of all active instances is a GEMM on the matrix cores.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rqp {
+
+enum BatchPrec { kBatchF32 = 0, kBatchBF16x3 = 1 };
+
+constexpr int kTileM = 128;   // instances per tile
+constexpr int kTileN = 128;   // layer rows per tile
+constexpr int kTileK = 32;    // k per LDS stage
+constexpr int kBatchBlock = 256;
+
+struct BatchArgs {
+  int n, m, L, B;
+  long ldk;                 // leading dimension (elements) of weights and operands, multiple of kTileK
+  int prec;                 // BatchPrec
+  const void* Wa;           // FP32 layer matrices, or BF16 high parts: n_rho x L x ldk
+  const void* Wb;           // BF16 low parts (kBatchBF16x3), else null
+  long w_stride;            // elements between penalty matrices
+  const void* Ca;           // check matrix [P, A'; A, 0], same format (L x ldk)
+  const void* Cb;
+  const float* Q;           // B x n
+  const float* Lo;          // B x m
+  const float* Up;          // B x m
+  const unsigned char* eq;  // m
+  const double* grid;
+  const double* mid;
+  int n_rho;
+  double sigma, alpha, eps_abs, eps_rel, rho_eq_scale;
+  int max_iter, check_interval, terminate, warm, j0;
+  float* X;                 // state B x n
+  float* Z;                 // state B x m
+  float* Y;                 // state B x m
+  void* Va;                 // layer inputs, 2 parities x B x ldk (FP32, or BF16 high)
+  void* Vb;                 // BF16 low parts
+  void* CVa;                // check operand [x; y], B x ldk
+  void* CVb;
+  int* jb;                  // B penalty indices (read at start when warm)
+  int* status;              // B
+  int* iterations;          // B
+  int* rho_hist;            // B x max_checks, may be null
+  double* prim_res;         // B x max_checks, may be null
+  double* dual_res;         // B x max_checks, may be null
+  int max_checks;
+  unsigned long long* norms;  // B x 8 (ordered FP64 bit patterns), zero at launch
+  int* lists;               // B instance ids grouped by penalty index
+  int* mtiles;              // per M-tile: {j, offset, count}, up to B/kTileM + n_rho entries, + count
+  unsigned* bar;            // grid barrier words (zero at launch)
+  const int* abort_flag;    // host-mapped
+};
+
+struct BatchPlan {
+  const void* fn;
+  int grid;
+};
+
+BatchPlan plan_batch(int prec);
+hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st);
+
+// FP64 -> (BF16 high, BF16 low) split of a row-major matrix into ldk-padded rows.
+hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long ldk,
+                      hipStream_t st);
+// FP64 -> FP32 copy into ldk-padded rows.
+hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long ldk, hipStream_t st);
+
+}  // namespace rqp

@@ -1,0 +1,671 @@
+// Batched persistent ReLU-QP solve on the matrix cores (gfx950).
+//
+// B instances share P and A, hence the layer matrices Wc_j = [D_j, D_jA'; AD_j, AD_jA'] of the
+// penalty grid; each has its own q, l, u, state (x, z, y), penalty index j_b and termination.
+// One iteration for all active instances is the GEMM  OUT[b][r] = sum_c V[b][c] Wc_{j_b}[r][c]
+// with V[b] = [sigma x_b - q_b ; rho_b z_b - y_b], followed by the row-local update of the
+// single-instance kernel (relaxation, clamp, dual update) fused into the GEMM epilogue, which
+// also writes the next V. Instances are grouped by penalty index so that a tile of 128
+// instances uses one matrix; tiles are 128 instances x 128 layer rows, K in steps of 32.
+//
+// Precision: FP32 operands on v_mfma_f32_32x32x2_f32, or BF16 high/low splits of both operands
+// with three products hi*hi + lo*hi + hi*lo on v_mfma_f32_32x32x16_bf16 (FP32 accumulation),
+// which keeps ~16 significant bits of each operand; iterates stay FP32.
+//
+// Every check_interval iterations the same GEMM with the check matrix [P, A'; A, 0] and the
+// operand [x; y] gives P x, A'y and A x of every instance; per-instance inf-norms are reduced
+// with integer max on ordered FP64 bit patterns (atomics across row tiles), then one thread per
+// instance applies the stopping test and the penalty rule. Phases are separated by a grid
+// barrier (cooperative launch). An instance's arithmetic never depends on which other
+// instances share its tiles, so a result is the same alone and in a batch.
+#include "batch_kernel.h"
+
+#include "device_common.h"
+
+namespace rqp {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+
+constexpr int BS = kBatchBlock;
+constexpr int TM = kTileM, TN = kTileN, TK = kTileK;
+constexpr int PADB = 8;  // bf16 row padding in LDS (elements)
+constexpr int PADF = 4;  // fp32 row padding in LDS (elements)
+constexpr unsigned kBarSpin = 1u << 24;
+
+enum { ST_RUNNING = 0, ST_SOLVED = 1, ST_MAX_ITER = 2, ST_NONFINITE = 3, ST_ABORTED = 4, ST_INTERNAL = 5 };
+enum { N_RP = 0, N_RD, N_AX, N_Z, N_PX, N_ATY, N_Q };
+
+__device__ __forceinline__ unsigned ld_acq(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Two-level grid barrier (8 groups by blockIdx % 8, then a global counter and a flag word).
+// Counters are monotone: barrier number e completes when they reach e * size. Returns false
+// if a wait exceeded the spin bound or another workgroup gave up (bar[1] set); every
+// workgroup then leaves the kernel.
+__device__ bool grid_barrier(unsigned* bar, unsigned e) {
+  __shared__ int ok_s;
+  // every wave's stores are made visible at device scope before its workgroup arrives
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned G = gridDim.x, g = blockIdx.x & 7u, ng = G < 8 ? G : 8;
+    const unsigned gsize = (G - g + 7u) / 8u;
+    int ok = 1;
+    const unsigned old = __hip_atomic_fetch_add(bar + 64 + 32 * g, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == e * gsize - 1u) {
+      const unsigned o2 = __hip_atomic_fetch_add(bar + 32, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 == e * ng - 1u) __hip_atomic_store(bar, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned spins = 0;
+    while (ld_acq(bar) < e) {
+      if (++spins > kBarSpin || ld_acq(bar + 1) != 0u) {
+        ok = 0;
+        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok_s = ok;
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// BF16 round to nearest even; the low part takes the rounding error, so hi + lo carries ~16
+// significant bits.
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+template <int PREC>
+__device__ __forceinline__ void put_operand(void* va, void* vb, long idx, float v) {
+  if constexpr (PREC == kBatchBF16x3) {
+    const unsigned short h = bf16_bits(v);
+    static_cast<unsigned short*>(va)[idx] = h;
+    static_cast<unsigned short*>(vb)[idx] = bf16_bits(v - bf16_float(h));
+  } else {
+    static_cast<float*>(va)[idx] = v;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// GEMM tile: acc[mb][nb] (each 32 x 32, lane layout of v_mfma_f32_32x32x*) for the 64 x 64
+// quarter of the 128 x 128 tile owned by this wave. Operand A rows are instances (element
+// offsets, -1 = zero row), B rows are matrix rows; both are K-contiguous with ld = ldk.
+
+template <int PREC>
+struct Smem;
+template <>
+struct Smem<kBatchBF16x3> {
+  static constexpr int kRowsPerThread = 2;  // rows tid/4 and tid/4 + 64, 8 bf16 each
+  unsigned short a[2][2][TM][TK + PADB];    // [stage][hi/lo][row][k]
+  unsigned short b[2][2][TN][TK + PADB];
+};
+template <>
+struct Smem<kBatchF32> {
+  static constexpr int kRowsPerThread = 4;  // rows tid/8 + 32 q, 4 floats each
+  float a[2][TM][TK + PADF];
+  float b[2][TN][TK + PADF];
+};
+
+template <int PREC>
+__device__ __forceinline__ int loader_row(int q) {
+  if constexpr (PREC == kBatchBF16x3)
+    return threadIdx.x / 4 + 64 * q;
+  else
+    return threadIdx.x / 8 + 32 * q;
+}
+
+template <int N, typename V>
+__device__ __forceinline__ V mask_k(V v, long c0, int kb, int ke) {
+  if (c0 >= kb && c0 + N <= ke) return v;
+#pragma unroll
+  for (int e = 0; e < N; ++e)
+    if (c0 + e < kb || c0 + e >= ke) v[e] = 0;
+  return v;
+}
+
+// acc = sum over k in [kb, ke) of A[row][k] B[col][k]
+template <int PREC>
+__device__ __forceinline__ void tile_gemm(Smem<PREC>& sm, const void* Aa, const void* Ab, const void* Ba,
+                                          const void* Bb, const long (&aoff)[Smem<PREC>::kRowsPerThread],
+                                          const long (&boff)[Smem<PREC>::kRowsPerThread], int kb, int ke,
+                                          floatx16 (&acc)[2][2]) {
+  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
+  const int s_first = kb / TK, nstage = (ke + TK - 1) / TK - s_first;
+
+  if constexpr (PREC == kBatchBF16x3) {
+    const int kc = (tid % 4) * 8;
+    const unsigned short* ah = static_cast<const unsigned short*>(Aa);
+    const unsigned short* al = static_cast<const unsigned short*>(Ab);
+    const unsigned short* bh = static_cast<const unsigned short*>(Ba);
+    const unsigned short* bl = static_cast<const unsigned short*>(Bb);
+    ushort8 ra[2][RPT], rb[2][RPT];
+    auto fetch = [&](int s) {
+      const long k0 = (long)(s_first + s) * TK + kc;
+#pragma unroll
+      for (int h = 0; h < RPT; ++h) {
+        ra[0][h] = aoff[h] >= 0 ? *reinterpret_cast<const ushort8*>(ah + aoff[h] + k0) : ushort8{};
+        ra[1][h] = aoff[h] >= 0 ? *reinterpret_cast<const ushort8*>(al + aoff[h] + k0) : ushort8{};
+        rb[0][h] = boff[h] >= 0 ? *reinterpret_cast<const ushort8*>(bh + boff[h] + k0) : ushort8{};
+        rb[1][h] = boff[h] >= 0 ? *reinterpret_cast<const ushort8*>(bl + boff[h] + k0) : ushort8{};
+        rb[0][h] = mask_k<8>(rb[0][h], k0, kb, ke);
+        rb[1][h] = mask_k<8>(rb[1][h], k0, kb, ke);
+      }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int h = 0; h < RPT; ++h)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          *reinterpret_cast<ushort8*>(&sm.a[buf][p][loader_row<PREC>(h)][kc]) = ra[p][h];
+          *reinterpret_cast<ushort8*>(&sm.b[buf][p][loader_row<PREC>(h)][kc]) = rb[p][h];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int s = 0; s < nstage; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nstage) fetch(s + 1);
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 16) {
+        const int kq = kk + 8 * (lane / 32);
+        bf16x8 fa[2][2], fb[2][2];  // [block][hi/lo]
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            fa[i][p] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const ushort8*>(&sm.a[buf][p][wm * 64 + i * 32 + lane % 32][kq]));
+            fb[i][p] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const ushort8*>(&sm.b[buf][p][wn * 64 + i * 32 + lane % 32][kq]));
+          }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][0], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fb[j][0], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][1], acc[i][j], 0, 0, 0);
+          }
+      }
+      if (s + 1 < nstage) stash(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    const int kc = (tid % 8) * 4;
+    const float* af = static_cast<const float*>(Aa);
+    const float* bf = static_cast<const float*>(Ba);
+    floatx4 ra[RPT], rb[RPT];
+    auto fetch = [&](int s) {
+      const long k0 = (long)(s_first + s) * TK + kc;
+#pragma unroll
+      for (int h = 0; h < RPT; ++h) {
+        ra[h] = aoff[h] >= 0 ? *reinterpret_cast<const floatx4*>(af + aoff[h] + k0) : floatx4{};
+        rb[h] = boff[h] >= 0 ? *reinterpret_cast<const floatx4*>(bf + boff[h] + k0) : floatx4{};
+        rb[h] = mask_k<4>(rb[h], k0, kb, ke);
+      }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int h = 0; h < RPT; ++h) {
+        *reinterpret_cast<floatx4*>(&sm.a[buf][loader_row<PREC>(h)][kc]) = ra[h];
+        *reinterpret_cast<floatx4*>(&sm.b[buf][loader_row<PREC>(h)][kc]) = rb[h];
+      }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int s = 0; s < nstage; ++s) {
+      const int buf = s & 1;
+      if (s + 1 < nstage) fetch(s + 1);
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 2) {
+        const int kq = kk + lane / 32;
+        float fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          fa[i] = sm.a[buf][wm * 64 + i * 32 + lane % 32][kq];
+          fb[i] = sm.b[buf][wn * 64 + i * 32 + lane % 32][kq];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+      if (s + 1 < nstage) stash(buf ^ 1);
+      __syncthreads();
+    }
+  }
+}
+
+// Position in the 128 x 128 tile of accumulator element v of block (i, j) for this lane.
+__device__ __forceinline__ int acc_row(int wm, int i, int v, int lane) {
+  return wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane / 32) + (v % 4);
+}
+__device__ __forceinline__ int acc_col(int wn, int j, int lane) { return wn * 64 + j * 32 + lane % 32; }
+
+// M-tile descriptor: {penalty index, offset into lists, instance count}
+struct MTile {
+  int j, off, cnt;
+};
+
+template <int PREC>
+__device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt, int nt, long abase, long bbase,
+                                             long (&aoff)[Smem<PREC>::kRowsPerThread],
+                                             long (&boff)[Smem<PREC>::kRowsPerThread]) {
+  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const int r = loader_row<PREC>(h);
+    aoff[h] = r < mt.cnt ? abase + (long)a.lists[mt.off + r] * a.ldk : -1;
+    const int row = nt * TN + r;
+    boff[h] = row < a.L ? bbase + (long)row * a.ldk : -1;
+  }
+}
+
+// Counting sort of the active instances by penalty index into lists[] and the M-tile table
+// (one workgroup; stable, so the order inside a bucket is by instance id).
+__device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */) {
+  const int tid = threadIdx.x;
+  constexpr int kMaxRhoB = 64;
+  if (tid < kMaxRhoB) s_count[tid] = 0;
+  __syncthreads();
+  // per-thread contiguous chunk of instances
+  const int chunk = (a.B + BS - 1) / BS;
+  const int b0 = tid * chunk, b1 = min(a.B, b0 + chunk);
+  for (int b = b0; b < b1; ++b)
+    if (a.status[b] == ST_RUNNING) atomicAdd(&s_count[a.jb[b]], 1);
+  __syncthreads();
+  __shared__ int s_base[kMaxRhoB];
+  if (tid == 0) {
+    int off = 0, nt = 0;
+    MTile* mt = reinterpret_cast<MTile*>(a.mtiles + 1);
+    for (int j = 0; j < a.n_rho; ++j) {
+      s_base[j] = off;
+      for (int c = 0; c < s_count[j]; c += TM) mt[nt++] = MTile{j, off + c, min(TM, s_count[j] - c)};
+      off += s_count[j];
+    }
+    a.mtiles[0] = nt;
+  }
+  __syncthreads();
+  // stable scatter: thread order then instance order; positions by an exclusive scan over
+  // threads per bucket, done serially per bucket (n_rho small) with LDS
+  __shared__ int s_scan[BS];
+  for (int j = 0; j < a.n_rho; ++j) {
+    int mine = 0;
+    for (int b = b0; b < b1; ++b) mine += (a.status[b] == ST_RUNNING && a.jb[b] == j);
+    s_scan[tid] = mine;
+    __syncthreads();
+    if (tid == 0) {
+      int acc = s_base[j];
+      for (int t = 0; t < BS; ++t) {
+        const int c = s_scan[t];
+        s_scan[t] = acc;
+        acc += c;
+      }
+    }
+    __syncthreads();
+    int pos = s_scan[tid];
+    for (int b = b0; b < b1; ++b)
+      if (a.status[b] == ST_RUNNING && a.jb[b] == j) a.lists[pos++] = b;
+    __syncthreads();
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Smem<PREC>& sm = *reinterpret_cast<Smem<PREC>*>(smem_raw);
+  __shared__ int s_count[64];
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int n = a.n, L = a.L, B = a.B;
+  const long ldk = a.ldk;
+  const long vpar = (long)B * ldk;  // elements per parity of V
+  const int ntiles_n = (L + TN - 1) / TN;
+  const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha), sigma = (float)a.sigma;
+  unsigned epoch = 0;
+  const long gtid = (long)g * BS + tid, gstride = (long)G * BS;
+
+  // ---- statuses and penalty indices
+  for (long b = gtid; b < B; b += gstride) {
+    a.status[b] = ST_RUNNING;
+    a.iterations[b] = 0;
+    if (!a.warm) a.jb[b] = a.j0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a.norms[b * 8 + q] = 0ull;
+  }
+  if (!a.warm) {
+    for (long e = gtid; e < (long)B * n; e += gstride) a.X[e] = 0.0f;
+    for (long e = gtid; e < (long)B * a.m; e += gstride) {
+      a.Z[e] = 0.0f;
+      a.Y[e] = 0.0f;
+    }
+  } else {
+    // warm start (Sec. II-B): keep x, y and the penalty, set z = A x
+    for (long e = gtid; e < (long)B * L; e += gstride) {
+      const int b = (int)(e / L), r = (int)(e % L);
+      put_operand<PREC>(a.CVa, a.CVb, (long)b * ldk + r, r < n ? a.X[(long)b * n + r] : a.Y[(long)b * a.m + (r - n)]);
+    }
+  }
+  if (!grid_barrier(a.bar, ++epoch)) return;
+  if (g == 0) build_tiles(a, s_count);
+  if (!grid_barrier(a.bar, ++epoch)) return;
+  if (a.warm) {
+    const int nmt = a.mtiles[0];
+    const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
+    const int nt0 = n / TN;  // first row tile holding constraint rows
+    for (int t = g; t < nmt * (ntiles_n - nt0); t += G) {
+      const MTile mt = mts[t % nmt];
+      const int nt = nt0 + t / nmt;
+      long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
+      tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
+      floatx16 acc[2][2];
+      tile_gemm<PREC>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int r = nt * TN + acc_col(wn, j, lane);
+          if (r < n || r >= L) continue;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int ti = acc_row(wm, i, v, lane);
+            if (ti < mt.cnt) a.Z[(long)a.lists[mt.off + ti] * a.m + (r - n)] = acc[i][j][v];
+          }
+        }
+    }
+    if (!grid_barrier(a.bar, ++epoch)) return;
+  }
+  // ---- first layer input V_1 (parity 1)
+  for (long e = gtid; e < (long)B * L; e += gstride) {
+    const int b = (int)(e / L), r = (int)(e % L);
+    float w;
+    if (r < n) {
+      w = sigma * a.X[(long)b * n + r] - a.Q[(long)b * n + r];
+    } else {
+      const int i = r - n;
+      const long zi = (long)b * a.m + i;
+      const float rho = (float)(a.grid[a.jb[b]] * (a.eq[i] ? a.rho_eq_scale : 1.0));
+      w = rho * a.Z[zi] - a.Y[zi];
+    }
+    put_operand<PREC>(a.Va, a.Vb, vpar + (long)b * ldk + r, w);
+  }
+  if (!grid_barrier(a.bar, ++epoch)) return;
+
+  int nchk = 0;
+  for (int k = 1; k <= a.max_iter; ++k) {
+    const bool is_check = (k % a.check_interval == 0) || (k == a.max_iter);
+    const int nmt = a.mtiles[0];
+    const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
+    const long vin = (long)(k & 1) * vpar, vout = (long)((k + 1) & 1) * vpar;
+
+    // ---- layer GEMM + fused update
+    for (int t = g; t < nmt * ntiles_n; t += G) {
+      const MTile mt = mts[t % nmt];
+      const int nt = t / nmt;
+      long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
+      tile_offsets<PREC>(a, mt, nt, vin, (long)mt.j * a.w_stride, aoff, boff);
+      floatx16 acc[2][2];
+      tile_gemm<PREC>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, 0, L, acc);
+      const double rho_bar = a.grid[mt.j];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int r = nt * TN + acc_col(wn, j, lane);
+          if (r >= L) continue;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int ti = acc_row(wm, i, v, lane);
+            if (ti >= mt.cnt) continue;
+            const int b = a.lists[mt.off + ti];
+            const float s = acc[i][j][v];
+            float w, cv;
+            if (r < n) {
+              const long xi = (long)b * n + r;
+              const float x = alpha * s + oma * a.X[xi];
+              a.X[xi] = x;
+              w = sigma * x - a.Q[xi];
+              cv = x;
+            } else {
+              const int ii = r - n;
+              const long zi = (long)b * a.m + ii;
+              const float rho = (float)(rho_bar * (a.eq[ii] ? a.rho_eq_scale : 1.0));
+              const float t2 = alpha * s + oma * a.Z[zi] + a.Y[zi] / rho;
+              const float lo = a.Lo[zi], up = a.Up[zi];
+              const float zn = t2 < lo ? lo : (t2 > up ? up : t2);
+              const float yn = rho * (t2 - zn);
+              a.Z[zi] = zn;
+              a.Y[zi] = yn;
+              w = rho * zn - yn;
+              cv = yn;
+            }
+            if (is_check)
+              put_operand<PREC>(a.CVa, a.CVb, (long)b * ldk + r, cv);
+            else
+              put_operand<PREC>(a.Va, a.Vb, vout + (long)b * ldk + r, w);
+          }
+        }
+    }
+    if (!grid_barrier(a.bar, ++epoch)) return;
+    if (!is_check) continue;
+
+    // ---- check GEMM: [P, A'; A, 0] [x; y]; K split at n keeps P x and A'y apart
+    for (int t = g; t < nmt * ntiles_n; t += G) {
+      const MTile mt = mts[t % nmt];
+      const int nt = t / nmt;
+      long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
+      tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
+      floatx16 acc_p[2][2], acc_a[2][2];
+      tile_gemm<PREC>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc_p);  // P x (x rows), A x (z rows)
+      tile_gemm<PREC>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, n, L, acc_a);  // A'y (x rows), 0 (z rows)
+      // per instance (accumulator row) maxima over this tile's rows
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int ti = acc_row(wm, i, v, lane);
+          const bool valid_i = ti < mt.cnt;
+          const int b = valid_i ? a.lists[mt.off + ti] : 0;
+          uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int r = nt * TN + acc_col(wn, j, lane);
+            if (!valid_i || r >= L) continue;
+            const double pp = (double)acc_p[i][j][v], pa = (double)acc_a[i][j][v];
+            if (r < n) {
+              const double q = (double)a.Q[(long)b * n + r];
+              const double rd = pp + pa + q;  // P x + A'y + q
+              const uint64_t vrd = abs_bits(rd), vpx = abs_bits(pp), vat = abs_bits(pa), vq = abs_bits(q);
+              nb[N_RD] = vrd > nb[N_RD] ? vrd : nb[N_RD];
+              nb[N_PX] = vpx > nb[N_PX] ? vpx : nb[N_PX];
+              nb[N_ATY] = vat > nb[N_ATY] ? vat : nb[N_ATY];
+              nb[N_Q] = vq > nb[N_Q] ? vq : nb[N_Q];
+            } else {
+              const double z = (double)a.Z[(long)b * a.m + (r - n)];
+              const uint64_t vrp = abs_bits(pp - z), vax = abs_bits(pp), vz = abs_bits(z);
+              nb[N_RP] = vrp > nb[N_RP] ? vrp : nb[N_RP];
+              nb[N_AX] = vax > nb[N_AX] ? vax : nb[N_AX];
+              nb[N_Z] = vz > nb[N_Z] ? vz : nb[N_Z];
+            }
+          }
+          // lanes with the same lane / 32 hold the same instance row: reduce over lane % 32
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            uint64_t x = nb[q];
+#pragma unroll
+            for (int off = 1; off < 32; off <<= 1) {
+              const uint64_t o = __shfl_xor(x, off, 64);
+              x = o > x ? o : x;
+            }
+            nb[q] = x;
+          }
+          if (valid_i && (lane % 32) == 0) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q)
+              if (nb[q]) atomicMax(a.norms + (long)b * 8 + q, (unsigned long long)nb[q]);
+          }
+        }
+    }
+    if (!grid_barrier(a.bar, ++epoch)) return;
+
+    // ---- per-instance decision (eqs. primal, dual, rho_update; nearest grid value)
+    const bool ab = a.abort_flag && __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (long b = gtid; b < B; b += gstride) {
+      if (a.status[b] != ST_RUNNING) continue;
+      unsigned long long* nm = a.norms + b * 8;
+      uint64_t bits[7];
+      bool nonfinite = false;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) {
+        bits[q] = nm[q];
+        nm[q] = 0;
+        nonfinite |= bits[q] >= kInfBits;
+      }
+      const double rp = bits_to_double(bits[N_RP]), rd = bits_to_double(bits[N_RD]);
+      const double nax = bits_to_double(bits[N_AX]), nz = bits_to_double(bits[N_Z]);
+      const double npx = bits_to_double(bits[N_PX]), naty = bits_to_double(bits[N_ATY]);
+      const double nq = bits_to_double(bits[N_Q]);
+      int st = ST_RUNNING;
+      if (nonfinite) {
+        st = ST_NONFINITE;
+      } else if (a.terminate) {
+        const double eps_p = a.eps_abs + a.eps_rel * fmax(nax, nz);
+        const double eps_d = a.eps_abs + a.eps_rel * fmax(fmax(npx, naty), nq);
+        if (rp <= eps_p && rd <= eps_d) st = ST_SOLVED;
+      }
+      if (st == ST_RUNNING && k == a.max_iter) st = ST_MAX_ITER;
+      if (st == ST_RUNNING && ab) st = ST_ABORTED;
+      int j = a.jb[b];
+      if (st == ST_RUNNING && a.n_rho > 1 && rp > 0.0 && rd > 0.0) {
+        const double num = rp * fmax(fmax(npx, naty), fmax(nq, 1e-4));
+        const double den = rd * fmax(fmax(nax, nz), 1e-4);
+        const double rh = a.grid[j] * sqrt(num / den);
+        int jn = 0;
+        while (jn < a.n_rho - 1 && rh > a.mid[jn]) ++jn;
+        j = jn;
+      }
+      a.jb[b] = j;
+      if (nchk < a.max_checks) {
+        if (a.rho_hist) a.rho_hist[b * a.max_checks + nchk] = j;
+        if (a.prim_res) a.prim_res[b * a.max_checks + nchk] = rp;
+        if (a.dual_res) a.dual_res[b * a.max_checks + nchk] = rd;
+      }
+      if (st != ST_RUNNING) {
+        a.status[b] = st;
+        a.iterations[b] = k;
+      }
+    }
+    ++nchk;
+    if (!grid_barrier(a.bar, ++epoch)) return;
+    if (g == 0) build_tiles(a, s_count);
+    if (!grid_barrier(a.bar, ++epoch)) return;
+    if (a.mtiles[0] == 0) break;
+
+    // ---- next layer input for the instances still running (penalty may have changed)
+    const int nmt2 = a.mtiles[0];
+    for (long e = gtid; e < (long)B * L; e += gstride) {
+      const int b = (int)(e / L), r = (int)(e % L);
+      if (a.status[b] != ST_RUNNING) continue;
+      float w;
+      if (r < n) {
+        const long xi = (long)b * n + r;
+        w = sigma * a.X[xi] - a.Q[xi];
+      } else {
+        const int ii = r - n;
+        const long zi = (long)b * a.m + ii;
+        const float rho = (float)(a.grid[a.jb[b]] * (a.eq[ii] ? a.rho_eq_scale : 1.0));
+        w = rho * a.Z[zi] - a.Y[zi];
+      }
+      put_operand<PREC>(a.Va, a.Vb, vout + (long)b * ldk + r, w);
+    }
+    (void)nmt2;
+    if (!grid_barrier(a.bar, ++epoch)) return;
+  }
+}
+
+}  // namespace
+
+BatchPlan plan_batch(int prec) {
+  BatchPlan p{nullptr, 0};
+  const void* fn = prec == kBatchBF16x3 ? reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3>)
+                                        : reinterpret_cast<const void*>(&batch_kernel<kBatchF32>);
+  const size_t smem = prec == kBatchBF16x3 ? sizeof(Smem<kBatchBF16x3>) : sizeof(Smem<kBatchF32>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return p;
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return p;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return p;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, BS, smem) != hipSuccess) return p;
+  if (per_cu < 1) return p;
+  p.fn = fn;
+  p.grid = cus;  // one workgroup per compute unit
+  return p;
+}
+
+hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st) {
+  if (!p.fn) return hipErrorInvalidValue;
+  const size_t smem = a.prec == kBatchBF16x3 ? sizeof(Smem<kBatchBF16x3>) : sizeof(Smem<kBatchF32>);
+  BatchArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(p.fn, dim3(p.grid), dim3(BS), args, smem, st);
+}
+
+namespace {
+__global__ void split_kernel(long rows, int cols, const double* __restrict__ src, long ld_src,
+                             unsigned short* __restrict__ hi, unsigned short* __restrict__ lo, long ldk) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ldk) return;
+  const long r = idx / ldk;
+  const int c = (int)(idx % ldk);
+  const float v = c < cols ? (float)src[r * ld_src + c] : 0.0f;
+  // split the FP64 value: hi from its FP32 rounding, lo from the remaining FP64 difference
+  const unsigned short h = bf16_bits(v);
+  const double rem = c < cols ? src[r * ld_src + c] - (double)bf16_float(h) : 0.0;
+  hi[idx] = h;
+  lo[idx] = bf16_bits((float)rem);
+}
+__global__ void pad_kernel(long rows, int cols, const double* __restrict__ src, long ld_src, float* __restrict__ dst,
+                           long ldk) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ldk) return;
+  const long r = idx / ldk;
+  const int c = (int)(idx % ldk);
+  dst[idx] = c < cols ? (float)src[r * ld_src + c] : 0.0f;
+}
+}  // namespace
+
+hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long ldk,
+                      hipStream_t st) {
+  const long total = rows * ldk;
+  hipLaunchKernelGGL(split_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, src, ld_src,
+                     static_cast<unsigned short*>(hi), static_cast<unsigned short*>(lo), ldk);
+  return hipGetLastError();
+}
+
+hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long ldk, hipStream_t st) {
+  const long total = rows * ldk;
+  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, src, ld_src,
+                     dst, ldk);
+  return hipGetLastError();
+}
+
+}  // namespace rqp

@@ -87,6 +87,115 @@ __device__ __forceinline__ T wave_sum_to_last(T v) {
 }
 constexpr int kLastLane = kWave - 1;
 
+// ---------------------------------------------------------------------------------------------
+// Sum of R values per lane over the wave, R a power of two <= 64, in ~R + log2(64/R) steps
+// instead of 6 R: at each of the first log2(R) pair steps a lane keeps half of its rows and adds
+// its partner's copy of them (cross-half swaps v_permlane32/16_swap for distances 32 and 16,
+// DPP for 8 and 4 (and 2, 1)); the remaining steps are plain pairwise sums. Every lane ends with
+// the complete sum of one row; which row is fixed by the network and found once with
+// rows_held() below. Lanes whose low log2(64/R) bits are zero hold distinct rows.
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+// x' + y' after swapping the upper half-group of x with the lower half-group of y
+template <int D>
+__device__ __forceinline__ float swap_add(float x, float y) {
+  const uint32_t a = __builtin_bit_cast(uint32_t, x), b = __builtin_bit_cast(uint32_t, y);
+  if constexpr (D == 32) {
+    auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    return __builtin_bit_cast(float, (uint32_t)r[0]) + __builtin_bit_cast(float, (uint32_t)r[1]);
+  } else {
+    auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    return __builtin_bit_cast(float, (uint32_t)r[0]) + __builtin_bit_cast(float, (uint32_t)r[1]);
+  }
+}
+template <int D>
+__device__ __forceinline__ double swap_add(double x, double y) {
+  const uint64_t a = __builtin_bit_cast(uint64_t, x), b = __builtin_bit_cast(uint64_t, y);
+  uint32_t xl, xh, yl, yh;
+  if constexpr (D == 32) {
+    auto rl = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+    auto rh = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+    xl = rl[0]; yl = rl[1]; xh = rh[0]; yh = rh[1];
+  } else {
+    auto rl = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+    auto rh = __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+    xl = rl[0]; yl = rl[1]; xh = rh[0]; yh = rh[1];
+  }
+  return __builtin_bit_cast(double, (uint64_t)xl | ((uint64_t)xh << 32)) +
+         __builtin_bit_cast(double, (uint64_t)yl | ((uint64_t)yh << 32));
+}
+
+// one step at distance D on C values (C even: pair step; C == 1: plain step)
+template <int D, int C, typename T, int N>
+__device__ __forceinline__ void rr_step(T (&v)[N], int lane) {
+  if constexpr (C >= 2) {
+    constexpr int H = C / 2;
+    if constexpr (D >= 16) {
+#pragma unroll
+      for (int i = 0; i < H; ++i) v[i] = swap_add<D>(v[i], v[i + H]);
+    } else {
+      const bool hi = (lane & D) != 0;
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        const T send = hi ? v[i] : v[i + H];
+        const T keep = hi ? v[i + H] : v[i];
+        T recv;
+        if constexpr (D == 8) recv = dpp_mov<0x128>(send);       // row_ror:8 = lane ^ 8 in a row
+        else if constexpr (D == 4) recv = dpp_mov<0x141>(send);  // row_half_mirror: i <-> 7 - i
+        else if constexpr (D == 2) recv = dpp_mov<0x4e>(send);   // quad_perm [2,3,0,1]
+        else recv = dpp_mov<0xb1>(send);                         // quad_perm [1,0,3,2]
+        v[i] = keep + recv;
+      }
+    }
+  } else {
+    if constexpr (D >= 16) v[0] = swap_add<D>(v[0], v[0]);
+    else if constexpr (D == 8) v[0] += dpp_mov<0x128>(v[0]);
+    else if constexpr (D == 4) v[0] += dpp_mov<0x141>(v[0]);
+    else if constexpr (D == 2) v[0] += dpp_mov<0x4e>(v[0]);
+    else v[0] += dpp_mov<0xb1>(v[0]);
+  }
+}
+
+template <int R, typename T, int N>
+__device__ __forceinline__ T reduce_rows(T (&v)[N]) {
+  static_assert(N >= R, "need R values");
+  static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32 || R == 64, "R must be a power of two");
+  const int lane = threadIdx.x % kWave;
+  constexpr int C1 = R, C2 = R > 1 ? R / 2 : 1, C3 = R > 2 ? R / 4 : 1, C4 = R > 4 ? R / 8 : 1,
+                C5 = R > 8 ? R / 16 : 1, C6 = R > 16 ? R / 32 : 1;
+  rr_step<32, C1>(v, lane);
+  rr_step<16, C2>(v, lane);
+  rr_step<8, C3>(v, lane);
+  rr_step<4, C4>(v, lane);
+  rr_step<2, C5>(v, lane);
+  rr_step<1, C6>(v, lane);
+  return v[0];
+}
+
+// Row whose total this lane holds after reduce_rows<R> (found by reducing row numbers).
+template <int R>
+__device__ __forceinline__ int rows_held() {
+  float v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = (float)(r + 1);
+  const float s = reduce_rows<R>(v);
+  return (int)(s / (float)kWave + 0.5f) - 1;
+}
+template <int R>
+__device__ __forceinline__ bool row_writer() {
+  return ((threadIdx.x % kWave) & (kWave / R - 1)) == 0;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

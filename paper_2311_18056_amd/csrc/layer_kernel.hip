@@ -34,9 +34,15 @@ namespace {
 constexpr int BS = kLayerBlock;
 constexpr int NWAVE = BS / kWave;
 constexpr unsigned kSpinLimit = 1u << 22;
-constexpr int RC = 1;  // rows per chunk for streamed rows and check rows
 
 enum { ST_RUNNING = 0, ST_SOLVED = 1, ST_MAX_ITER = 2, ST_NONFINITE = 3, ST_ABORTED = 4, ST_INTERNAL = 5 };
+constexpr int kMaxRho = 64;  // the host accepts at most 64 penalty values
+
+// penalty grid and the geometric midpoints between neighbours, copied to LDS once per launch
+struct RhoTable {
+  double grid[kMaxRho];
+  double mid[kMaxRho];
+};
 enum { N_RP = 0, N_RD, N_AX, N_Z, N_PX, N_ATY, N_Q, N_FLAGS };
 
 // The error word holds the tag of the solve that failed, so a failure never leaks into a later
@@ -67,17 +73,17 @@ __device__ __forceinline__ bool gather(const uint64_t* buf, int L, uint32_t tag,
   while (true) {
     bool all = true;
 #pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+      for (int q = 0; q < NW; ++q) all &= ll_tag(w[k][q]) == tag;
+    if (all) break;
+    // reload every word of the lane (no per-word branches): simple code, few live masks
+#pragma unroll
     for (int k = 0; k < NC; ++k) {
       const int c = tid + BS * k;
 #pragma unroll
-      for (int q = 0; q < NW; ++q) {
-        if (ll_tag(w[k][q]) != tag) {
-          all = false;
-          w[k][q] = ll_load_word(buf + (long)c * NW + q);
-        }
-      }
+      for (int q = 0; q < NW; ++q) w[k][q] = (c < L) ? ll_load_word(buf + (long)c * NW + q) : dummy;
     }
-    if (all) break;
     if ((++spins & 255u) == 0u && (spins > kSpinLimit || err_set(err, etag))) {
       ok = false;
       break;
@@ -97,24 +103,28 @@ __device__ __forceinline__ bool gather(const uint64_t* buf, int L, uint32_t tag,
 // which all carry the same norm index t % 8.
 __device__ __forceinline__ bool gather_norms(const uint64_t* buf, int count, uint32_t tag, uint64_t& mx,
                                              const unsigned* err, uint32_t etag) {
+  // count <= 8 * 256 (one entry per workgroup and norm), so a lane has at most two entries
   const int tid = threadIdx.x;
-  mx = 0;
+  const int e0 = tid, e1 = tid + BS;
+  const uint64_t dummy = (uint64_t)tag << 32;
+  uint64_t w0 = e0 < count ? ll_load_word(buf + 2L * e0) : dummy;
+  uint64_t w1 = e0 < count ? ll_load_word(buf + 2L * e0 + 1) : dummy;
+  uint64_t w2 = e1 < count ? ll_load_word(buf + 2L * e1) : dummy;
+  uint64_t w3 = e1 < count ? ll_load_word(buf + 2L * e1 + 1) : dummy;
+  unsigned spins = 0;
   bool ok = true;
-  for (int e = tid; e < count; e += BS) {
-    uint64_t lo = ll_load_word(buf + 2L * e), hi = ll_load_word(buf + 2L * e + 1);
-    unsigned spins = 0;
-    while (ll_tag(lo) != tag || ll_tag(hi) != tag) {
-      if (ll_tag(lo) != tag) lo = ll_load_word(buf + 2L * e);
-      if (ll_tag(hi) != tag) hi = ll_load_word(buf + 2L * e + 1);
-      if ((++spins & 255u) == 0u && (spins > kSpinLimit || err_set(err, etag))) {
-        ok = false;
-        break;
-      }
+  while (ll_tag(w0) != tag || ll_tag(w1) != tag || ll_tag(w2) != tag || ll_tag(w3) != tag) {
+    w0 = e0 < count ? ll_load_word(buf + 2L * e0) : dummy;
+    w1 = e0 < count ? ll_load_word(buf + 2L * e0 + 1) : dummy;
+    w2 = e1 < count ? ll_load_word(buf + 2L * e1) : dummy;
+    w3 = e1 < count ? ll_load_word(buf + 2L * e1 + 1) : dummy;
+    if ((++spins & 255u) == 0u && (spins > kSpinLimit || err_set(err, etag))) {
+      ok = false;
+      break;
     }
-    if (!ok) break;
-    uint64_t v = ll_bits64(lo, hi);
-    mx = v > mx ? v : mx;
   }
+  const uint64_t v0 = e0 < count ? ll_bits64(w0, w1) : 0, v1 = e1 < count ? ll_bits64(w2, w3) : 0;
+  mx = v0 > v1 ? v0 : v1;
   return ok;
 }
 
@@ -141,6 +151,7 @@ __device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows
   const int n = a.n, L = a.L;
   const long ldw = a.ldw;
   const T* Cm = static_cast<const T*>(a.C);
+  constexpr int RC = 16 / NC > 0 ? 16 / NC : 1;  // rows of the check matrix loaded together
   for (int rr = 0; rr < nrows; rr += RC) {
     T cr[RC][NC];
 #pragma unroll
@@ -196,8 +207,8 @@ struct CheckOut {
 // grid value, Sec. III-C) at iteration k, check number nchk. Every workgroup returns the same
 // result.
 template <typename T, int NC>
-__device__ __forceinline__ CheckOut run_check(const LayerArgs& a, RowState<T> rs, int r0, int nrows, int k, int nchk,
-                                           int j) {
+__device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable& rt, RowState<T> rs, int r0,
+                                              int nrows, int k, int nchk, int j) {
   __shared__ uint64_t nred[NWAVE][8];
   __shared__ uint64_t nfin[8];
   constexpr int NW = LLWords<T>::kWords;
@@ -268,41 +279,49 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, RowState<T> rs
   }
   __syncthreads();
 
-  bool nonfinite = false;
+  // one thread decides (every workgroup sees the same bits, so all decide alike) and the
+  // workgroup reads the decision back from LDS
+  __shared__ int decision[2];
+  if (tid == 0) {
+    bool nonfinite = false;
 #pragma unroll
-  for (int i = 0; i < 7; ++i) nonfinite |= nfin[i] >= kInfBits;
-  const double rp = bits_to_double(nfin[N_RP]), rd = bits_to_double(nfin[N_RD]);
-  const double nax = bits_to_double(nfin[N_AX]), nz = bits_to_double(nfin[N_Z]);
-  const double npx = bits_to_double(nfin[N_PX]), naty = bits_to_double(nfin[N_ATY]);
-  const double nq = bits_to_double(nfin[N_Q]);
-  const uint64_t flags = nfin[N_FLAGS];
-  __syncthreads();  // nfin and nred are reused by the next check
-  int st = ST_RUNNING;
-  if (nonfinite) {
-    st = ST_NONFINITE;
-  } else if (a.terminate) {
-    const double eps_p = a.eps_abs + a.eps_rel * fmax(nax, nz);
-    const double eps_d = a.eps_abs + a.eps_rel * fmax(fmax(npx, naty), nq);
-    if (rp <= eps_p && rd <= eps_d) st = ST_SOLVED;
+    for (int i = 0; i < 7; ++i) nonfinite |= nfin[i] >= kInfBits;
+    const double rp = bits_to_double(nfin[N_RP]), rd = bits_to_double(nfin[N_RD]);
+    const double nax = bits_to_double(nfin[N_AX]), nz = bits_to_double(nfin[N_Z]);
+    const double npx = bits_to_double(nfin[N_PX]), naty = bits_to_double(nfin[N_ATY]);
+    const double nq = bits_to_double(nfin[N_Q]);
+    const uint64_t flags = nfin[N_FLAGS];
+    int st = ST_RUNNING;
+    if (nonfinite) {
+      st = ST_NONFINITE;
+    } else if (a.terminate) {
+      const double eps_p = a.eps_abs + a.eps_rel * fmax(nax, nz);
+      const double eps_d = a.eps_abs + a.eps_rel * fmax(fmax(npx, naty), nq);
+      if (rp <= eps_p && rd <= eps_d) st = ST_SOLVED;
+    }
+    if (st == ST_RUNNING && k == a.max_iter) st = ST_MAX_ITER;
+    if (st == ST_RUNNING && flags >= 2) st = ST_INTERNAL;
+    if (st == ST_RUNNING && flags == 1) st = ST_ABORTED;
+    int jn = j;
+    if (st == ST_RUNNING && a.n_rho > 1 && rp > 0.0 && rd > 0.0) {
+      const double num = rp * fmax(fmax(npx, naty), fmax(nq, 1e-4));
+      const double den = rd * fmax(fmax(nax, nz), 1e-4);
+      const double rh = rt.grid[j] * sqrt(num / den);
+      jn = 0;
+      while (jn < a.n_rho - 1 && rh > rt.mid[jn]) ++jn;
+    }
+    if (g == 0) {
+      if (a.rho_hist) a.rho_hist[nchk] = jn;
+      if (a.prim_res) a.prim_res[nchk] = rp;
+      if (a.dual_res) a.dual_res[nchk] = rd;
+    }
+    decision[0] = st;
+    decision[1] = jn;
   }
-  if (st == ST_RUNNING && k == a.max_iter) st = ST_MAX_ITER;
-  if (st == ST_RUNNING && flags >= 2) st = ST_INTERNAL;
-  if (st == ST_RUNNING && flags == 1) st = ST_ABORTED;
-  int jn = j;
-  if (st == ST_RUNNING && a.n_rho > 1 && rp > 0.0 && rd > 0.0) {
-    const double num = rp * fmax(fmax(npx, naty), fmax(nq, 1e-4));
-    const double den = rd * fmax(fmax(nax, nz), 1e-4);
-    const double rh = a.grid[j] * sqrt(num / den);
-    jn = 0;
-    while (jn < a.n_rho - 1 && rh > a.mid[jn]) ++jn;
-  }
-  if (g == 0 && tid == 0) {
-    if (a.rho_hist) a.rho_hist[nchk] = jn;
-    if (a.prim_res) a.prim_res[nchk] = rp;
-    if (a.dual_res) a.dual_res[nchk] = rd;
-  }
-  out.status = st;
-  out.jn = jn;
+  __syncthreads();
+  out.status = decision[0];
+  out.jn = decision[1];
+  __syncthreads();  // nfin, nred and decision are reused by the next check
   return out;
 }
 
@@ -341,25 +360,31 @@ __device__ __forceinline__ void load_stationary(const LayerArgs& a, int j, int r
     }
 }
 
-// Rows NRS .. NRS + nlds - 1 of the block live in LDS for the whole solve, laid out
+// Rows NRS .. NRS + NLM - 1 of the block live in LDS for the whole solve, laid out
 // [row][k][lane] so that every lane reads and writes only its own words (no barrier needed,
-// no bank conflicts).
-template <typename T, int NC>
+// no bank conflicts). Rows past the end of the block are zero, so the row loops need no
+// per-row branches.
+template <typename T, int NC, int NLM>
 __device__ __forceinline__ void load_lds_rows(const LayerArgs& a, int j, int r0, int first, int nlds, T* wl) {
   const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
   const int tid = threadIdx.x;
-  for (int rr = 0; rr < nlds; ++rr)
+  for (int rr = 0; rr < NLM; ++rr)
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const int c = tid + BS * k;
-      wl[(rr * NC + k) * BS + tid] = (c < a.L) ? Wj[(long)(r0 + first + rr) * a.ldw + c] : (T)0;
+      wl[(rr * NC + k) * BS + tid] = (rr < nlds && c < a.L) ? Wj[(long)(r0 + first + rr) * a.ldw + c] : (T)0;
     }
 }
 
-template <typename T, int NC, int NRS>
+// NRS rows of each block in registers, NLM in LDS, the rest streamed. The loop between two
+// checks is kept free of everything the check needs, and the register rows are reloaded after
+// every check, so the check code does not compete with them for registers.
+template <typename T, int NC, int NRS, int NLM>
 __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   constexpr int NW = LLWords<T>::kWords;
   __shared__ T red[NWAVE][kMaxRows];
+  __shared__ int fail_flag;
+  __shared__ RhoTable rt;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   T* wl = reinterpret_cast<T*>(dyn_lds);
 
@@ -370,9 +395,15 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   const int nrows = rbase + (g < rextra ? 1 : 0);
   const int r0 = g * rbase + (g < rextra ? g : rextra);
   const int nstat = nrows < NRS ? nrows : NRS;
-  const int nlds = nrows - nstat < a.lds_rows ? nrows - nstat : a.lds_rows;
-  const int nres = nstat + nlds;  // rows held on chip; rows nres..nrows-1 stream from memory
-  const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
+  const int nlds = nrows - nstat < NLM ? nrows - nstat : NLM;
+  constexpr int nres = NRS + NLM;  // rows held on chip; rows nres..nrows-1 stream from memory
+  constexpr int RON = NRS + NLM;
+  const int my_row = rows_held<RON>();
+  const bool writer = row_writer<RON>();
+  if (tid == 0) fail_flag = 0;
+  if (tid < a.n_rho) rt.grid[tid] = a.grid[tid];
+  if (tid < a.n_rho - 1) rt.mid[tid] = a.mid[tid];
+  __syncthreads();
 
   // row-owner state
   RowState<T> rs;
@@ -395,13 +426,12 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
     }
   }
   int j = a.warm ? *a.js : a.j0;
-  T srho = (T)(a.grid[j] * (seq ? a.rho_eq_scale : 1.0));
-
-  T wst[NRS][NC];
-  load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
-  load_lds_rows<T, NC>(a, j, r0, NRS, nlds, wl);
+  T srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
+  load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
+  __syncthreads();  // fail_flag
 
   const uint32_t tag = a.tag;
+  const int ci = a.check_interval, max_iter = a.max_iter;
   int nchk = 0;
 
   // warm start: z = A x (Sec. II-B, warm starting)
@@ -421,97 +451,103 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
 
   // first layer input w_1
   {
+    const T sigma = (T)a.sigma;
     const T w1 = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
     if (rs.own) ll_store(a.xw + ((long)L + rs.R) * NW, w1, tag + 1u);
   }
 
-  for (int k = 1; k <= a.max_iter; ++k) {
-    // layer matvec: rows of Wc_j times w_k
-    T wv[NC];
-    const bool ok = gather<T, NC>(a.xw + (long)(k & 1) * L * NW, L, tag + (uint32_t)k, wv, a.err, tag);
-    if (__syncthreads_or(!ok)) {
+  int k = 0;
+  while (true) {
+    const int kend = (k / ci + 1) * ci < max_iter ? (k / ci + 1) * ci : max_iter;
+    {
+      T wst[NRS][NC];
+      load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+      const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
+      uint64_t* xw = a.xw;
+      while (k < kend) {
+        ++k;
+        // layer matvec: rows of Wc_j times w_k
+        T wv[NC];
+        const bool ok = gather<T, NC>(xw + (long)(k & 1) * L * NW, L, tag + (uint32_t)k, wv, a.err, tag);
+        if (!ok) fail_flag = 1;
+        // all rows on chip, no per-row branches (rows past the block have zero weights)
+        // all on-chip rows, then one multi-row wave reduction (rows past the block are zero)
+        T acc[RON];
+#pragma unroll
+        for (int rr = 0; rr < RON; ++rr) {
+          acc[rr] = 0;
+          if (rr < NRS) {
+#pragma unroll
+            for (int k2 = 0; k2 < NC; ++k2) acc[rr] = fma(wst[rr < NRS ? rr : 0][k2], wv[k2], acc[rr]);
+          } else {
+#pragma unroll
+            for (int k2 = 0; k2 < NC; ++k2) acc[rr] = fma(wl[((rr - NRS) * NC + k2) * BS + tid], wv[k2], acc[rr]);
+          }
+        }
+        const T rsum = reduce_rows<RON>(acc);
+        if (writer) red[wave][my_row] = rsum;
+        if (nrows > nres) {
+          const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
+          for (int rr = nres; rr < nrows; ++rr) {
+            T acc = 0;
+#pragma unroll
+            for (int k2 = 0; k2 < NC; ++k2) {
+              const int c = tid + BS * k2;
+              acc = fma(c < L ? Wj[(long)(r0 + rr) * a.ldw + c] : (T)0, wv[k2], acc);
+            }
+            acc = wave_sum_to_last(acc);
+            if (lane == kLastLane) red[wave][rr] = acc;
+          }
+        }
+        __syncthreads();
+        if (fail_flag) {
+          if (tid == 0) err_raise(a.err, tag);
+          finish<T>(a, rs, k, ST_INTERNAL, j);
+          return;
+        }
+
+        // row-local update: relaxation, clamp (eq. clamp), dual update
+        if (rs.own) {
+          T v = 0;
+#pragma unroll
+          for (int w = 0; w < NWAVE; ++w) v += red[w][tid];
+          if (rs.xrow) {
+            rs.sx = alpha * v + oma * rs.sx;
+          } else {
+            const T t = alpha * v + oma * rs.sz + rs.sy / srho;
+            const T zn = box_clamp(t, sl, su);
+            rs.sy = srho * (t - zn);
+            rs.sz = zn;
+          }
+          // No barrier after this: a wave passes the next gather only after every row of the
+          // block was published, and each owner publishes after it has read red[][].
+          if (k < kend) {
+            const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
+            ll_store(xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
+          }
+        }
+      }
+    }
+
+    // check at iteration k (every check_interval iterations and at max_iter)
+    __syncthreads();
+    const CheckOut co = run_check<T, NC>(a, rt, rs, r0, nrows, k, nchk, j);
+    ++nchk;
+    if (!co.ok) {
       if (tid == 0) err_raise(a.err, tag);
       finish<T>(a, rs, k, ST_INTERNAL, j);
       return;
     }
-#pragma unroll
-    for (int rr = 0; rr < NRS; ++rr) {
-      if (rr < nstat) {
-        T acc = 0;
-#pragma unroll
-        for (int k2 = 0; k2 < NC; ++k2) acc = fma(wst[rr][k2], wv[k2], acc);
-        acc = wave_sum_to_last(acc);
-        if (lane == kLastLane) red[wave][rr] = acc;
-      }
+    if (co.status != ST_RUNNING) {
+      finish<T>(a, rs, k, co.status, j);
+      return;
     }
-
-    for (int rr = 0; rr < nlds; ++rr) {
-      T acc = 0;
-#pragma unroll
-      for (int k2 = 0; k2 < NC; ++k2) acc = fma(wl[(rr * NC + k2) * BS + tid], wv[k2], acc);
-      acc = wave_sum_to_last(acc);
-      if (lane == kLastLane) red[wave][NRS + rr] = acc;
+    if (co.jn != j) {
+      j = co.jn;
+      srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
+      load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
     }
-    if (nrows > nres) {
-      const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
-      for (int rr = nres; rr < nrows; rr += RC) {
-        T wr[RC][NC];
-#pragma unroll
-        for (int b = 0; b < RC; ++b)
-#pragma unroll
-          for (int k2 = 0; k2 < NC; ++k2) {
-            const int c = tid + BS * k2;
-            wr[b][k2] = (rr + b < nrows && c < L) ? Wj[(long)(r0 + rr + b) * a.ldw + c] : (T)0;
-          }
-#pragma unroll
-        for (int b = 0; b < RC; ++b) {
-          T acc = 0;
-#pragma unroll
-          for (int k2 = 0; k2 < NC; ++k2) acc = fma(wr[b][k2], wv[k2], acc);
-          acc = wave_sum_to_last(acc);
-          if (lane == kLastLane && rr + b < nrows) red[wave][rr + b] = acc;
-        }
-      }
-    }
-    __syncthreads();
-
-    // row-local update: relaxation, clamp (eq. clamp), dual update
-    if (rs.own) {
-      T v = 0;
-      for (int w = 0; w < NWAVE; ++w) v += red[w][tid];
-      if (rs.xrow) {
-        rs.sx = alpha * v + oma * rs.sx;
-      } else {
-        const T t = alpha * v + oma * rs.sz + rs.sy / srho;
-        const T zn = box_clamp(t, sl, su);
-        rs.sy = srho * (t - zn);
-        rs.sz = zn;
-      }
-    }
-    // No barrier here: a wave can only pass the next gather after every row of this block
-    // was published, and each owner publishes after it has read red[][].
-
-    if ((k % a.check_interval == 0) || (k == a.max_iter)) {
-      const CheckOut co = run_check<T, NC>(a, rs, r0, nrows, k, nchk, j);
-      ++nchk;
-      if (!co.ok) {
-        if (tid == 0) err_raise(a.err, tag);
-        finish<T>(a, rs, k, ST_INTERNAL, j);
-        return;
-      }
-      if (co.status != ST_RUNNING) {
-        finish<T>(a, rs, k, co.status, j);
-        return;
-      }
-      if (co.jn != j) {
-        j = co.jn;
-        srho = (T)(a.grid[j] * (seq ? a.rho_eq_scale : 1.0));
-        load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
-        load_lds_rows<T, NC>(a, j, r0, NRS, nlds, wl);
-      }
-    }
-
-    // next layer input
+    const T sigma = (T)a.sigma;
     const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
     if (rs.own) ll_store(a.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
   }
@@ -522,29 +558,36 @@ constexpr int words() {
   return LLWords<T>::kWords;
 }
 
+// Register rows: 32 registers of weights per lane; as many LDS rows again, so that the on-chip
+// rows are a power of two (the multi-row reduction needs one) and at most 32 (accumulators).
 template <typename T, int NC>
-const void* pick_kernel() {
-  constexpr int nrs0 = 32 / (NC * words<T>());
-  constexpr int nrs = nrs0 > kMaxRows ? kMaxRows : nrs0;
-  return reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs>);
+constexpr int reg_rows() {
+  return 32 / (NC * words<T>()) > 16 / words<T>() ? 16 / words<T>() : 32 / (NC * words<T>());
+}
+template <typename T, int NC>
+constexpr int lds_rows_max() {
+  return reg_rows<T, NC>();
 }
 
 struct KernelChoice {
   const void* fn;
-  int nc, nrs;
+  int nc, nrs, nlm;
 };
+
+template <typename T, int NC>
+KernelChoice pick_kernel() {
+  constexpr int nrs = reg_rows<T, NC>();
+  constexpr int nlm = lds_rows_max<T, NC>();
+  return KernelChoice{reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs, nlm>), NC, nrs, nlm};
+}
 
 template <typename T>
 KernelChoice kernel_for(int L) {
-  auto mk = [](const void* f, int nc) {
-    int nrs0 = 32 / (nc * words<T>());
-    return KernelChoice{f, nc, nrs0 > kMaxRows ? kMaxRows : nrs0};
-  };
-  if (L <= BS) return mk(pick_kernel<T, 1>(), 1);
-  if (L <= 2 * BS) return mk(pick_kernel<T, 2>(), 2);
-  if (L <= 4 * BS) return mk(pick_kernel<T, 4>(), 4);
-  if (L <= 8 * BS) return mk(pick_kernel<T, 8>(), 8);
-  return KernelChoice{nullptr, 0, 0};
+  if (L <= BS) return pick_kernel<T, 1>();
+  if (L <= 2 * BS) return pick_kernel<T, 2>();
+  if (L <= 4 * BS) return pick_kernel<T, 4>();
+  if (L <= 8 * BS) return pick_kernel<T, 8>();
+  return KernelChoice{nullptr, 0, 0, 0};
 }
 
 }  // namespace
@@ -561,11 +604,9 @@ LaunchPlan plan_layer(int L, int grid) {
   hipFuncAttributes fa{};
   if (hipFuncGetAttributes(&fa, kc.fn) != hipSuccess) return p;
   const long row_bytes = (long)kc.nc * BS * sizeof(T);
-  const int rows_max = (L + grid - 1) / grid;  // rows of the largest block
-  const int want = rows_max > kc.nrs ? rows_max - kc.nrs : 0;
-  const long room = (long)smem_max - (long)fa.sharedSizeBytes - 256;
-  int lds_rows = room > 0 ? (int)(room / row_bytes) : 0;
-  if (lds_rows > want) lds_rows = want;
+  const long room = (long)smem_max - (long)fa.sharedSizeBytes;
+  const int lds_rows = kc.nlm;  // the kernel always keeps NLM rows (zeros past the block)
+  if ((long)lds_rows * row_bytes > room) return p;
   p.fn = kc.fn;
   p.lds_rows = lds_rows;
   p.dyn_bytes = (size_t)lds_rows * row_bytes;

@@ -11,7 +11,8 @@
 #include <string>
 #include <vector>
 
-#include "../../include/relu_qp.h"
+#include "relu_qp.h"
+#include "batch_kernel.h"
 #include "layer_kernel.h"
 #include "setup_kernels.h"
 
@@ -86,15 +87,38 @@ struct relu_qp_handle {
   double* E_d = nullptr;
   double* lo_d = nullptr;
   double* hi_d = nullptr;
-  double* qlu64 = nullptr;  // staging for update_device / update_x0 (n + 2m doubles)
+  // batched engine
+  bool batched = false;
+  int bprec = 0;
+  long ldk = 0;
+  void* bWa = nullptr;
+  void* bWb = nullptr;
+  void* bCa = nullptr;
+  void* bCb = nullptr;
+  float* bX = nullptr;
+  float* bZ = nullptr;
+  float* bY = nullptr;
+  void* bVa = nullptr;
+  void* bVb = nullptr;
+  void* bCVa = nullptr;
+  void* bCVb = nullptr;
+  int* bjb = nullptr;
+  unsigned long long* bnorms = nullptr;
+  int* blists = nullptr;
+  int* bmtiles = nullptr;
+  unsigned* bbar = nullptr;
+  rqp::BatchPlan bplan{};
 };
 
 namespace {
 
 void free_handle(relu_qp_handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->W, h->C, h->q, h->l, h->u, h->eq_d, h->grid_d, h->mid_d, h->xs, h->zs, h->ys, h->js, h->xw,
-                  h->xc, h->xn, h->err, h->F_d, h->E_d, h->lo_d, h->hi_d, h->qlu64};
+  void* ptrs[] = {h->W,    h->C,    h->q,    h->l,    h->u,     h->eq_d,   h->grid_d,  h->mid_d,
+                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,
+                  h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
+                  h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
+                  h->bnorms, h->blists, h->bmtiles, h->bbar};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->abort_h) (void)hipHostFree(h->abort_h);
@@ -114,8 +138,15 @@ int validate_settings(const relu_qp_settings* s) {
   if (!(s->eps_abs >= 0.0) || !(s->eps_rel >= 0.0)) return fail(RQP_EINVAL, "eps_abs and eps_rel must be >= 0");
   if (s->max_iter < 1 || s->max_iter > (1 << 28)) return fail(RQP_EINVAL, "max_iter must be in [1, 2^28]");
   if (s->check_interval < 1) return fail(RQP_EINVAL, "check_interval must be >= 1");
-  if (s->precision != RQP_FP64 && s->precision != RQP_FP32) return fail(RQP_EINVAL, "unknown precision");
-  if (s->batch != 1) return fail(RQP_EINVAL, "this build solves batch == 1 per handle");
+  if (s->precision != RQP_FP64 && s->precision != RQP_FP32 && s->precision != RQP_BF16X3)
+    return fail(RQP_EINVAL, "unknown precision");
+  if (s->batch < 1 || s->batch > (1 << 20)) return fail(RQP_EINVAL, "batch must be in [1, 2^20]");
+  if (s->engine < RQP_ENGINE_AUTO || s->engine > RQP_ENGINE_BATCH) return fail(RQP_EINVAL, "unknown engine");
+  const bool batched = s->engine == RQP_ENGINE_BATCH ||
+                       (s->engine == RQP_ENGINE_AUTO && (s->batch > 1 || s->precision == RQP_BF16X3));
+  if (batched && s->precision == RQP_FP64) return fail(RQP_EINVAL, "the batched engine runs FP32 or BF16X3");
+  if (!batched && s->precision == RQP_BF16X3) return fail(RQP_EINVAL, "BF16X3 needs the batched engine");
+  if (!batched && s->batch != 1) return fail(RQP_EINVAL, "the single-instance engine needs batch == 1");
   return RQP_OK;
 }
 
@@ -214,7 +245,8 @@ rqp::LaunchPlan make_plan(const relu_qp_handle* h, int grid) {
 // per workgroup.
 int set_grid(relu_qp_handle* h, int grid) {
   const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
-  if (grid < need || grid > h->L) return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, h->L);
+  const int top = h->L < 256 ? h->L : 256;  // the check gathers at most 8 * 256 norm partials
+  if (grid < need || grid > top) return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, top);
   rqp::LaunchPlan p = make_plan(h, grid);
   if (!p.fn) return fail(RQP_EHIP, "no kernel resources for n + m = %d", h->L);
   if (grid > p.max_grid) return fail(RQP_EINVAL, "grid %d exceeds the cooperative limit %d", grid, p.max_grid);
@@ -229,6 +261,7 @@ int choose_grid(relu_qp_handle* h) {
   HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
   int g = cus < h->L ? cus : h->L;
+  if (g > 256) g = 256;
   if (g < need) g = need;
   return set_grid(h, g);
 }
@@ -244,6 +277,161 @@ int alloc_exchange(relu_qp_handle* h) {
   HIP_OR_FAIL(hipMemset(h->xc, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xn, 0, h->xn_words * 8));
   h->tag = 1;
+  return RQP_OK;
+}
+
+
+bool is_batched(const relu_qp_settings& s) {
+  return s.engine == RQP_ENGINE_BATCH || (s.engine == RQP_ENGINE_AUTO && (s.batch > 1 || s.precision == RQP_BF16X3));
+}
+
+int upload_f32(float* dst, const double* src, size_t count) { return upload_vec<float>(dst, src, count); }
+
+// Layer and check matrices for the batched engine, FP32 or BF16 high/low, rows padded to ldk.
+int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hipStream_t st) {
+  const int n = h->n, m = h->m, L = h->L;
+  DevBuf P_d, A_d, Gw, K, DAt, ADAt, work, omega, info, Wd;
+  const size_t nn = (size_t)n * n, mn = (size_t)m * n, mm = (size_t)m * m, LL = (size_t)L * L;
+  if (P_d.alloc(nn * 8) || A_d.alloc(mn * 8) || Gw.alloc(nn * 8) || K.alloc(nn * 8) || DAt.alloc(mn * 8) ||
+      ADAt.alloc(mm * 8) || work.alloc((2 * 32 * (size_t)n + 32 * 32) * 8) || omega.alloc((size_t)m * 8) ||
+      info.alloc(sizeof(int)) || Wd.alloc(LL * 8))
+    return fail(RQP_ENOMEM, "setup workspace allocation failed (n=%d, m=%d)", n, m);
+  HIP_OR_FAIL(hipMemcpyAsync(P_d.p, P, nn * 8, hipMemcpyHostToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(A_d.p, A, mn * 8, hipMemcpyHostToDevice, st));
+  std::vector<double> om(m);
+  for (int i = 0; i < m; ++i) om[i] = h->eq[i] ? h->s.rho_eq_scale : 1.0;
+  HIP_OR_FAIL(hipMemcpyAsync(omega.p, om.data(), (size_t)m * 8, hipMemcpyHostToDevice, st));
+  HIP_OR_FAIL(hipMemsetAsync(info.p, 0, sizeof(int), st));
+  HIP_OR_FAIL(rqp::gemm_f64(n, n, m, 1.0, A_d.d(), 1, n, omega.d(), A_d.d(), n, 1, 0.0, Gw.d(), n, st));
+  const size_t es = h->bprec == rqp::kBatchBF16x3 ? 2 : 4;
+  for (size_t j = 0; j < h->grid.size(); ++j) {
+    HIP_OR_FAIL(rqp::kkt_form_f64(n, P_d.d(), Gw.d(), h->s.sigma, h->grid[j], K.d(), st));
+    HIP_OR_FAIL(rqp::spd_inverse_f64(n, K.d(), work.d(), static_cast<int*>(info.p), st));
+    HIP_OR_FAIL(rqp::gemm_f64(n, m, n, 1.0, K.d(), n, 1, nullptr, A_d.d(), 1, n, 0.0, DAt.d(), m, st));
+    HIP_OR_FAIL(rqp::gemm_f64(m, m, n, 1.0, A_d.d(), n, 1, nullptr, DAt.d(), m, 1, 0.0, ADAt.d(), m, st));
+    HIP_OR_FAIL(rqp::assemble_layer<double>(n, m, K.d(), DAt.d(), ADAt.d(), Wd.d(), L, st));
+    const size_t off = j * (size_t)h->w_stride * es;
+    if (h->bprec == rqp::kBatchBF16x3)
+      HIP_OR_FAIL(rqp::split_bf16(L, L, Wd.d(), L, static_cast<char*>(h->bWa) + off, static_cast<char*>(h->bWb) + off,
+                                  h->ldk, st));
+    else
+      HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, reinterpret_cast<float*>(static_cast<char*>(h->bWa) + off), h->ldk, st));
+  }
+  HIP_OR_FAIL(rqp::assemble_check<double>(n, m, P_d.d(), A_d.d(), Wd.d(), L, st));
+  if (h->bprec == rqp::kBatchBF16x3)
+    HIP_OR_FAIL(rqp::split_bf16(L, L, Wd.d(), L, h->bCa, h->bCb, h->ldk, st));
+  else
+    HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, static_cast<float*>(h->bCa), h->ldk, st));
+  int hinfo = 0;
+  HIP_OR_FAIL(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_OR_FAIL(hipStreamSynchronize(st));
+  if (hinfo) return fail(RQP_ENOTPD, "P + sigma I + A' diag(rho) A is not positive definite");
+  return RQP_OK;
+}
+
+int setup_batched(relu_qp_handle* h, const double* P, const double* q, const double* A, const double* l,
+                  const double* u, hipStream_t st) {
+  const int n = h->n, m = h->m, L = h->L, B = h->batch;
+  h->batched = true;
+  h->bprec = h->s.precision == RQP_BF16X3 ? rqp::kBatchBF16x3 : rqp::kBatchF32;
+  h->ldk = (L + rqp::kTileK - 1) / rqp::kTileK * rqp::kTileK;
+  h->w_stride = (long)L * h->ldk;
+  const size_t es = h->bprec == rqp::kBatchBF16x3 ? 2 : 4;
+  const size_t nr = h->grid.size();
+  const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->w_stride * es;
+  const size_t vbytes = (size_t)B * h->ldk * es;
+  const size_t ntile_max = (size_t)B / rqp::kTileM + nr + 1;
+  auto al = [](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 8) == hipSuccess; };
+  const bool two = h->bprec == rqp::kBatchBF16x3;
+  if (!al(&h->bWa, wbytes) || (two && !al(&h->bWb, wbytes)) || !al(&h->bCa, cbytes) || (two && !al(&h->bCb, cbytes)) ||
+      !al((void**)&h->bX, (size_t)B * n * 4) || !al((void**)&h->bZ, (size_t)B * m * 4) ||
+      !al((void**)&h->bY, (size_t)B * m * 4) || !al(&h->bVa, 2 * vbytes) || (two && !al(&h->bVb, 2 * vbytes)) ||
+      !al(&h->bCVa, vbytes) || (two && !al(&h->bCVb, vbytes)) || !al((void**)&h->bjb, (size_t)B * 4) ||
+      !al((void**)&h->bnorms, (size_t)B * 8 * 8) || !al((void**)&h->blists, (size_t)B * 4) ||
+      !al((void**)&h->bmtiles, (1 + 3 * ntile_max) * 4) || !al((void**)&h->bbar, 1024 * 4) ||
+      !al(&h->q, (size_t)B * n * 4) || !al(&h->l, (size_t)B * m * 4) || !al(&h->u, (size_t)B * m * 4)) {
+    (void)hipGetLastError();
+    return fail(RQP_ENOMEM, "device allocation failed (batch %d, n=%d, m=%d)", B, n, m);
+  }
+  // operand padding columns must read as zero
+  HIP_OR_FAIL(hipMemset(h->bVa, 0, 2 * vbytes));
+  if (two) HIP_OR_FAIL(hipMemset(h->bVb, 0, 2 * vbytes));
+  HIP_OR_FAIL(hipMemset(h->bCVa, 0, vbytes));
+  if (two) HIP_OR_FAIL(hipMemset(h->bCVb, 0, vbytes));
+  HIP_OR_FAIL(hipMemset(h->bnorms, 0, (size_t)B * 64));
+  std::vector<int> j0(B, h->j0);
+  HIP_OR_FAIL(hipMemcpy(h->bjb, j0.data(), (size_t)B * 4, hipMemcpyHostToDevice));
+  int rc;
+  if ((rc = upload_f32(static_cast<float*>(h->q), q, (size_t)B * n)) ||
+      (rc = upload_f32(static_cast<float*>(h->l), l, (size_t)B * m)) ||
+      (rc = upload_f32(static_cast<float*>(h->u), u, (size_t)B * m)))
+    return rc;
+  if ((rc = build_batch_weights(h, P, A, st))) return rc;
+  h->bplan = rqp::plan_batch(h->bprec);
+  if (!h->bplan.fn) return fail(RQP_EHIP, "no resources for the batched kernel");
+  return RQP_OK;
+}
+
+int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
+  const int B = h->batch;
+  HIP_OR_FAIL(hipMemsetAsync(h->bbar, 0, 1024 * 4, st));
+  __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
+  rqp::BatchArgs a{};
+  a.n = h->n;
+  a.m = h->m;
+  a.L = h->L;
+  a.B = B;
+  a.ldk = h->ldk;
+  a.prec = h->bprec;
+  a.Wa = h->bWa;
+  a.Wb = h->bWb;
+  a.w_stride = h->w_stride;
+  a.Ca = h->bCa;
+  a.Cb = h->bCb;
+  a.Q = static_cast<const float*>(h->q);
+  a.Lo = static_cast<const float*>(h->l);
+  a.Up = static_cast<const float*>(h->u);
+  a.eq = h->eq_d;
+  a.grid = h->grid_d;
+  a.mid = h->mid_d;
+  a.n_rho = (int)h->grid.size();
+  a.sigma = h->s.sigma;
+  a.alpha = h->s.alpha;
+  a.eps_abs = h->s.eps_abs;
+  a.eps_rel = h->s.eps_rel;
+  a.rho_eq_scale = h->s.rho_eq_scale;
+  a.max_iter = h->s.max_iter;
+  a.check_interval = h->s.check_interval;
+  a.terminate = !(h->s.eps_abs == 0.0 && h->s.eps_rel == 0.0);
+  a.warm = (h->warm_pending || (h->warm_mode && h->have_prev)) ? 1 : 0;
+  a.j0 = h->j0;
+  a.X = h->bX;
+  a.Z = h->bZ;
+  a.Y = h->bY;
+  a.Va = h->bVa;
+  a.Vb = h->bVb;
+  a.CVa = h->bCVa;
+  a.CVb = h->bCVb;
+  a.jb = h->bjb;
+  a.status = out->status;
+  a.iterations = out->iterations;
+  a.rho_hist = out->rho_hist;
+  a.prim_res = out->prim_res;
+  a.dual_res = out->dual_res;
+  a.max_checks = h->s.max_iter / h->s.check_interval + (h->s.max_iter % h->s.check_interval ? 1 : 0);
+  a.norms = h->bnorms;
+  a.lists = h->blists;
+  a.mtiles = h->bmtiles;
+  a.bar = h->bbar;
+  a.abort_flag = h->abort_d;
+  hipError_t e = rqp::launch_batch(a, h->bplan, st);
+  if (e != hipSuccess) return fail(RQP_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+  HIP_OR_FAIL(hipMemcpyAsync(out->x, h->bX, (size_t)B * h->n * 4, hipMemcpyDeviceToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(out->z, h->bZ, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(out->y, h->bY, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(out->rho_index, h->bjb, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  h->warm_pending = false;
+  h->have_prev = true;
   return RQP_OK;
 }
 
@@ -266,6 +454,7 @@ void relu_qp_default_settings(relu_qp_settings* s) {
   s->check_interval = 25;
   s->precision = RQP_FP32;
   s->batch = 1;
+  s->engine = RQP_ENGINE_AUTO;
 }
 
 const char* relu_qp_last_error(void) { return g_last_error.c_str(); }
@@ -290,15 +479,22 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
         return fail(RQP_EINVAL, "P is not symmetric (%d, %d)", i, k);
   for (long i = 0; i < (long)m * n; ++i)
     if (!std::isfinite(A[i])) return fail(RQP_EINVAL, "A has a non-finite entry");
-  rc = validate_bounds(m, l, u);
-  if (rc) return rc;
+  const bool batched = is_batched(*s);
+  const int B = s->batch;
+  for (int b = 0; b < B; ++b) {
+    rc = validate_bounds(m, l + (size_t)b * m, u + (size_t)b * m);
+    if (rc) return rc;
+    for (int i = 0; i < m; ++i)
+      if ((l[(size_t)b * m + i] == u[(size_t)b * m + i]) != (l[i] == u[i]))
+        return fail(RQP_EINVAL, "instance %d has another equality-row pattern (row %d)", b, i);
+  }
 
   relu_qp_handle* h = new relu_qp_handle();
   h->n = n;
   h->m = m;
   h->L = n + m;
   h->s = *s;
-  h->batch = s->batch;
+  h->batch = B;
   h->esize = s->precision == RQP_FP64 ? 8 : 4;
   h->ldw = (h->L + 3) / 4 * 4;  // 16-byte aligned rows
   h->w_stride = (long)h->L * h->ldw;
@@ -312,17 +508,10 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
     return code;
   };
   const size_t nr = h->grid.size();
-  if (hipMalloc(&h->W, nr * h->w_stride * h->esize) != hipSuccess ||
-      hipMalloc(&h->C, (size_t)h->w_stride * h->esize) != hipSuccess ||
-      hipMalloc(&h->q, (size_t)n * h->esize) != hipSuccess || hipMalloc(&h->l, (size_t)m * h->esize) != hipSuccess ||
-      hipMalloc(&h->u, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->eq_d, (size_t)m) != hipSuccess ||
-      hipMalloc(&h->grid_d, nr * 8) != hipSuccess || hipMalloc(&h->mid_d, h->mid.size() * 8) != hipSuccess ||
-      hipMalloc(&h->xs, (size_t)n * h->esize) != hipSuccess || hipMalloc(&h->zs, (size_t)m * h->esize) != hipSuccess ||
-      hipMalloc(&h->ys, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->js, sizeof(int)) != hipSuccess ||
-      hipMalloc(&h->err, sizeof(unsigned)) != hipSuccess ||
-      hipMalloc(&h->qlu64, ((size_t)n + 2 * m) * 8) != hipSuccess) {
+  if (hipMalloc(&h->eq_d, (size_t)m) != hipSuccess || hipMalloc(&h->grid_d, nr * 8) != hipSuccess ||
+      hipMalloc(&h->mid_d, h->mid.size() * 8) != hipSuccess) {
     (void)hipGetLastError();
-    return bail(fail(RQP_ENOMEM, "device allocation failed (n=%d, m=%d, %zu penalties)", n, m, nr));
+    return bail(fail(RQP_ENOMEM, "device allocation failed"));
   }
   if (hipHostMalloc(&h->abort_h, sizeof(int), hipHostMallocMapped) != hipSuccess) {
     (void)hipGetLastError();
@@ -331,12 +520,28 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
   *h->abort_h = 0;
   if (hipHostGetDevicePointer((void**)&h->abort_d, h->abort_h, 0) != hipSuccess)
     return bail(fail(RQP_EHIP, "hipHostGetDevicePointer failed"));
-
-  if ((rc = upload(h, h->q, q, n)) || (rc = upload(h, h->l, l, m)) || (rc = upload(h, h->u, u, m))) return bail(rc);
   if (hipMemcpy(h->eq_d, h->eq.data(), m, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->grid_d, h->grid.data(), nr * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(h->mid_d, h->mid.data(), h->mid.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(h->xs, 0, (size_t)n * h->esize) != hipSuccess || hipMemset(h->zs, 0, (size_t)m * h->esize) != hipSuccess ||
+      hipMemcpy(h->mid_d, h->mid.data(), h->mid.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(RQP_EHIP, "initial copies failed"));
+
+  if (batched) {
+    if ((rc = setup_batched(h, P, q, A, l, u, st))) return bail(rc);
+    *hp = h;
+    return RQP_OK;
+  }
+
+  if (hipMalloc(&h->W, nr * h->w_stride * h->esize) != hipSuccess ||
+      hipMalloc(&h->C, (size_t)h->w_stride * h->esize) != hipSuccess ||
+      hipMalloc(&h->q, (size_t)n * h->esize) != hipSuccess || hipMalloc(&h->l, (size_t)m * h->esize) != hipSuccess ||
+      hipMalloc(&h->u, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->xs, (size_t)n * h->esize) != hipSuccess ||
+      hipMalloc(&h->zs, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->ys, (size_t)m * h->esize) != hipSuccess ||
+      hipMalloc(&h->js, sizeof(int)) != hipSuccess || hipMalloc(&h->err, sizeof(unsigned)) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(RQP_ENOMEM, "device allocation failed (n=%d, m=%d, %zu penalties)", n, m, nr));
+  }
+  if ((rc = upload(h, h->q, q, n)) || (rc = upload(h, h->l, l, m)) || (rc = upload(h, h->u, u, m))) return bail(rc);
+  if (hipMemset(h->xs, 0, (size_t)n * h->esize) != hipSuccess || hipMemset(h->zs, 0, (size_t)m * h->esize) != hipSuccess ||
       hipMemset(h->ys, 0, (size_t)m * h->esize) != hipSuccess || hipMemset(h->js, 0, sizeof(int)) != hipSuccess ||
       hipMemset(h->err, 0, sizeof(unsigned)) != hipSuccess)
     return bail(fail(RQP_EHIP, "initial copies failed"));
@@ -350,6 +555,25 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
 
 int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const double* u) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (h->batched) {
+    const int B = h->batch, n = h->n, m = h->m;
+    if ((l == nullptr) != (u == nullptr)) return fail(RQP_EINVAL, "the batched engine updates l and u together");
+    if (l) {
+      for (int b = 0; b < B; ++b) {
+        int rc = validate_bounds(m, l + (size_t)b * m, u + (size_t)b * m);
+        if (rc) return rc;
+        for (int i = 0; i < m; ++i)
+          if ((l[(size_t)b * m + i] == u[(size_t)b * m + i]) != (h->eq[i] != 0))
+            return fail(RQP_EINVAL, "update changes the equality-row pattern (instance %d, row %d)", b, i);
+      }
+    }
+    int rc;
+    if (q && (rc = upload_f32(static_cast<float*>(h->q), q, (size_t)B * n))) return rc;
+    if (l && ((rc = upload_f32(static_cast<float*>(h->l), l, (size_t)B * m)) ||
+              (rc = upload_f32(static_cast<float*>(h->u), u, (size_t)B * m))))
+      return rc;
+    return RQP_OK;
+  }
   std::vector<double> lv, uv;
   if (l || u) {
     lv.resize(h->m);
@@ -390,9 +614,10 @@ int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const do
 int relu_qp_update_device(relu_qp_handle* h, const double* q, const double* l, const double* u, void* stream) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (q) HIP_OR_FAIL(cast_dev(h, h->n, q, h->q, st));
-  if (l) HIP_OR_FAIL(cast_dev(h, h->m, l, h->l, st));
-  if (u) HIP_OR_FAIL(cast_dev(h, h->m, u, h->u, st));
+  const long B = h->batch;
+  if (q) HIP_OR_FAIL(cast_dev(h, B * h->n, q, h->q, st));
+  if (l) HIP_OR_FAIL(cast_dev(h, B * h->m, l, h->l, st));
+  if (u) HIP_OR_FAIL(cast_dev(h, B * h->m, u, h->u, st));
   return RQP_OK;
 }
 
@@ -426,13 +651,14 @@ int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream) 
   if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
   if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  double* qd = h->qlu64;
-  double* ld = qd + h->n;
-  double* ud = ld + h->m;
-  HIP_OR_FAIL(rqp::mpc_vectors_f64(h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0, qd, ld, ud, st));
-  HIP_OR_FAIL(cast_dev(h, h->n, qd, h->q, st));
-  HIP_OR_FAIL(cast_dev(h, h->m, ld, h->l, st));
-  HIP_OR_FAIL(cast_dev(h, h->m, ud, h->u, st));
+  if (h->esize == 8)
+    HIP_OR_FAIL(rqp::mpc_vectors<double>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
+                                         static_cast<double*>(h->q), static_cast<double*>(h->l),
+                                         static_cast<double*>(h->u), st));
+  else
+    HIP_OR_FAIL(rqp::mpc_vectors<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
+                                        static_cast<float*>(h->q), static_cast<float*>(h->l),
+                                        static_cast<float*>(h->u), st));
   return RQP_OK;
 }
 
@@ -441,6 +667,14 @@ int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int 
   if (!x || !y) return fail(RQP_EINVAL, "x or y is NULL");
   if (rho_index < 0 || rho_index >= (int)h->grid.size()) return fail(RQP_EINVAL, "rho_index out of range");
   int rc;
+  if (h->batched) {
+    const int B = h->batch;
+    if ((rc = upload_f32(h->bX, x, (size_t)B * h->n)) || (rc = upload_f32(h->bY, y, (size_t)B * h->m))) return rc;
+    std::vector<int> jv(B, rho_index);
+    HIP_OR_FAIL(hipMemcpy(h->bjb, jv.data(), (size_t)B * 4, hipMemcpyHostToDevice));
+    h->warm_pending = true;
+    return RQP_OK;
+  }
   if ((rc = upload(h, h->xs, x, h->n)) || (rc = upload(h, h->ys, y, h->m))) return rc;
   HIP_OR_FAIL(hipMemcpy(h->js, &rho_index, sizeof(int), hipMemcpyHostToDevice));
   h->warm_pending = true;
@@ -458,6 +692,7 @@ int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
   if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
     return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (h->batched) return solve_batched(h, st, out);
   const uint32_t span = (uint32_t)h->s.max_iter + 2u;
   if ((uint64_t)h->tag + span >= 0xffffffffull) {
     // restart the tag sequence: clear every exchange word so no stale tag can match
@@ -541,13 +776,14 @@ int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid, int* n_rho) {
 
 int relu_qp_set_launch(relu_qp_handle* h, int grid) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (h->batched) return grid == 0 ? RQP_OK : fail(RQP_EINVAL, "the batched engine uses one workgroup per CU");
   return grid == 0 ? choose_grid(h) : set_grid(h, grid);
 }
 
 int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
-  if (grid) *grid = h->grid_wg;
-  if (block) *block = rqp::kLayerBlock;
+  if (grid) *grid = h->batched ? h->bplan.grid : h->grid_wg;
+  if (block) *block = h->batched ? rqp::kBatchBlock : rqp::kLayerBlock;
   return RQP_OK;
 }
 

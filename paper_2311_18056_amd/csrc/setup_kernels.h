@@ -30,10 +30,12 @@ hipError_t assemble_layer(int n, int m, const double* D, const double* DAt, cons
 template <typename T>
 hipError_t assemble_check(int n, int m, const double* P, const double* A, T* C, long ldw, hipStream_t st);
 
-// Parametric QP vectors of condensed MPC (Sec. IV): q = F x0, l = lo - E x0, u = hi - E x0,
-// F n x nx and E m x nx row-major, all FP64 on the device.
-hipError_t mpc_vectors_f64(int n, int m, int nx, const double* F, const double* E, const double* lo, const double* hi,
-                           const double* x0, double* q, double* l, double* u, hipStream_t st);
+// Parametric QP vectors of condensed MPC (Sec. IV) for B instances: q_b = F x0_b,
+// l_b = lo - E x0_b, u_b = hi - E x0_b; F n x nx and E m x nx row-major FP64 on the device,
+// x0 B x nx; accumulated in FP64 and written as T (q: B x n, l and u: B x m).
+template <typename T>
+hipError_t mpc_vectors(int B, int n, int m, int nx, const double* F, const double* E, const double* lo,
+                       const double* hi, const double* x0, T* q, T* l, T* u, hipStream_t st);
 
 // y = x cast to T (count elements).
 template <typename T>

@@ -274,27 +274,32 @@ __global__ void cast_kernel(long count, const double* __restrict__ x, T* __restr
   if (idx < count) y[idx] = (T)x[idx];
 }
 
-// One wave per output row: q rows first, then the m constraint rows.
-__global__ void __launch_bounds__(256) mpc_vectors_kernel(int n, int m, int nx, const double* __restrict__ F,
+// One wave per output row: q rows first, then the m constraint rows. Writes the vectors
+// straight in the iteration precision T.
+template <typename T>
+__global__ void __launch_bounds__(256) mpc_vectors_kernel(long B, int n, int m, int nx, const double* __restrict__ F,
                                                           const double* __restrict__ E, const double* __restrict__ lo,
                                                           const double* __restrict__ hi,
-                                                          const double* __restrict__ x0, double* __restrict__ q,
-                                                          double* __restrict__ l, double* __restrict__ u) {
-  const int row = blockIdx.x * 4 + threadIdx.x / 64;
+                                                          const double* __restrict__ x0, T* __restrict__ q,
+                                                          T* __restrict__ l, T* __restrict__ u) {
+  const long grow = (long)blockIdx.x * 4 + threadIdx.x / 64;  // instance * (n + m) + row
   const int lane = threadIdx.x % 64;
-  if (row >= n + m) return;
+  if (grow >= B * (n + m)) return;
+  const long b = grow / (n + m);
+  const int row = (int)(grow % (n + m));
   const double* a = row < n ? F + (long)row * nx : E + (long)(row - n) * nx;
+  const double* xb = x0 + b * nx;
   double s = 0.0;
-  for (int c = lane; c < nx; c += 64) s = fma(a[c], x0[c], s);
+  for (int c = lane; c < nx; c += 64) s = fma(a[c], xb[c], s);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) {
     if (row < n) {
-      q[row] = s;
+      q[b * n + row] = (T)s;
     } else {
       const int i = row - n;
-      l[i] = lo[i] - s;
-      u[i] = hi[i] - s;
+      l[b * m + i] = (T)(lo[i] - s);
+      u[b * m + i] = (T)(hi[i] - s);
     }
   }
 }
@@ -352,9 +357,12 @@ hipError_t assemble_check(int n, int m, const double* P, const double* A, T* C, 
   return hipGetLastError();
 }
 
-hipError_t mpc_vectors_f64(int n, int m, int nx, const double* F, const double* E, const double* lo, const double* hi,
-                           const double* x0, double* q, double* l, double* u, hipStream_t st) {
-  hipLaunchKernelGGL(mpc_vectors_kernel, dim3((n + m + 3) / 4), dim3(256), 0, st, n, m, nx, F, E, lo, hi, x0, q, l, u);
+template <typename T>
+hipError_t mpc_vectors(int B, int n, int m, int nx, const double* F, const double* E, const double* lo,
+                       const double* hi, const double* x0, T* q, T* l, T* u, hipStream_t st) {
+  const long rows = (long)B * (n + m);
+  hipLaunchKernelGGL(mpc_vectors_kernel<T>, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, (long)B, n, m, nx, F, E,
+                     lo, hi, x0, q, l, u);
   return hipGetLastError();
 }
 
@@ -371,6 +379,10 @@ template hipError_t assemble_layer<double>(int, int, const double*, const double
                                            hipStream_t);
 template hipError_t assemble_check<float>(int, int, const double*, const double*, float*, long, hipStream_t);
 template hipError_t assemble_check<double>(int, int, const double*, const double*, double*, long, hipStream_t);
+template hipError_t mpc_vectors<float>(int, int, int, int, const double*, const double*, const double*,
+                                       const double*, const double*, float*, float*, float*, hipStream_t);
+template hipError_t mpc_vectors<double>(int, int, int, int, const double*, const double*, const double*,
+                                        const double*, const double*, double*, double*, double*, hipStream_t);
 template hipError_t cast_from_f64<float>(long, const double*, float*, hipStream_t);
 template hipError_t cast_from_f64<double>(long, const double*, double*, hipStream_t);
 

@@ -13,7 +13,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import RQP_FP32, RQP_FP64, Result, Settings, check, lib
+from ._lib import (RQP_BF16X3, RQP_ENGINE_AUTO, RQP_ENGINE_BATCH, RQP_ENGINE_SINGLE, RQP_FP32, RQP_FP64, Result,
+                   Settings, check, lib)
 
 STATUS_NAMES = {0: "running", 1: "solved", 2: "max_iter", 3: "nonfinite", 4: "aborted", 5: "internal"}
 
@@ -40,7 +41,9 @@ def default_settings(**overrides) -> Settings:
     lib().relu_qp_default_settings(byref(s))
     for k, v in overrides.items():
         if k == "precision" and isinstance(v, str):
-            v = {"fp64": RQP_FP64, "fp32": RQP_FP32}[v]
+            v = {"fp64": RQP_FP64, "fp32": RQP_FP32, "bf16x3": RQP_BF16X3}[v]
+        if k == "engine" and isinstance(v, str):
+            v = {"auto": RQP_ENGINE_AUTO, "single": RQP_ENGINE_SINGLE, "batch": RQP_ENGINE_BATCH}[v]
         if not hasattr(s, k):
             raise AttributeError(k)
         setattr(s, k, v)
@@ -54,34 +57,43 @@ class Solver:
     """
 
     def __init__(self, P, q, A, l, u, *, device="cuda:0", stream=None, **settings):
+        """q: (n,) or (batch, n); l, u: (m,) or (batch, m). ``batch`` defaults to the leading
+        dimension of q."""
         L = lib()
         P = _f64(P)
         n = P.shape[0]
         A = _f64(A)
         m = A.shape[0]
-        q, l, u = _f64(q, (n,)), _f64(l, (m,)), _f64(u, (m,))
+        q = _f64(q)
+        batch = 1 if q.ndim == 1 else q.shape[0]
+        settings.setdefault("batch", batch)
+        if settings["batch"] != batch:
+            raise ValueError("batch must match the leading dimension of q")
+        q = _f64(q, (n,) if batch == 1 and q.ndim == 1 else (batch, n))
+        l = _f64(l, (m,) if batch == 1 and np.ndim(l) == 1 else (batch, m))
+        u = _f64(u, (m,) if batch == 1 and np.ndim(u) == 1 else (batch, m))
         if P.shape != (n, n) or A.shape != (m, n):
             raise ValueError("P must be n x n and A m x n")
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         self.settings = default_settings(**settings)
-        self.n, self.m = n, m
-        self.fp64 = self.settings.precision == RQP_FP64
-        self.dtype = torch.float64 if self.fp64 else torch.float32
+        self.n, self.m, self.batch = n, m, batch
         self._h = c_void_p()
         check(L.relu_qp_setup(byref(self._h), n, m, _ptr(P), _ptr(q), _ptr(A), _ptr(l), _ptr(u),
                               byref(self.settings), _stream_handle(stream)))
         self.max_checks = check(L.relu_qp_max_checks(self._h))
-        dev = self.device
-        self.x = torch.zeros(n, dtype=self.dtype, device=dev)
-        self.y = torch.zeros(m, dtype=self.dtype, device=dev)
-        self.z = torch.zeros(m, dtype=self.dtype, device=dev)
-        self.iterations = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.rho_index = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.rho_hist = torch.full((self.max_checks,), -1, dtype=torch.int32, device=dev)
-        self.prim_res = torch.zeros(self.max_checks, dtype=torch.float64, device=dev)
-        self.dual_res = torch.zeros(self.max_checks, dtype=torch.float64, device=dev)
+        self.fp64 = self.settings.precision == RQP_FP64
+        self.dtype = torch.float64 if self.fp64 else torch.float32
+        dev, B = self.device, batch
+        self.x = torch.zeros(B, n, dtype=self.dtype, device=dev)
+        self.y = torch.zeros(B, m, dtype=self.dtype, device=dev)
+        self.z = torch.zeros(B, m, dtype=self.dtype, device=dev)
+        self.iterations = torch.zeros(B, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(B, dtype=torch.int32, device=dev)
+        self.rho_index = torch.zeros(B, dtype=torch.int32, device=dev)
+        self.rho_hist = torch.full((B, self.max_checks), -1, dtype=torch.int32, device=dev)
+        self.prim_res = torch.zeros(B, self.max_checks, dtype=torch.float64, device=dev)
+        self.dual_res = torch.zeros(B, self.max_checks, dtype=torch.float64, device=dev)
         self._res = Result(
             self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(), self.iterations.data_ptr(),
             self.status.data_ptr(), self.rho_index.data_ptr(), self.rho_hist.data_ptr(),
@@ -90,8 +102,8 @@ class Solver:
 
     # ------------------------------------------------------------------ online stage
     def update(self, q=None, l=None, u=None):
-        n, m = self.n, self.m
-        args = [None if v is None else _f64(v, s) for v, s in ((q, (n,)), (l, (m,)), (u, (m,)))]
+        n, m, B = self.n, self.m, self.batch
+        args = [None if v is None else _f64(v).reshape(B * s) for v, s in ((q, n), (l, m), (u, m))]
         self._keep = args
         check(lib().relu_qp_update(self._h, *[None if a is None else _ptr(a) for a in args]))
 
@@ -119,7 +131,7 @@ class Solver:
         check(lib().relu_qp_update_x0_device(self._h, c_void_p(x0.data_ptr()), _stream_handle(stream)))
 
     def warm_start(self, x, y, rho_index: int):
-        x, y = _f64(x, (self.n,)), _f64(y, (self.m,))
+        x, y = _f64(x).reshape(self.batch * self.n), _f64(y).reshape(self.batch * self.m)
         check(lib().relu_qp_warm_start(self._h, _ptr(x), _ptr(y), int(rho_index)))
 
     def set_warm(self, enabled: bool):
@@ -169,21 +181,30 @@ class Solver:
         check(lib().relu_qp_get_rho_grid(self._h, _ptr(g), byref(k)))
         return g
 
-    def result(self) -> dict:
-        """Synchronise and copy the last solve's outputs to the host."""
+    def result(self, index: int | None = None) -> dict:
+        """Synchronise and copy outputs to the host: instance ``index`` (default: 0 for a single
+        instance, all instances as arrays otherwise)."""
         torch.cuda.synchronize(self.device)
-        it = int(self.iterations.item())
+        if index is None and self.batch > 1:
+            return dict(
+                x=self.x.double().cpu().numpy(), y=self.y.double().cpu().numpy(), z=self.z.double().cpu().numpy(),
+                iterations=self.iterations.cpu().numpy(), status=self.status.cpu().numpy(),
+                rho_index=self.rho_index.cpu().numpy(), rho_hist=self.rho_hist.cpu().numpy(),
+                prim_res=self.prim_res.cpu().numpy(), dual_res=self.dual_res.cpu().numpy(),
+            )
+        b = 0 if index is None else int(index)
+        it = int(self.iterations[b].item())
         nck = min(self.max_checks, -(-it // self.settings.check_interval)) if it > 0 else 0
         return dict(
-            x=self.x.double().cpu().numpy(),
-            y=self.y.double().cpu().numpy(),
-            z=self.z.double().cpu().numpy(),
+            x=self.x[b].double().cpu().numpy(),
+            y=self.y[b].double().cpu().numpy(),
+            z=self.z[b].double().cpu().numpy(),
             iterations=it,
-            status=int(self.status.item()),
-            rho_index=int(self.rho_index.item()),
-            rho_hist=self.rho_hist[:nck].cpu().numpy().tolist(),
-            prim_res=self.prim_res[:nck].cpu().numpy(),
-            dual_res=self.dual_res[:nck].cpu().numpy(),
+            status=int(self.status[b].item()),
+            rho_index=int(self.rho_index[b].item()),
+            rho_hist=self.rho_hist[b, :nck].cpu().numpy().tolist(),
+            prim_res=self.prim_res[b, :nck].cpu().numpy(),
+            dual_res=self.dual_res[b, :nck].cpu().numpy(),
         )
 
     def close(self):

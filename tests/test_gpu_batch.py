@@ -1,0 +1,174 @@
+"""GPU parity of the batched engine (many instances sharing P and A, one persistent launch).
+
+FP32 matrix-core products: per vector ||gpu - oracle||_inf <= 1e-4 * max(||oracle||_inf, 1) over
+fixed iteration counts with each instance's penalty schedule replayed in the FP64 oracle.
+BF16 x3 products: the error against the FP64 oracle is measured and bounded (printed), and
+the final solutions pass the FP64 residual test.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import admm
+from oracle.mpc_update import qp_vectors
+from workloads import make_config, random_qp, x0_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2311_18056_amd as rq
+
+    rq.lib()
+    return rq
+
+
+def _os(**kw):
+    s = admm.Settings()
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1.0)
+
+
+def _batch_inputs(prob, B, seed, scale):
+    x0 = x0_batch(prob.nx, B, seed, scale=scale)
+    q, l, u = prob.instance(x0)
+    return x0, q, l, u
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 5e-3)])
+def test_batch_fixed_iterations_replayed(rq, prec, tol):
+    prob = make_config("c0")
+    B = 5
+    _, q, l, u = _batch_inputs(prob, B, 2000, 5.0)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0,
+                    max_iter=150)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    worst = 0.0
+    for b in range(B):
+        hist = res["rho_hist"][b][: 6].tolist()
+        ref = oracle.solve(prob.P, q[b], prob.A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=150),
+                           rho_replay=hist)
+        assert res["status"][b] == rq.RQP_MAX_ITER and res["iterations"][b] == 150
+        for name in ("x", "z", "y"):
+            e = _rel(res[name][b], getattr(ref, name))
+            worst = max(worst, e)
+            assert e <= tol, f"{prec} instance {b} {name}: {e:.3e}"
+    print(f"\n{prec}: worst per-vector relative error vs FP64 oracle after 150 iterations = {worst:.3e}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_several_tiles(rq, prec):
+    """300 instances (three instance tiles) of a QP with n + m = 230 (two row tiles) and equality
+    rows, 60 iterations, every instance against the oracle with its schedule replayed."""
+    P, q0, A, l0, u0 = random_qp(150, 20, 60, seed=21)
+    B = 300
+    rng = np.random.default_rng(5)
+    q = q0[None, :] + 0.3 * rng.standard_normal((B, 150))
+    l = np.repeat(l0[None, :], B, axis=0)
+    u = np.repeat(u0[None, :], B, axis=0)
+    sol = rq.Solver(P, q, A, l, u, precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    tol = 1e-4 if prec == "fp32" else 5e-3
+    for b in list(range(0, B, 37)) + [B - 1]:
+        ref = oracle.solve(P, q[b], A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60),
+                           rho_replay=res["rho_hist"][b][:3].tolist())
+        for name in ("x", "z", "y"):
+            assert _rel(res[name][b], getattr(ref, name)) <= tol, (prec, b, name)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_alone_equals_in_the_mix(rq, prec):
+    """An instance gives bit-identical results solved alone and inside a batch."""
+    prob = make_config("c0")
+    _, q, l, u = _batch_inputs(prob, 7, 2001, 5.0)
+    kw = dict(precision=prec, engine="batch", n_rho=8)
+    mix = rq.Solver(prob.P, q, prob.A, l, u, **kw)
+    mix.solve()
+    rm = mix.result()
+    mix.close()
+    for b in (0, 3, 6):
+        one = rq.Solver(prob.P, q[b:b + 1], prob.A, l[b:b + 1], u[b:b + 1], **kw)
+        one.solve()
+        r1 = one.result(0)
+        one.close()
+        assert r1["iterations"] == rm["iterations"][b] and r1["status"] == rm["status"][b]
+        for name in ("x", "z", "y"):
+            assert np.array_equal(r1[name], rm[name][b]), (prec, b, name)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_batch_solves_to_tolerance(rq, prec):
+    prob = make_config("c0")
+    B = 64
+    _, q, l, u = _batch_inputs(prob, B, 2002, 5.0)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision=prec, engine="batch", n_rho=8)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    assert np.all(res["status"] == rq.RQP_SOLVED)
+    errs = []
+    for b in range(0, B, 9):
+        nm = admm.residual_norms(prob.P, q[b], prob.A, res["x"][b], res["z"][b], res["y"][b])
+        assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
+        assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+        xs = oracle.solve(prob.P, q[b], prob.A, l[b], u[b], _os(eps_abs=1e-10, eps_rel=1e-10, n_rho=8,
+                                                                max_iter=40000)).x
+        errs.append(_rel(res["x"][b], xs))
+    print(f"\n{prec}: solution error |x - x*|/max(|x*|,1) at eps=1e-3: max {max(errs):.3e}")
+    assert max(errs) < 5e-2
+
+
+def test_batch_parametric_update_and_warm_start(rq):
+    import torch
+
+    prob = make_config("c0")
+    B = 9
+    x0, q, l, u = _batch_inputs(prob, B, 2003, 5.0)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp32", engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0,
+                    max_iter=50)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    x0b = 5.0 * x0_batch(prob.nx, B, 2004)
+    sol.update_x0_device(torch.tensor(x0b, dtype=torch.float64, device="cuda"))
+    sol.solve()
+    res = sol.result()
+    for b in (0, 4, 8):
+        q2, l2, u2 = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, x0b[b])
+        ref = oracle.solve(prob.P, q2, prob.A, l2, u2, _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=50),
+                           rho_replay=res["rho_hist"][b][:2].tolist())
+        for name in ("x", "z", "y"):
+            assert _rel(res[name][b], getattr(ref, name)) <= 1e-4
+    # warm start from the previous state: z = A x, penalty kept
+    sol.warm_start(res["x"], res["y"], 4)
+    sol.solve()
+    r2 = sol.result()
+    b = 2
+    q2, l2, u2 = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, x0b[b])
+    ref = oracle.solve(prob.P, q2, prob.A, l2, u2, _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=50),
+                       warm=(res["x"][b], res["y"][b], 4), rho_replay=r2["rho_hist"][b][:2].tolist())
+    for name in ("x", "z", "y"):
+        assert _rel(r2[name][b], getattr(ref, name)) <= 1e-4
+    sol.close()
+
+
+def test_batch_nonfinite_instance_is_isolated(rq):
+    prob = make_config("c0")
+    _, q, l, u = _batch_inputs(prob, 4, 2005, 5.0)
+    q = q.copy()
+    q[1, 2] = np.nan
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp32", engine="batch", n_rho=8)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    assert res["status"][1] == rq.RQP_NONFINITE and res["iterations"][1] == 25
+    assert all(res["status"][b] == rq.RQP_SOLVED for b in (0, 2, 3))
