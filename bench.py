@@ -32,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3}  # dense bf16 / fp32 matrix-core peaks
 
 
 def parse():
@@ -43,6 +44,15 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
+    ap.add_argument("--workload", choices=["c1", "batch", "serve"], default="c1",
+                    help="c1: one instance per solve (the headline); batch: 4096 instances of the same "
+                         "family per solve on the matrix cores; serve: continuous batching of MPC requests")
+    ap.add_argument("--precision", choices=["bf16x3", "fp32"], default="bf16x3", help="batched engine precision")
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--rates", default="100,300,1000,3000,10000,20000", help="serve: request rates per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals per rate")
+    ap.add_argument("--slots", type=int, default=256, help="serve: slots per family")
+    ap.add_argument("--families", default="f200,f800,f1600,f3200")
     return ap.parse_args()
 
 
@@ -86,6 +96,10 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import torch
 
@@ -208,13 +222,180 @@ def main():
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "layer_kernel<float,4,8>",
+            "kernel": "layer_kernel<float,4,8,8>",
             "alg_bytes_per_unit": bytes_per_unit,
             "avg_launch_us": float(np.mean(kern_ms) * 1e3),
         },
         "cpu_baseline": cpu,
     }
     sol.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """B instances of the configuration-1 family (same P and A, x0 per instance) per solve on
+    the batched matrix-core engine. One step = device update of every instance's q, l, u plus
+    one persistent solve of all of them to eps = 1e-3."""
+    import torch
+
+    import paper_2311_18056_amd as rq
+    from workloads import make_config, x0_batch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = make_config("c1")
+    n, m, nx, B = prob.n, prob.m, prob.nx, args.batch
+    steps, warmup = args.steps, args.warmup
+    total = steps + warmup
+    # instance i of step s: x0 from seed 3_000_000 + s (B rows)
+    x0_host = np.stack([x0_batch(nx, B, 3_000_000 + s, scale=args.x0_scale) for s in range(total)])
+    q0, l0, u0 = prob.instance(x0_host[0])
+    settings = dict(precision=args.precision, engine="batch", n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3,
+                    eps_rel=1e-3, max_iter=4000, check_interval=25)
+    t_setup = time.perf_counter()
+    sol = rq.Solver(prob.P, q0, prob.A, l0, u0, **settings)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t_setup) * 1e3
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    x0_dev = torch.tensor(x0_host, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(total)]
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(total)]
+    its, sts = [], []
+
+    def step(i):
+        sol.update_x0_device(x0_dev[i], stream)
+        ev1[i].record(stream)
+        sol.solve(stream)
+        ev2[i].record(stream)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, total):
+        step(i)
+        # results are overwritten by the next solve: keep counts on the device stream
+        its.append(sol.iterations.clone())
+        sts.append(sol.status.clone())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    it = torch.stack(its).cpu().numpy().astype(np.int64)
+    st = torch.stack(sts).cpu().numpy()
+    kern_ms = np.array([ev1[i].elapsed_time(ev2[i]) for i in range(warmup, total)])
+    checks = -(-it // 25)
+    flops_per_unit = 2.0 * (n * n + 2 * m * n)  # useful flops per instance-iteration
+    alg_flops = float(np.sum((it + checks) * flops_per_unit))
+    achieved = alg_flops / (np.sum(kern_ms) * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[args.precision]
+
+    steady = None
+    if args.steady_iters > 0:
+        k = min(args.steady_iters, 200)
+        fx = rq.Solver(prob.P, q0, prob.A, l0, u0, **dict(settings, eps_abs=0.0, eps_rel=0.0, max_iter=k))
+        fx.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+        fx.update_x0_device(x0_dev[0], stream)
+        fx.solve(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fx.solve(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        nck = -(-k // 25)
+        steady = {"iterations": k, "ms": ms, "us_per_iter": ms * 1e3 / k,
+                  "useful_TFLOPs": B * (k + nck) * flops_per_unit / (ms * 1e-3) / 1e12}
+        fx.close()
+
+    out = {
+        "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
+        "value": B * steps / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3" if args.precision == "bf16x3" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{B} instances per solve of the n=1600, m=1600 MPC family (nx=120, nu=40, N=40), "
+                        "batched matrix-core engine",
+            "x0": f"{args.x0_scale:g} * U[-1,1]^120, seed 3000000 + step",
+            "penalties": "8 log-spaced 1e-3..1e3",
+            "eps": 1e-3,
+        },
+        "admm_iters_per_s": float(np.sum(it)) / wall,
+        "iters_per_solve": float(np.mean(it)),
+        "status_counts": {rq.STATUS_NAMES[int(s)]: int(np.sum(st == s)) for s in np.unique(st)},
+        "setup_ms": setup_ms,
+        "steady_state": steady,
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "kernel": f"batch_kernel<{1 if args.precision == 'bf16x3' else 0}>",
+            "alg_flops_per_unit": flops_per_unit,
+            "avg_launch_us": float(np.mean(kern_ms) * 1e3),
+        },
+        "cpu_baseline": None,
+    }
+    sol.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Open-loop Poisson requests over four MPC families, served by continuous batching vs one
+    at a time on the single-instance engine; p50/p99 latency per offered rate."""
+    import torch
+
+    from paper_2311_18056_amd import Solver
+    from paper_2311_18056_amd.serving import Family, Server, latency_summary, poisson_requests, serve_plain
+    from workloads import make_config
+
+    torch.cuda.set_device(0)
+    probs = [make_config(f) for f in args.families.split(",")]
+    gens = [lambda rng, p=p: args.x0_scale * rng.uniform(-1.0, 1.0, p.nx) for p in probs]
+    settings = dict(n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000, check_interval=25)
+    fams = [Family.from_mpc(p, slots=args.slots, precision=args.precision, **settings) for p in probs]
+    singles = []
+    for p in probs:
+        q, l, u = p.instance(np.zeros(p.nx))
+        s = Solver(p.P, q, p.A, l, u, precision="fp32", **settings)
+        s.set_parametric(p.F, p.E, p.lo, p.hi)
+        singles.append(s)
+    rows = []
+    for i, rate in enumerate(float(r) for r in args.rates.split(",")):
+        count = int(min(20000, rate * args.duration))
+        reqs = poisson_requests(rate, count, args.duration, gens, seed=4 + i)
+        for f in fams:
+            f.pin = None
+        Server(fams, n_checks=1, warm=True).run(reqs, time_limit=args.duration * 3)
+        served = latency_summary(reqs, warmup=1.0)
+        reqs = poisson_requests(rate, count, args.duration, gens, seed=4 + i)
+        serve_plain(singles, reqs, time_limit=args.duration * 3)
+        plain = latency_summary(reqs, warmup=1.0)
+        rows.append({"rate": rate, "served": served, "plain": plain})
+        print(json.dumps(rows[-1]), flush=True)
+    out = {
+        "metric": "p50/p99 solve latency, served vs plain",
+        "unit": "ms",
+        "n_gpus": 1,
+        "data": "synthetic",
+        "config": {"workload": "MPC families " + args.families + ", Poisson arrivals, family uniform",
+                   "slots_per_family": args.slots, "precision": args.precision, "x0_scale": args.x0_scale},
+        "rates": rows,
+    }
+    for f in fams:
+        f.solver.close()
+    for s in singles:
+        s.close()
     print(json.dumps(out), flush=True)
 
 

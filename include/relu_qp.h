@@ -48,7 +48,8 @@ enum {
   RQP_MAX_ITER = 2,  /* max_iter reached (also for infeasible problems: no detection) */
   RQP_NONFINITE = 3, /* a residual norm was NaN or infinite */
   RQP_ABORTED = 4,   /* relu_qp_abort() was seen at a check */
-  RQP_INTERNAL = 5   /* the in-kernel exchange timed out (a library fault, never expected) */
+  RQP_INTERNAL = 5,  /* the in-kernel exchange timed out (a library fault, never expected) */
+  RQP_IDLE = 6       /* serving: the slot holds no instance */
 };
 
 /* arithmetic of the online iteration */
@@ -145,6 +146,38 @@ int relu_qp_set_warm(relu_qp_handle* h, int enabled);
  * every iteration, check and penalty switch. Results go to out (caller-owned device buffers);
  * read them after a stream synchronisation. */
 int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out);
+
+/* ---- Serving (continuous batching; batched engine only).
+ * The handle's `batch` instances are slots. A slot holds one request from its admission until
+ * a final status; finished and idle slots cost nothing in a step. Warm starts follow the
+ * receding-horizon use of Sec. II-B / V-B: the last solution of the same QP family, shifted
+ * by one stage. All four calls are asynchronous on stream; `slots` is a HOST array of
+ * n_slots distinct indices in [0, batch). */
+
+/* q, l, u of the listed slots from DEVICE FP64 rows (n_slots*n, n_slots*m); NULL keeps a
+ * vector. No validation of l <= u. */
+int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const double* q, const double* l,
+                       const double* u, void* stream);
+
+/* q, l, u of the listed slots from initial states x0 (DEVICE FP64, n_slots*nx) with the
+ * parametric data of relu_qp_set_parametric (Sec. IV). */
+int relu_qp_load_slots_x0(relu_qp_handle* h, const int* slots, int n_slots, const double* x0, void* stream);
+
+/* The listed slots start at the next relu_qp_step: cold (src_slot == -1: x = z = y = 0 and the
+ * start penalty), or warm from the current x and y of slot src_slot shifted forward by
+ * shift_x and shift_y entries (entries shifted in from beyond the end are 0; the stage-major
+ * layout of Sec. IV makes one stage nu entries), with its penalty index and z = A x. The
+ * source is read before any listed slot is written, so it may be one of them. */
+int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot, int shift_x, int shift_y,
+                  void* stream);
+
+/* One persistent launch of at most n_checks * check_interval iterations for every running or
+ * admitted slot. Slots stop at checks exactly as in relu_qp_solve; iterations count from
+ * admission, so a slot reaches max_iter across several steps. Afterwards every slot's x, y, z,
+ * status (RQP_RUNNING while unfinished), iterations and rho_index are in out; rho_hist,
+ * prim_res and dual_res entries are written at index (check number since admission).
+ * Needs max_iter % check_interval == 0 (RQP_EINVAL otherwise). */
+int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* out);
 
 /* Ask a running solve to stop at its next check with status RQP_ABORTED (any thread). */
 int relu_qp_abort(relu_qp_handle* h);

@@ -9,8 +9,10 @@ import torch  # noqa: F401  (loads the process's HIP runtime before the library)
 
 from ._lib import (  # noqa: F401
     RQP_ABORTED,
+    RQP_BF16X3,
     RQP_FP32,
     RQP_FP64,
+    RQP_IDLE,
     RQP_INTERNAL,
     RQP_MAX_ITER,
     RQP_NONFINITE,

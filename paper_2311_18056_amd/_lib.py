@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librelu_qp.so")
 
 RQP_OK, RQP_EINVAL, RQP_ENOMEM, RQP_EHIP, RQP_ENOTPD, RQP_ESTATE = 0, -1, -2, -3, -4, -5
-RQP_RUNNING, RQP_SOLVED, RQP_MAX_ITER, RQP_NONFINITE, RQP_ABORTED, RQP_INTERNAL = 0, 1, 2, 3, 4, 5
+RQP_RUNNING, RQP_SOLVED, RQP_MAX_ITER, RQP_NONFINITE, RQP_ABORTED, RQP_INTERNAL, RQP_IDLE = 0, 1, 2, 3, 4, 5, 6
 RQP_FP64, RQP_FP32, RQP_BF16X3 = 0, 1, 2
 RQP_ENGINE_AUTO, RQP_ENGINE_SINGLE, RQP_ENGINE_BATCH = 0, 1, 2
 
@@ -37,6 +37,10 @@ EXPORTS = [
     "relu_qp_warm_start",
     "relu_qp_set_warm",
     "relu_qp_solve",
+    "relu_qp_load_slots",
+    "relu_qp_load_slots_x0",
+    "relu_qp_admit",
+    "relu_qp_step",
     "relu_qp_abort",
     "relu_qp_max_checks",
     "relu_qp_get_rho_grid",
@@ -109,6 +113,11 @@ def lib():
     L.relu_qp_warm_start.argtypes = [h, _dp, _dp, c_int]
     L.relu_qp_set_warm.argtypes = [h, c_int]
     L.relu_qp_solve.argtypes = [h, c_void_p, POINTER(Result)]
+    _ip = POINTER(c_int)
+    L.relu_qp_load_slots.argtypes = [h, _ip, c_int, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.relu_qp_load_slots_x0.argtypes = [h, _ip, c_int, c_void_p, c_void_p]
+    L.relu_qp_admit.argtypes = [h, _ip, c_int, c_int, c_int, c_int, c_void_p]
+    L.relu_qp_step.argtypes = [h, c_int, c_void_p, POINTER(Result)]
     L.relu_qp_abort.argtypes = [h]
     L.relu_qp_max_checks.argtypes = [h]
     L.relu_qp_get_rho_grid.argtypes = [h, _dp, POINTER(c_int)]

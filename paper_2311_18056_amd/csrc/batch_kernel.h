@@ -9,6 +9,18 @@ namespace rqp {
 
 enum BatchPrec { kBatchF32 = 0, kBatchBF16x3 = 1 };
 
+// Slot states beyond the public statuses: a slot is idle until admitted; an admitted slot
+// starts at the next launch, cold (x = z = y = 0, start penalty) or warm (x, y and penalty
+// index already in place, z = A x).
+enum { kSlotIdle = 6, kSlotAdmitCold = 16, kSlotAdmitWarm = 17 };
+
+// Up to 64 slot indices passed by value in the kernel arguments.
+constexpr int kMaxSlotsPerCall = 64;
+struct SlotList {
+  int n;
+  int s[kMaxSlotsPerCall];
+};
+
 constexpr int kTileM = 128;   // instances per tile
 constexpr int kTileN = 128;   // layer rows per tile
 constexpr int kTileK = 32;    // k per LDS stage
@@ -31,7 +43,8 @@ struct BatchArgs {
   const double* mid;
   int n_rho;
   double sigma, alpha, eps_abs, eps_rel, rho_eq_scale;
-  int max_iter, check_interval, terminate, warm, j0;
+  int max_iter, check_interval, terminate, j0;
+  int steps;                // iterations this launch may run (max_iter for a whole solve)
   float* X;                 // state B x n
   float* Z;                 // state B x m
   float* Y;                 // state B x m
@@ -39,9 +52,9 @@ struct BatchArgs {
   void* Vb;                 // BF16 low parts
   void* CVa;                // check operand [x; y], B x ldk
   void* CVb;
-  int* jb;                  // B penalty indices (read at start when warm)
-  int* status;              // B
-  int* iterations;          // B
+  int* jb;                  // B penalty indices (kept for running and warm-admitted slots)
+  int* status;              // B slot states (kSlot* below, or a final status), persistent
+  int* iterations;          // B iterations since admission, persistent
   int* rho_hist;            // B x max_checks, may be null
   double* prim_res;         // B x max_checks, may be null
   double* dual_res;         // B x max_checks, may be null
@@ -59,6 +72,19 @@ struct BatchPlan {
 };
 
 BatchPlan plan_batch(int prec);
+// Set every slot's state (e.g. admit all for a whole-batch solve).
+hipError_t fill_status(int B, int value, int* status, hipStream_t st);
+// q, l, u of the listed slots: from initial states x0 (n_slots x nx, FP64, device) with the
+// parametric data F, E, lo, hi; or copied from FP64 device rows (a NULL vector is kept).
+hipError_t load_x0_slots(const SlotList& sl, int n, int m, int nx, const double* F, const double* E, const double* lo,
+                         const double* hi, const double* x0, float* Q, float* Lo, float* Up, hipStream_t st);
+hipError_t load_slots(const SlotList& sl, int n, int m, const double* q, const double* l, const double* u, float* Q,
+                      float* Lo, float* Up, hipStream_t st);
+// Admit the listed slots: cold (src == -1), or warm from slot src's x and y shifted by sx / sy
+// entries (entries shifted in from beyond the end are 0) and its penalty index. The source is
+// first copied to stage (n + m floats and one int); src == -2 reuses what stage holds.
+hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m, float* X, float* Y, int* jb,
+                       int* status, float* stage, hipStream_t st);
 hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st);
 
 // FP64 -> (BF16 high, BF16 low) split of a row-major matrix into ldk-padded rows.

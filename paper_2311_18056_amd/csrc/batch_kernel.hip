@@ -280,18 +280,22 @@ __device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt
   }
 }
 
-// Counting sort of the active instances by penalty index into lists[] and the M-tile table
-// (one workgroup; stable, so the order inside a bucket is by instance id).
-__device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */) {
+// Counting sort of the slots in state `want` by penalty index into lists[] and the M-tile
+// table (one workgroup; stable, so the order inside a bucket is by slot id). Before counting,
+// slots in state `from` (if >= 0) move to state `to`.
+__device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */, int want, int from, int to) {
   const int tid = threadIdx.x;
   constexpr int kMaxRhoB = 64;
   if (tid < kMaxRhoB) s_count[tid] = 0;
-  __syncthreads();
-  // per-thread contiguous chunk of instances
+  // per-thread contiguous chunk of slots
   const int chunk = (a.B + BS - 1) / BS;
-  const int b0 = tid * chunk, b1 = min(a.B, b0 + chunk);
+  const int b0 = min(a.B, tid * chunk), b1 = min(a.B, b0 + chunk);
+  if (from >= 0)
+    for (int b = b0; b < b1; ++b)
+      if (a.status[b] == from) a.status[b] = to;
+  __syncthreads();
   for (int b = b0; b < b1; ++b)
-    if (a.status[b] == ST_RUNNING) atomicAdd(&s_count[a.jb[b]], 1);
+    if (a.status[b] == want) atomicAdd(&s_count[a.jb[b]], 1);
   __syncthreads();
   __shared__ int s_base[kMaxRhoB];
   if (tid == 0) {
@@ -305,12 +309,11 @@ __device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */
     a.mtiles[0] = nt;
   }
   __syncthreads();
-  // stable scatter: thread order then instance order; positions by an exclusive scan over
-  // threads per bucket, done serially per bucket (n_rho small) with LDS
+  // stable scatter: positions by an exclusive scan over threads, one bucket at a time
   __shared__ int s_scan[BS];
   for (int j = 0; j < a.n_rho; ++j) {
     int mine = 0;
-    for (int b = b0; b < b1; ++b) mine += (a.status[b] == ST_RUNNING && a.jb[b] == j);
+    for (int b = b0; b < b1; ++b) mine += (a.status[b] == want && a.jb[b] == j);
     s_scan[tid] = mine;
     __syncthreads();
     if (tid == 0) {
@@ -324,7 +327,7 @@ __device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */
     __syncthreads();
     int pos = s_scan[tid];
     for (int b = b0; b < b1; ++b)
-      if (a.status[b] == ST_RUNNING && a.jb[b] == j) a.lists[pos++] = b;
+      if (a.status[b] == want && a.jb[b] == j) a.lists[pos++] = b;
     __syncthreads();
   }
 }
@@ -345,31 +348,31 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   unsigned epoch = 0;
   const long gtid = (long)g * BS + tid, gstride = (long)G * BS;
 
-  // ---- statuses and penalty indices
+  // ---- admitted slots: cold ones start from zero, warm ones from their x and y with z = A x
   for (long b = gtid; b < B; b += gstride) {
-    a.status[b] = ST_RUNNING;
-    a.iterations[b] = 0;
-    if (!a.warm) a.jb[b] = a.j0;
+    const int st = a.status[b];
+    if (st == kSlotAdmitCold || st == kSlotAdmitWarm) a.iterations[b] = 0;
+    if (st == kSlotAdmitCold) a.jb[b] = a.j0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) a.norms[b * 8 + q] = 0ull;
   }
-  if (!a.warm) {
-    for (long e = gtid; e < (long)B * n; e += gstride) a.X[e] = 0.0f;
-    for (long e = gtid; e < (long)B * a.m; e += gstride) {
+  for (long e = gtid; e < (long)B * n; e += gstride)
+    if (a.status[e / n] == kSlotAdmitCold) a.X[e] = 0.0f;
+  for (long e = gtid; e < (long)B * a.m; e += gstride)
+    if (a.status[e / a.m] == kSlotAdmitCold) {
       a.Z[e] = 0.0f;
       a.Y[e] = 0.0f;
     }
-  } else {
-    // warm start (Sec. II-B): keep x, y and the penalty, set z = A x
-    for (long e = gtid; e < (long)B * L; e += gstride) {
-      const int b = (int)(e / L), r = (int)(e % L);
+  for (long e = gtid; e < (long)B * L; e += gstride) {
+    const int b = (int)(e / L), r = (int)(e % L);
+    if (a.status[b] == kSlotAdmitWarm)
       put_operand<PREC>(a.CVa, a.CVb, (long)b * ldk + r, r < n ? a.X[(long)b * n + r] : a.Y[(long)b * a.m + (r - n)]);
-    }
   }
   if (!grid_barrier(a.bar, ++epoch)) return;
-  if (g == 0) build_tiles(a, s_count);
+  if (g == 0) build_tiles(a, s_count, kSlotAdmitWarm, kSlotAdmitCold, ST_RUNNING);
   if (!grid_barrier(a.bar, ++epoch)) return;
-  if (a.warm) {
+  if (a.mtiles[0] > 0) {
+    // warm start (Sec. II-B): z = A x from the z rows of the check product over K in [0, n)
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
     const int nt0 = n / TN;  // first row tile holding constraint rows
@@ -395,9 +398,13 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
   }
+  if (g == 0) build_tiles(a, s_count, ST_RUNNING, kSlotAdmitWarm, ST_RUNNING);
+  if (!grid_barrier(a.bar, ++epoch)) return;
+  if (a.mtiles[0] == 0) return;  // nothing to run
   // ---- first layer input V_1 (parity 1)
   for (long e = gtid; e < (long)B * L; e += gstride) {
     const int b = (int)(e / L), r = (int)(e % L);
+    if (a.status[b] != ST_RUNNING) continue;
     float w;
     if (r < n) {
       w = sigma * a.X[(long)b * n + r] - a.Q[(long)b * n + r];
@@ -411,9 +418,9 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   }
   if (!grid_barrier(a.bar, ++epoch)) return;
 
-  int nchk = 0;
-  for (int k = 1; k <= a.max_iter; ++k) {
-    const bool is_check = (k % a.check_interval == 0) || (k == a.max_iter);
+  const int ci = a.check_interval;
+  for (int k = 1; k <= a.steps; ++k) {
+    const bool is_check = (k % ci == 0) || (k == a.steps);
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
     const long vin = (long)(k & 1) * vpar, vout = (long)((k + 1) & 1) * vpar;
@@ -545,6 +552,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       const double nax = bits_to_double(bits[N_AX]), nz = bits_to_double(bits[N_Z]);
       const double npx = bits_to_double(bits[N_PX]), naty = bits_to_double(bits[N_ATY]);
       const double nq = bits_to_double(bits[N_Q]);
+      const int it = a.iterations[b] + k;  // iterations since admission
       int st = ST_RUNNING;
       if (nonfinite) {
         st = ST_NONFINITE;
@@ -553,7 +561,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
         const double eps_d = a.eps_abs + a.eps_rel * fmax(fmax(npx, naty), nq);
         if (rp <= eps_p && rd <= eps_d) st = ST_SOLVED;
       }
-      if (st == ST_RUNNING && k == a.max_iter) st = ST_MAX_ITER;
+      if (st == ST_RUNNING && it >= a.max_iter) st = ST_MAX_ITER;
       if (st == ST_RUNNING && ab) st = ST_ABORTED;
       int j = a.jb[b];
       if (st == ST_RUNNING && a.n_rho > 1 && rp > 0.0 && rd > 0.0) {
@@ -565,21 +573,22 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
         j = jn;
       }
       a.jb[b] = j;
-      if (nchk < a.max_checks) {
-        if (a.rho_hist) a.rho_hist[b * a.max_checks + nchk] = j;
-        if (a.prim_res) a.prim_res[b * a.max_checks + nchk] = rp;
-        if (a.dual_res) a.dual_res[b * a.max_checks + nchk] = rd;
+      const int c = (it + ci - 1) / ci - 1;  // check number since admission
+      if (c < a.max_checks) {
+        if (a.rho_hist) a.rho_hist[b * a.max_checks + c] = j;
+        if (a.prim_res) a.prim_res[b * a.max_checks + c] = rp;
+        if (a.dual_res) a.dual_res[b * a.max_checks + c] = rd;
       }
       if (st != ST_RUNNING) {
         a.status[b] = st;
-        a.iterations[b] = k;
+        a.iterations[b] = it;
       }
     }
-    ++nchk;
     if (!grid_barrier(a.bar, ++epoch)) return;
-    if (g == 0) build_tiles(a, s_count);
+    if (g == 0) build_tiles(a, s_count, ST_RUNNING, -1, -1);
     if (!grid_barrier(a.bar, ++epoch)) return;
-    if (a.mtiles[0] == 0) break;
+    if (a.mtiles[0] == 0) return;
+    if (k == a.steps) break;  // the next launch rebuilds the layer input from the state
 
     // ---- next layer input for the instances still running (penalty may have changed)
     const int nmt2 = a.mtiles[0];
@@ -601,6 +610,9 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     (void)nmt2;
     if (!grid_barrier(a.bar, ++epoch)) return;
   }
+  // slots still running carry their iteration count into the next launch
+  for (long b = gtid; b < B; b += gstride)
+    if (a.status[b] == ST_RUNNING) a.iterations[b] += a.steps;
 }
 
 }  // namespace
@@ -652,6 +664,109 @@ __global__ void pad_kernel(long rows, int cols, const double* __restrict__ src, 
   dst[idx] = c < cols ? (float)src[r * ld_src + c] : 0.0f;
 }
 }  // namespace
+
+namespace {
+__global__ void fill_status_kernel(int B, int value, int* __restrict__ status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) status[b] = value;
+}
+__global__ void stage_kernel(int src, int n, int m, const float* __restrict__ X, const float* __restrict__ Y,
+                             const int* __restrict__ jb, float* __restrict__ stage) {
+  for (int i = threadIdx.x; i < n + m; i += blockDim.x)
+    stage[i] = i < n ? X[(long)src * n + i] : Y[(long)src * m + (i - n)];
+  if (threadIdx.x == 0) reinterpret_cast<int*>(stage)[n + m] = jb[src];
+}
+// one workgroup per listed slot
+__global__ void admit_kernel(SlotList sl, int warm, int sx, int sy, int n, int m, float* __restrict__ X,
+                             float* __restrict__ Y, int* __restrict__ jb, int* __restrict__ status,
+                             const float* __restrict__ stage) {
+  const long s = sl.s[blockIdx.x];
+  if (warm) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) X[s * n + i] = i + sx < n ? stage[i + sx] : 0.0f;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) Y[s * m + i] = i + sy < m ? stage[n + i + sy] : 0.0f;
+  }
+  if (threadIdx.x == 0) {
+    if (warm) jb[s] = reinterpret_cast<const int*>(stage)[n + m];
+    status[s] = warm ? kSlotAdmitWarm : kSlotAdmitCold;
+  }
+}
+// Parametric vectors of the listed slots (Sec. IV): q = F x0, l = lo - E x0, u = hi - E x0;
+// one wave per (listed slot, row).
+__global__ void __launch_bounds__(256) x0_slots_kernel(SlotList sl, int n, int m, int nx, const double* __restrict__ F,
+                                                       const double* __restrict__ E, const double* __restrict__ lo,
+                                                       const double* __restrict__ hi, const double* __restrict__ x0,
+                                                       float* __restrict__ Q, float* __restrict__ Lo,
+                                                       float* __restrict__ Up) {
+  const long grow = (long)blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (grow >= (long)sl.n * (n + m)) return;
+  const int i = (int)(grow / (n + m)), row = (int)(grow % (n + m));
+  const long s = sl.s[i];
+  const double* arow = row < n ? F + (long)row * nx : E + (long)(row - n) * nx;
+  const double* xi = x0 + (long)i * nx;
+  double acc = 0.0;
+  for (int c = lane; c < nx; c += 64) acc = fma(arow[c], xi[c], acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    if (row < n) {
+      Q[s * n + row] = (float)acc;
+    } else {
+      Lo[s * m + (row - n)] = (float)(lo[row - n] - acc);
+      Up[s * m + (row - n)] = (float)(hi[row - n] - acc);
+    }
+  }
+}
+// q, l, u rows of the listed slots from FP64 device arrays (n_slots x n, n_slots x m)
+__global__ void vec_slots_kernel(SlotList sl, int n, int m, const double* __restrict__ q, const double* __restrict__ l,
+                                 const double* __restrict__ u, float* __restrict__ Q, float* __restrict__ Lo,
+                                 float* __restrict__ Up) {
+  const int i = blockIdx.x;
+  const long s = sl.s[i];
+  for (int r = threadIdx.x; r < n + m; r += blockDim.x) {
+    if (r < n) {
+      if (q) Q[s * n + r] = (float)q[(long)i * n + r];
+    } else {
+      if (l) Lo[s * m + (r - n)] = (float)l[(long)i * m + (r - n)];
+      if (u) Up[s * m + (r - n)] = (float)u[(long)i * m + (r - n)];
+    }
+  }
+}
+}  // namespace
+
+hipError_t load_x0_slots(const SlotList& sl, int n, int m, int nx, const double* F, const double* E, const double* lo,
+                         const double* hi, const double* x0, float* Q, float* Lo, float* Up, hipStream_t st) {
+  if (sl.n <= 0) return hipSuccess;
+  const long rows = (long)sl.n * (n + m);
+  hipLaunchKernelGGL(x0_slots_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, sl, n, m, nx, F, E, lo, hi,
+                     x0, Q, Lo, Up);
+  return hipGetLastError();
+}
+
+hipError_t load_slots(const SlotList& sl, int n, int m, const double* q, const double* l, const double* u, float* Q,
+                      float* Lo, float* Up, hipStream_t st) {
+  if (sl.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vec_slots_kernel, dim3((unsigned)sl.n), dim3(256), 0, st, sl, n, m, q, l, u, Q, Lo, Up);
+  return hipGetLastError();
+}
+
+hipError_t fill_status(int B, int value, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(fill_status_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, B, value, status);
+  return hipGetLastError();
+}
+
+hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m, float* X, float* Y, int* jb,
+                       int* status, float* stage, hipStream_t st) {
+  if (sl.n <= 0) return hipSuccess;
+  if (src >= 0) {
+    hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(256), 0, st, src, n, m, X, Y, jb, stage);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(admit_kernel, dim3((unsigned)sl.n), dim3(256), 0, st, sl, src != -1 ? 1 : 0, sx, sy, n, m, X, Y,
+                     jb, status, stage);
+  return hipGetLastError();
+}
 
 hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long ldk,
                       hipStream_t st) {

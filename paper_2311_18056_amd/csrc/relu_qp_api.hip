@@ -2,6 +2,7 @@
 // stage (Algorithm 1, "Offline") and the launch of the online stage.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -107,6 +108,9 @@ struct relu_qp_handle {
   int* blists = nullptr;
   int* bmtiles = nullptr;
   unsigned* bbar = nullptr;
+  int* bstatus = nullptr;   // slot states, persistent across launches
+  int* biter = nullptr;     // iterations since admission
+  float* bstage = nullptr;  // warm-start staging: n + m floats and one int
   rqp::BatchPlan bplan{};
 };
 
@@ -118,7 +122,7 @@ void free_handle(relu_qp_handle* h) {
                   h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,
                   h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
                   h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
-                  h->bnorms, h->blists, h->bmtiles, h->bbar};
+                  h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->abort_h) (void)hipHostFree(h->abort_h);
@@ -349,7 +353,9 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
       !al(&h->bCVa, vbytes) || (two && !al(&h->bCVb, vbytes)) || !al((void**)&h->bjb, (size_t)B * 4) ||
       !al((void**)&h->bnorms, (size_t)B * 8 * 8) || !al((void**)&h->blists, (size_t)B * 4) ||
       !al((void**)&h->bmtiles, (1 + 3 * ntile_max) * 4) || !al((void**)&h->bbar, 1024 * 4) ||
-      !al(&h->q, (size_t)B * n * 4) || !al(&h->l, (size_t)B * m * 4) || !al(&h->u, (size_t)B * m * 4)) {
+      !al(&h->q, (size_t)B * n * 4) || !al(&h->l, (size_t)B * m * 4) || !al(&h->u, (size_t)B * m * 4) ||
+      !al((void**)&h->bstatus, (size_t)B * 4) || !al((void**)&h->biter, (size_t)B * 4) ||
+      !al((void**)&h->bstage, ((size_t)n + m + 1) * 4)) {
     (void)hipGetLastError();
     return fail(RQP_ENOMEM, "device allocation failed (batch %d, n=%d, m=%d)", B, n, m);
   }
@@ -359,6 +365,11 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   HIP_OR_FAIL(hipMemset(h->bCVa, 0, vbytes));
   if (two) HIP_OR_FAIL(hipMemset(h->bCVb, 0, vbytes));
   HIP_OR_FAIL(hipMemset(h->bnorms, 0, (size_t)B * 64));
+  HIP_OR_FAIL(hipMemset(h->biter, 0, (size_t)B * 4));
+  HIP_OR_FAIL(hipMemset(h->bX, 0, (size_t)B * n * 4));
+  HIP_OR_FAIL(hipMemset(h->bZ, 0, (size_t)B * m * 4));
+  HIP_OR_FAIL(hipMemset(h->bY, 0, (size_t)B * m * 4));
+  HIP_OR_FAIL(rqp::fill_status(B, rqp::kSlotIdle, h->bstatus, st));
   std::vector<int> j0(B, h->j0);
   HIP_OR_FAIL(hipMemcpy(h->bjb, j0.data(), (size_t)B * 4, hipMemcpyHostToDevice));
   int rc;
@@ -372,7 +383,9 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   return RQP_OK;
 }
 
-int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
+// One persistent launch of the batched kernel over every running or admitted slot, for at most
+// `steps` iterations, then copies of the slot results into out.
+int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out) {
   const int B = h->batch;
   HIP_OR_FAIL(hipMemsetAsync(h->bbar, 0, 1024 * 4, st));
   __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
@@ -403,8 +416,8 @@ int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
   a.max_iter = h->s.max_iter;
   a.check_interval = h->s.check_interval;
   a.terminate = !(h->s.eps_abs == 0.0 && h->s.eps_rel == 0.0);
-  a.warm = (h->warm_pending || (h->warm_mode && h->have_prev)) ? 1 : 0;
   a.j0 = h->j0;
+  a.steps = steps;
   a.X = h->bX;
   a.Z = h->bZ;
   a.Y = h->bY;
@@ -413,8 +426,8 @@ int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
   a.CVa = h->bCVa;
   a.CVb = h->bCVb;
   a.jb = h->bjb;
-  a.status = out->status;
-  a.iterations = out->iterations;
+  a.status = h->bstatus;
+  a.iterations = h->biter;
   a.rho_hist = out->rho_hist;
   a.prim_res = out->prim_res;
   a.dual_res = out->dual_res;
@@ -430,8 +443,38 @@ int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
   HIP_OR_FAIL(hipMemcpyAsync(out->z, h->bZ, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
   HIP_OR_FAIL(hipMemcpyAsync(out->y, h->bY, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
   HIP_OR_FAIL(hipMemcpyAsync(out->rho_index, h->bjb, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(out->status, h->bstatus, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  HIP_OR_FAIL(hipMemcpyAsync(out->iterations, h->biter, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  return RQP_OK;
+}
+
+int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
+  const bool warm = h->warm_pending || (h->warm_mode && h->have_prev);
+  HIP_OR_FAIL(rqp::fill_status(h->batch, warm ? rqp::kSlotAdmitWarm : rqp::kSlotAdmitCold, h->bstatus, st));
+  const int rc = launch_batched(h, h->s.max_iter, st, out);
+  if (rc) return rc;
   h->warm_pending = false;
   h->have_prev = true;
+  return RQP_OK;
+}
+
+// Host slot list -> chunks of at most kMaxSlotsPerCall passed by value.
+template <typename F>
+int for_slot_chunks(relu_qp_handle* h, const int* slots, int n_slots, F&& f) {
+  if (!h->batched) return fail(RQP_ESTATE, "slots exist only with the batched engine");
+  if (n_slots < 0 || (n_slots > 0 && !slots)) return fail(RQP_EINVAL, "bad slot list");
+  std::vector<char> seen(h->batch, 0);
+  for (int i = 0; i < n_slots; ++i) {
+    if (slots[i] < 0 || slots[i] >= h->batch) return fail(RQP_EINVAL, "slot %d out of range [0, %d)", slots[i], h->batch);
+    if (seen[slots[i]]++) return fail(RQP_EINVAL, "slot %d listed twice", slots[i]);
+  }
+  for (int i0 = 0; i0 < n_slots; i0 += rqp::kMaxSlotsPerCall) {
+    rqp::SlotList sl{};
+    sl.n = std::min(rqp::kMaxSlotsPerCall, n_slots - i0);
+    for (int k = 0; k < sl.n; ++k) sl.s[k] = slots[i0 + k];
+    const int rc = f(sl, i0);
+    if (rc) return rc;
+  }
   return RQP_OK;
 }
 
@@ -754,6 +797,66 @@ int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
   h->warm_pending = false;
   h->have_prev = true;
   return RQP_OK;
+}
+
+int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const double* q, const double* l,
+                       const double* u, void* stream) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return for_slot_chunks(h, slots, n_slots, [&](const rqp::SlotList& sl, int i0) -> int {
+    const size_t n = h->n, m = h->m;
+    HIP_OR_FAIL(rqp::load_slots(sl, h->n, h->m, q ? q + i0 * n : nullptr, l ? l + i0 * m : nullptr,
+                                u ? u + i0 * m : nullptr, static_cast<float*>(h->q), static_cast<float*>(h->l),
+                                static_cast<float*>(h->u), st));
+    return RQP_OK;
+  });
+}
+
+int relu_qp_load_slots_x0(relu_qp_handle* h, const int* slots, int n_slots, const double* x0, void* stream) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
+  if (!x0 && n_slots > 0) return fail(RQP_EINVAL, "x0 is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return for_slot_chunks(h, slots, n_slots, [&](const rqp::SlotList& sl, int i0) -> int {
+    HIP_OR_FAIL(rqp::load_x0_slots(sl, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d,
+                                   x0 + (size_t)i0 * h->nx, static_cast<float*>(h->q), static_cast<float*>(h->l),
+                                   static_cast<float*>(h->u), st));
+    return RQP_OK;
+  });
+}
+
+int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot, int shift_x, int shift_y,
+                  void* stream) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (h->batched && (src_slot < -1 || src_slot >= h->batch))
+    return fail(RQP_EINVAL, "src_slot %d out of range [-1, %d)", src_slot, h->batch);
+  if (shift_x < 0 || shift_x > h->n || shift_y < 0 || shift_y > h->m) return fail(RQP_EINVAL, "bad shift");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bool first = true;
+  return for_slot_chunks(h, slots, n_slots, [&](const rqp::SlotList& sl, int) -> int {
+    // the source state is staged once, before any listed slot (which may include it) is written
+    if (src_slot >= 0 && !first) {
+      HIP_OR_FAIL(rqp::admit_slots(sl, -2, shift_x, shift_y, h->n, h->m, h->bX, h->bY, h->bjb, h->bstatus,
+                                   h->bstage, st));
+    } else {
+      HIP_OR_FAIL(rqp::admit_slots(sl, src_slot, shift_x, shift_y, h->n, h->m, h->bX, h->bY, h->bjb, h->bstatus,
+                                   h->bstage, st));
+    }
+    first = false;
+    return RQP_OK;
+  });
+}
+
+int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* out) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!h->batched) return fail(RQP_ESTATE, "relu_qp_step needs the batched engine");
+  if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
+    return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
+  if (h->s.max_iter % h->s.check_interval != 0)
+    return fail(RQP_EINVAL, "serving needs max_iter to be a multiple of check_interval");
+  if (n_checks < 1 || n_checks > h->s.max_iter / h->s.check_interval)
+    return fail(RQP_EINVAL, "n_checks must be in [1, max_iter / check_interval]");
+  return launch_batched(h, n_checks * h->s.check_interval, static_cast<hipStream_t>(stream), out);
 }
 
 int relu_qp_abort(relu_qp_handle* h) {

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import (RQP_BF16X3, RQP_ENGINE_AUTO, RQP_ENGINE_BATCH, RQP_ENGINE_SINGLE, RQP_FP32, RQP_FP64, Result,
                    Settings, check, lib)
 
-STATUS_NAMES = {0: "running", 1: "solved", 2: "max_iter", 3: "nonfinite", 4: "aborted", 5: "internal"}
+STATUS_NAMES = {0: "running", 1: "solved", 2: "max_iter", 3: "nonfinite", 4: "aborted", 5: "internal", 6: "idle"}
 
 
 def _f64(a, shape=None):
@@ -141,6 +141,43 @@ class Solver:
         """Launch the whole online loop (asynchronous on the stream). ``out`` optionally names
         other device result buffers (a ``Result`` from ``result_slots``)."""
         check(lib().relu_qp_solve(self._h, _stream_handle(stream), byref(out if out is not None else self._res)))
+
+    # ------------------------------------------------------------------ serving (batched engine)
+    @staticmethod
+    def _slot_array(slots):
+        arr = (c_int * len(slots))(*[int(s) for s in slots])
+        return arr, len(slots)
+
+    @staticmethod
+    def _dev_f64(t):
+        if t is None:
+            return None
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("slot data are contiguous float64 cuda tensors")
+        return c_void_p(t.data_ptr())
+
+    def load_slots(self, slots, q=None, l=None, u=None, stream=None):
+        """q (len(slots), n), l, u (len(slots), m): float64 cuda tensors; None keeps a vector."""
+        arr, k = self._slot_array(slots)
+        check(lib().relu_qp_load_slots(self._h, arr, k, self._dev_f64(q), self._dev_f64(l), self._dev_f64(u),
+                                       _stream_handle(stream)))
+
+    def load_slots_x0(self, slots, x0: torch.Tensor, stream=None):
+        """x0: (len(slots), nx) float64 cuda tensor; needs ``set_parametric``."""
+        arr, k = self._slot_array(slots)
+        check(lib().relu_qp_load_slots_x0(self._h, arr, k, self._dev_f64(x0), _stream_handle(stream)))
+
+    def admit(self, slots, src_slot: int = -1, shift_x: int = 0, shift_y: int = 0, stream=None):
+        """Start the listed slots at the next ``step``: cold (src_slot = -1) or warm from slot
+        src_slot's x and y shifted by shift_x / shift_y entries, with z = A x."""
+        arr, k = self._slot_array(slots)
+        check(lib().relu_qp_admit(self._h, arr, k, int(src_slot), int(shift_x), int(shift_y),
+                                  _stream_handle(stream)))
+
+    def step(self, n_checks: int = 1, stream=None):
+        """Run up to n_checks * check_interval iterations of every running or admitted slot
+        (asynchronous); results of all slots land in this object's tensors."""
+        check(lib().relu_qp_step(self._h, int(n_checks), _stream_handle(stream), byref(self._res)))
 
     def result_slots(self, count: int):
         """Device buffers for ``count`` solves (one slot each) and their ``Result`` structs.

@@ -57,3 +57,30 @@ def test_null_handle_is_rejected_without_a_gpu():
     rc = lib.relu_qp_setup(ctypes.byref(h), 2, 2, z, z, z, z, z, ctypes.byref(s), None)
     assert rc == rq._lib.RQP_EINVAL and h.value is None
     assert b"alpha" in lib.relu_qp_last_error()
+
+
+def test_serving_calls_reject_a_null_handle():
+    import paper_2311_18056_amd as rq
+
+    lib = rq.lib()
+    E = rq._lib.RQP_ESTATE
+    assert lib.relu_qp_load_slots(None, None, 0, None, None, None, None) == E
+    assert lib.relu_qp_load_slots_x0(None, None, 0, None, None) == E
+    assert lib.relu_qp_admit(None, None, 0, -1, 0, 0, None) == E
+    assert lib.relu_qp_step(None, 1, None, None) == E
+
+
+def test_settings_rules_for_engines():
+    import ctypes
+
+    import paper_2311_18056_amd as rq
+
+    lib = rq.lib()
+    h = ctypes.c_void_p()
+    z = (ctypes.c_double * 4)()
+    for kw, word in ((dict(precision="fp64", engine="batch"), b"FP32 or BF16X3"),
+                     (dict(precision="bf16x3", engine="single"), b"batched engine"),
+                     (dict(batch=2, engine="single"), b"batch == 1")):
+        s = rq.default_settings(**kw)
+        assert lib.relu_qp_setup(ctypes.byref(h), 2, 2, z, z, z, z, z, ctypes.byref(s), None) == rq._lib.RQP_EINVAL
+        assert word in lib.relu_qp_last_error(), kw

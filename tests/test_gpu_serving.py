@@ -1,0 +1,180 @@
+"""GPU tests of continuous batching (slots admitted and retired between persistent launches).
+
+A request served in a slot, next to other requests admitted at other times, must give the
+bit-identical result of the same request solved alone by the batched engine (same kernels, an
+instance's arithmetic never depends on its neighbours), and match the FP64 oracle with its
+penalty schedule replayed to the FP32 tolerance.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import admm
+from oracle.mpc_update import qp_vectors
+from workloads import make_config, x0_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2311_18056_amd as rq
+
+    rq.lib()
+    return rq
+
+
+def _os(**kw):
+    s = admm.Settings()
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1.0)
+
+
+def _dev(a):
+    import torch
+
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _solo(rq, prob, x0, warm=None, **kw):
+    """The same request alone: batch of one on the batched engine."""
+    s = rq.Solver(prob.P, np.zeros((1, prob.n)), prob.A, prob.lo[None, :], prob.hi[None, :], engine="batch", **kw)
+    s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    s.update_x0_device(_dev(x0[None, :]))
+    if warm is not None:
+        s.warm_start(warm[0][None, :], warm[1][None, :], warm[2])
+    s.solve()
+    r = s.result(0)
+    s.close()
+    return r
+
+
+def _snapshot(sol, slot):
+    r = sol.result()
+    it = int(r["iterations"][slot])
+    nck = -(-it // sol.settings.check_interval)
+    return dict(x=r["x"][slot].copy(), y=r["y"][slot].copy(), z=r["z"][slot].copy(), iterations=it,
+                status=int(r["status"][slot]), rho_index=int(r["rho_index"][slot]),
+                rho_hist=r["rho_hist"][slot][:nck].tolist())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_slots_admitted_at_different_steps_match_solo(rq, prec):
+    prob = make_config("c0")
+    kw = dict(precision=prec, n_rho=8)
+    B = 6
+    sol = rq.Solver(prob.P, np.zeros((B, prob.n)), prob.A, np.repeat(prob.lo[None], B, 0),
+                    np.repeat(prob.hi[None], B, 0), engine="batch", **kw)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    x0 = 5.0 * x0_batch(prob.nx, 5, 3000)
+    sol.step(1)  # nothing admitted: a no-op launch
+    assert np.all(sol.result()["status"] == rq.RQP_IDLE)
+
+    done = {}
+    admitted = {0: 0, 3: 1}
+    sol.load_slots_x0([0, 3], _dev(x0[:2]))
+    sol.admit([0, 3])
+    plan = {1: ([5], [2])}  # after step 1, slot 5 gets request 2
+    for step in range(200):
+        sol.step(1)
+        r = sol.result()
+        for s, req in list(admitted.items()):
+            if r["status"][s] != rq.RQP_RUNNING:
+                done[req] = _snapshot(sol, s)
+                del admitted[s]
+        if step in plan:
+            slots, reqs = plan[step]
+            sol.load_slots_x0(slots, _dev(x0[reqs]))
+            sol.admit(slots)
+            admitted.update(dict(zip(slots, reqs)))
+        if not admitted:
+            break
+    assert sorted(done) == [0, 1, 2]
+
+    # warm admissions from slot 3's final state, shifted by one stage, into slot 3 itself and slot 1
+    src = done[1]
+    sol.load_slots_x0([3, 1], _dev(x0[3:5]))
+    sol.admit([3, 1], src_slot=3, shift_x=prob.nu, shift_y=prob.nu)
+    admitted = {3: 3, 1: 4}
+    for _ in range(200):
+        sol.step(2)
+        r = sol.result()
+        for s, req in list(admitted.items()):
+            if r["status"][s] != rq.RQP_RUNNING:
+                done[req] = _snapshot(sol, s)
+                del admitted[s]
+        if not admitted:
+            break
+    assert sorted(done) == [0, 1, 2, 3, 4]
+    sol.close()
+
+    nu = prob.nu
+    xs = np.concatenate([src["x"][nu:], np.zeros(nu)])
+    ys = np.concatenate([src["y"][nu:], np.zeros(nu)])
+    for req, d in done.items():
+        warm = (xs, ys, src["rho_index"]) if req >= 3 else None
+        solo = _solo(rq, prob, x0[req], warm=warm, **kw)
+        assert d["status"] == solo["status"] == rq.RQP_SOLVED, req
+        assert d["iterations"] == solo["iterations"] and d["rho_hist"] == solo["rho_hist"], req
+        for name in ("x", "y", "z"):
+            assert np.array_equal(d[name], solo[name]), (prec, req, name)
+        if prec == "fp32":
+            q, l, u = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, x0[req])
+            ref = oracle.solve(prob.P, q, prob.A, l, u,
+                               _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=d["iterations"]),
+                               warm=warm, rho_replay=d["rho_hist"])
+            for name in ("x", "y", "z"):
+                assert _rel(d[name], getattr(ref, name)) <= 1e-4, (req, name)
+
+
+def test_step_reaches_max_iter_across_launches(rq):
+    """max_iter counts from admission over several steps."""
+    prob = make_config("c0")
+    B = 3
+    sol = rq.Solver(prob.P, np.zeros((B, prob.n)), prob.A, np.repeat(prob.lo[None], B, 0),
+                    np.repeat(prob.hi[None], B, 0), engine="batch", precision="fp32", n_rho=8, eps_abs=0.0,
+                    eps_rel=0.0, max_iter=100)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    x0 = 5.0 * x0_batch(prob.nx, 1, 3100)
+    sol.load_slots_x0([1], _dev(x0))
+    sol.admit([1])
+    for k in range(3):
+        sol.step(1)
+        r = sol.result()
+        assert r["status"][1] == rq.RQP_RUNNING and r["iterations"][1] == 25 * (k + 1)
+    sol.step(3)
+    r = sol.result()
+    assert r["status"][1] == rq.RQP_MAX_ITER and r["iterations"][1] == 100
+    assert r["status"][0] == rq.RQP_IDLE and r["status"][2] == rq.RQP_IDLE
+    q, l, u = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, x0[0])
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=100),
+                       rho_replay=r["rho_hist"][1][:4].tolist())
+    for name in ("x", "y", "z"):
+        assert _rel(r[name][1], getattr(ref, name)) <= 1e-4
+    sol.close()
+
+
+def test_server_two_families(rq):
+    from paper_2311_18056_amd.serving import Family, Server, latency_summary, poisson_requests
+
+    probs = [make_config("c0"), make_config("c0", seed=7)]
+    fams = [Family.from_mpc(p, slots=8, precision="fp32", keep_x=True, n_rho=8) for p in probs]
+    gens = [lambda rng, p=p: 5.0 * rng.uniform(-1, 1, p.nx) for p in probs]
+    reqs = poisson_requests(2000.0, 60, 10.0, gens, seed=4)
+    Server(fams, n_checks=1, warm=True).run(reqs, time_limit=60.0)
+    for r in reqs:
+        assert r.status == rq.RQP_SOLVED, r.rid
+        p = probs[r.family]
+        q, l, u = qp_vectors(p.F, p.E, p.lo, p.hi, r.x0)
+        xs = oracle.solve(p.P, q, p.A, l, u, _os(n_rho=8, eps_abs=1e-9, eps_rel=1e-9, max_iter=40000)).x
+        assert _rel(r.x, xs) < 5e-2, r.rid
+    summ = latency_summary(reqs)
+    assert summ["completed"] == len(reqs)
+    for f in fams:
+        f.solver.close()
