@@ -179,7 +179,9 @@ int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot
  * Needs max_iter % check_interval == 0 (RQP_EINVAL otherwise). */
 int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* out);
 
-/* Ask a running solve to stop at its next check with status RQP_ABORTED (any thread). */
+/* Ask a running solve to stop with status RQP_ABORTED (any thread). The flag lives in host
+ * memory and a kernel polls it at every 16th check of a launch (every 400 iterations with the
+ * default check_interval), since each poll is a PCIe round trip. */
 int relu_qp_abort(relu_qp_handle* h);
 
 /* Sizes of the result arrays and the grid. */

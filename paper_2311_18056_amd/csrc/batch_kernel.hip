@@ -125,133 +125,157 @@ __device__ __forceinline__ int loader_row(int q) {
     return threadIdx.x / 8 + 32 * q;
 }
 
-template <int N, typename V>
-__device__ __forceinline__ V mask_k(V v, long c0, int kb, int ke) {
-  if (c0 >= kb && c0 + N <= ke) return v;
+// One K stage of this thread's operand rows, held in registers between its global loads and
+// its LDS stores (so that the loads of the next stages are in flight during the products).
+template <int PREC>
+struct Frag;
+template <>
+struct Frag<kBatchBF16x3> {
+  ushort8 a[2][2], b[2][2];  // [hi/lo][row]
+};
+template <>
+struct Frag<kBatchF32> {
+  floatx4 a[4], b[4];
+};
+
+// Loads never branch: a row outside the tile's valid range reads a valid dummy row (its
+// products land in accumulator rows or columns that are discarded).
+template <int PREC>
+__device__ __forceinline__ void fetch(Frag<PREC>& f, const void* Aa, const void* Ab, const void* Ba, const void* Bb,
+                                      const long (&aoff)[Smem<PREC>::kRowsPerThread],
+                                      const long (&boff)[Smem<PREC>::kRowsPerThread], int stage) {
+  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+  if constexpr (PREC == kBatchBF16x3) {
+    const long k0 = (long)stage * TK + (threadIdx.x % 4) * 8;
 #pragma unroll
-  for (int e = 0; e < N; ++e)
-    if (c0 + e < kb || c0 + e >= ke) v[e] = 0;
-  return v;
+    for (int h = 0; h < RPT; ++h) {
+      f.a[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Aa) + aoff[h] + k0);
+      f.a[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ab) + aoff[h] + k0);
+      f.b[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ba) + boff[h] + k0);
+      f.b[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Bb) + boff[h] + k0);
+    }
+  } else {
+    const long k0 = (long)stage * TK + (threadIdx.x % 8) * 4;
+#pragma unroll
+    for (int h = 0; h < RPT; ++h) {
+      f.a[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Aa) + aoff[h] + k0);
+      f.b[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Ba) + boff[h] + k0);
+    }
+  }
 }
 
-// acc = sum over k in [kb, ke) of A[row][k] B[col][k]
+// LDS stores of one stage; with MASK, matrix entries with k outside [kb, ke) become zero.
+template <int PREC, bool MASK>
+__device__ __forceinline__ void stash(Smem<PREC>& sm, int buf, const Frag<PREC>& f, int stage, int kb, int ke) {
+  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+  if constexpr (PREC == kBatchBF16x3) {
+    const int kc = (threadIdx.x % 4) * 8;
+    const int k0 = stage * TK + kc;
+#pragma unroll
+    for (int h = 0; h < RPT; ++h) {
+      const int row = loader_row<PREC>(h);
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        ushort8 bv = f.b[p][h];
+        if constexpr (MASK) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bv[e] = (k0 + e >= kb && k0 + e < ke) ? bv[e] : (unsigned short)0;
+        }
+        *reinterpret_cast<ushort8*>(&sm.a[buf][p][row][kc]) = f.a[p][h];
+        *reinterpret_cast<ushort8*>(&sm.b[buf][p][row][kc]) = bv;
+      }
+    }
+  } else {
+    const int kc = (threadIdx.x % 8) * 4;
+    const int k0 = stage * TK + kc;
+#pragma unroll
+    for (int h = 0; h < RPT; ++h) {
+      const int row = loader_row<PREC>(h);
+      floatx4 bv = f.b[h];
+      if constexpr (MASK) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[e] = (k0 + e >= kb && k0 + e < ke) ? bv[e] : 0.0f;
+      }
+      *reinterpret_cast<floatx4*>(&sm.a[buf][row][kc]) = f.a[h];
+      *reinterpret_cast<floatx4*>(&sm.b[buf][row][kc]) = bv;
+    }
+  }
+}
+
+// Products of one LDS stage into this wave's 64 x 64 quarter.
 template <int PREC>
+__device__ __forceinline__ void compute(const Smem<PREC>& sm, int buf, floatx16 (&acc)[2][2]) {
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int wm = wave / 2, wn = wave % 2;
+  if constexpr (PREC == kBatchBF16x3) {
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 16) {
+      const int kq = kk + 8 * (lane / 32);
+      bf16x8 fa[2][2], fb[2][2];  // [block][hi/lo]
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          fa[i][p] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const ushort8*>(&sm.a[buf][p][wm * 64 + i * 32 + lane % 32][kq]));
+          fb[i][p] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const ushort8*>(&sm.b[buf][p][wn * 64 + i * 32 + lane % 32][kq]));
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][0], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fb[j][0], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][1], acc[i][j], 0, 0, 0);
+        }
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 2) {
+      const int kq = kk + lane / 32;
+      float fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        fa[i] = sm.a[buf][wm * 64 + i * 32 + lane % 32][kq];
+        fb[i] = sm.b[buf][wn * 64 + i * 32 + lane % 32][kq];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  }
+}
+
+// acc = sum over k in [kb, ke) of A[row][k] B[col][k]. Stages of TK columns are double
+// buffered in LDS; the global loads run two stages ahead of the products.
+template <int PREC, bool MASK>
 __device__ __forceinline__ void tile_gemm(Smem<PREC>& sm, const void* Aa, const void* Ab, const void* Ba,
                                           const void* Bb, const long (&aoff)[Smem<PREC>::kRowsPerThread],
                                           const long (&boff)[Smem<PREC>::kRowsPerThread], int kb, int ke,
                                           floatx16 (&acc)[2][2]) {
-  constexpr int RPT = Smem<PREC>::kRowsPerThread;
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wm = wave / 2, wn = wave % 2;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
-  const int s_first = kb / TK, nstage = (ke + TK - 1) / TK - s_first;
-
-  if constexpr (PREC == kBatchBF16x3) {
-    const int kc = (tid % 4) * 8;
-    const unsigned short* ah = static_cast<const unsigned short*>(Aa);
-    const unsigned short* al = static_cast<const unsigned short*>(Ab);
-    const unsigned short* bh = static_cast<const unsigned short*>(Ba);
-    const unsigned short* bl = static_cast<const unsigned short*>(Bb);
-    ushort8 ra[2][RPT], rb[2][RPT];
-    auto fetch = [&](int s) {
-      const long k0 = (long)(s_first + s) * TK + kc;
-#pragma unroll
-      for (int h = 0; h < RPT; ++h) {
-        ra[0][h] = aoff[h] >= 0 ? *reinterpret_cast<const ushort8*>(ah + aoff[h] + k0) : ushort8{};
-        ra[1][h] = aoff[h] >= 0 ? *reinterpret_cast<const ushort8*>(al + aoff[h] + k0) : ushort8{};
-        rb[0][h] = boff[h] >= 0 ? *reinterpret_cast<const ushort8*>(bh + boff[h] + k0) : ushort8{};
-        rb[1][h] = boff[h] >= 0 ? *reinterpret_cast<const ushort8*>(bl + boff[h] + k0) : ushort8{};
-        rb[0][h] = mask_k<8>(rb[0][h], k0, kb, ke);
-        rb[1][h] = mask_k<8>(rb[1][h], k0, kb, ke);
-      }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-      for (int h = 0; h < RPT; ++h)
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          *reinterpret_cast<ushort8*>(&sm.a[buf][p][loader_row<PREC>(h)][kc]) = ra[p][h];
-          *reinterpret_cast<ushort8*>(&sm.b[buf][p][loader_row<PREC>(h)][kc]) = rb[p][h];
-        }
-    };
-    fetch(0);
-    stash(0);
+  const int s0 = kb / TK, ns = (ke + TK - 1) / TK - s0;
+  Frag<PREC> f0, f1;
+  fetch<PREC>(f0, Aa, Ab, Ba, Bb, aoff, boff, s0);
+  if (ns > 1) fetch<PREC>(f1, Aa, Ab, Ba, Bb, aoff, boff, s0 + 1);
+  stash<PREC, MASK>(sm, 0, f0, s0, kb, ke);
+  __syncthreads();
+  for (int s = 0; s < ns; s += 2) {
+    // stage s is in LDS buffer 0, stage s + 1 in flight in f1
+    if (s + 2 < ns) fetch<PREC>(f0, Aa, Ab, Ba, Bb, aoff, boff, s0 + s + 2);
+    compute<PREC>(sm, 0, acc);
+    if (s + 1 < ns) stash<PREC, MASK>(sm, 1, f1, s0 + s + 1, kb, ke);
     __syncthreads();
-    for (int s = 0; s < nstage; ++s) {
-      const int buf = s & 1;
-      if (s + 1 < nstage) fetch(s + 1);
-#pragma unroll
-      for (int kk = 0; kk < TK; kk += 16) {
-        const int kq = kk + 8 * (lane / 32);
-        bf16x8 fa[2][2], fb[2][2];  // [block][hi/lo]
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int p = 0; p < 2; ++p) {
-            fa[i][p] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const ushort8*>(&sm.a[buf][p][wm * 64 + i * 32 + lane % 32][kq]));
-            fb[i][p] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const ushort8*>(&sm.b[buf][p][wn * 64 + i * 32 + lane % 32][kq]));
-          }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][0], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fb[j][0], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][1], acc[i][j], 0, 0, 0);
-          }
-      }
-      if (s + 1 < nstage) stash(buf ^ 1);
-      __syncthreads();
-    }
-  } else {
-    const int kc = (tid % 8) * 4;
-    const float* af = static_cast<const float*>(Aa);
-    const float* bf = static_cast<const float*>(Ba);
-    floatx4 ra[RPT], rb[RPT];
-    auto fetch = [&](int s) {
-      const long k0 = (long)(s_first + s) * TK + kc;
-#pragma unroll
-      for (int h = 0; h < RPT; ++h) {
-        ra[h] = aoff[h] >= 0 ? *reinterpret_cast<const floatx4*>(af + aoff[h] + k0) : floatx4{};
-        rb[h] = boff[h] >= 0 ? *reinterpret_cast<const floatx4*>(bf + boff[h] + k0) : floatx4{};
-        rb[h] = mask_k<4>(rb[h], k0, kb, ke);
-      }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-      for (int h = 0; h < RPT; ++h) {
-        *reinterpret_cast<floatx4*>(&sm.a[buf][loader_row<PREC>(h)][kc]) = ra[h];
-        *reinterpret_cast<floatx4*>(&sm.b[buf][loader_row<PREC>(h)][kc]) = rb[h];
-      }
-    };
-    fetch(0);
-    stash(0);
+    if (s + 1 >= ns) break;
+    if (s + 3 < ns) fetch<PREC>(f1, Aa, Ab, Ba, Bb, aoff, boff, s0 + s + 3);
+    compute<PREC>(sm, 1, acc);
+    if (s + 2 < ns) stash<PREC, MASK>(sm, 0, f0, s0 + s + 2, kb, ke);
     __syncthreads();
-    for (int s = 0; s < nstage; ++s) {
-      const int buf = s & 1;
-      if (s + 1 < nstage) fetch(s + 1);
-#pragma unroll
-      for (int kk = 0; kk < TK; kk += 2) {
-        const int kq = kk + lane / 32;
-        float fa[2], fb[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          fa[i] = sm.a[buf][wm * 64 + i * 32 + lane % 32][kq];
-          fb[i] = sm.b[buf][wn * 64 + i * 32 + lane % 32][kq];
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
-      }
-      if (s + 1 < nstage) stash(buf ^ 1);
-      __syncthreads();
-    }
   }
 }
 
@@ -274,9 +298,10 @@ __device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt
 #pragma unroll
   for (int h = 0; h < RPT; ++h) {
     const int r = loader_row<PREC>(h);
-    aoff[h] = r < mt.cnt ? abase + (long)a.lists[mt.off + r] * a.ldk : -1;
+    // rows past the tile's instances or past L read row 0 (their results are discarded)
+    aoff[h] = abase + (r < mt.cnt ? (long)a.lists[mt.off + r] * a.ldk : 0);
     const int row = nt * TN + r;
-    boff[h] = row < a.L ? bbase + (long)row * a.ldk : -1;
+    boff[h] = bbase + (row < a.L ? (long)row * a.ldk : 0);
   }
 }
 
@@ -382,7 +407,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
       tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
       floatx16 acc[2][2];
-      tile_gemm<PREC>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc);
+      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -432,7 +457,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
       tile_offsets<PREC>(a, mt, nt, vin, (long)mt.j * a.w_stride, aoff, boff);
       floatx16 acc[2][2];
-      tile_gemm<PREC>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, 0, L, acc);
+      tile_gemm<PREC, false>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, 0, L, acc);
       const double rho_bar = a.grid[mt.j];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -483,8 +508,8 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
       tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
       floatx16 acc_p[2][2], acc_a[2][2];
-      tile_gemm<PREC>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc_p);  // P x (x rows), A x (z rows)
-      tile_gemm<PREC>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, n, L, acc_a);  // A'y (x rows), 0 (z rows)
+      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc_p);  // P x (x rows), A x (z rows)
+      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, n, L, acc_a);  // A'y (x rows), 0 (z rows)
       // per instance (accumulator row) maxima over this tile's rows
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -536,7 +561,13 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (!grid_barrier(a.bar, ++epoch)) return;
 
     // ---- per-instance decision (eqs. primal, dual, rho_update; nearest grid value)
-    const bool ab = a.abort_flag && __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    // host-mapped flag: one PCIe read per workgroup at every kAbortEvery-th check
+    __shared__ int ab_s;
+    if (tid == 0)
+      ab_s = (k / ci) % kAbortEvery == kAbortEvery - 1 && a.abort_flag &&
+             __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
+    const bool ab = ab_s != 0;
     for (long b = gtid; b < B; b += gstride) {
       if (a.status[b] != ST_RUNNING) continue;
       unsigned long long* nm = a.norms + b * 8;

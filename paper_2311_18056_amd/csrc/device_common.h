@@ -58,6 +58,8 @@ __device__ __forceinline__ uint64_t abs_bits(double v) {
 }
 __device__ __forceinline__ double bits_to_double(uint64_t b) { return __longlong_as_double((long long)b); }
 constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
+// the host's abort flag is polled at every kAbortEvery-th check of a launch
+constexpr int kAbortEvery = 16;
 
 // Wave-wide sum with DPP lane permutations (VALU, no LDS round trip): quad swaps, half-row
 // and row mirrors give 16-lane sums in every lane, then the two row broadcasts fold the four

@@ -153,6 +153,8 @@ __device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows
   const T* Cm = static_cast<const T*>(a.C);
   constexpr int RC = 16 / NC > 0 ? 16 / NC : 1;  // rows of the check matrix loaded together
   for (int rr = 0; rr < nrows; rr += RC) {
+    // branch-free loads (masked entries read a valid address and are zeroed afterwards), so
+    // that all RC * NC loads are in flight together
     T cr[RC][NC];
 #pragma unroll
     for (int b = 0; b < RC; ++b) {
@@ -162,16 +164,19 @@ __device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows
       for (int k = 0; k < NC; ++k) {
         const int c = tid + BS * k;
         const bool ld = rv && c < L && (Rr < n || c < n);
-        cr[b][k] = ld ? Cm[(long)Rr * ldw + c] : (T)0;
+        cr[b][k] = Cm[ld ? (long)Rr * ldw + c : 0];
       }
     }
 #pragma unroll
     for (int b = 0; b < RC; ++b) {
+      const int Rr = r0 + rr + b;
+      const bool rv = rr + b < nrows;
       double p = 0.0, q2 = 0.0;
 #pragma unroll
       for (int k = 0; k < NC; ++k) {
         const int c = tid + BS * k;
-        const double v = (double)cr[b][k] * (double)cv.v[k];
+        const bool ld = rv && c < L && (Rr < n || c < n);
+        const double v = ld ? (double)cr[b][k] * (double)cv.v[k] : 0.0;
         if (c < n)
           p += v;
         else
@@ -179,7 +184,7 @@ __device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows
       }
       p = wave_sum_to_last(p);
       q2 = wave_sum_to_last(q2);
-      if (lane == kLastLane && rr + b < nrows) {
+      if (lane == kLastLane && rv) {
         redd[wave][2 * (rr + b)] = p;
         redd[wave][2 * (rr + b) + 1] = q2;
       }
@@ -253,7 +258,10 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
     if (tid < 7) {
       for (int w = 0; w < NWAVE; ++w) v = nred[w][tid] > v ? nred[w][tid] : v;
     } else {
-      const bool ab = a.abort_flag && __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      // the host-mapped flag costs a PCIe round trip (~13 us measured), so it is read at
+      // every kAbortEvery-th check only
+      const bool ab = (nchk % kAbortEvery) == kAbortEvery - 1 && a.abort_flag &&
+                      __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       v = err_set(a.err, a.tag) ? 2u : (ab ? 1u : 0u);
     }
     ll_store_bits64(a.xn + ((long)(nchk & 1) * G * 8 + (long)g * 8 + tid) * 2, v, ctag);
@@ -368,12 +376,27 @@ template <typename T, int NC, int NLM>
 __device__ __forceinline__ void load_lds_rows(const LayerArgs& a, int j, int r0, int first, int nlds, T* wl) {
   const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
   const int tid = threadIdx.x;
-  for (int rr = 0; rr < NLM; ++rr)
+  // batches of RB rows: their loads first (branch-free: masked entries read a valid address),
+  // then the LDS stores
+  constexpr int RB = 16 / NC < 1 ? 1 : (16 / NC > NLM ? NLM : 16 / NC);
+#pragma unroll 1
+  for (int r0b = 0; r0b < NLM; r0b += RB) {
+    T v[RB][NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const int c = tid + BS * k;
-      wl[(rr * NC + k) * BS + tid] = (rr < nlds && c < a.L) ? Wj[(long)(r0 + first + rr) * a.ldw + c] : (T)0;
-    }
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int rr = r0b + b, c = tid + BS * k;
+        v[b][k] = Wj[(rr < nlds && c < a.L) ? (long)(r0 + first + rr) * a.ldw + c : 0];
+      }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const int rr = r0b + b, c = tid + BS * k;
+        if (rr < NLM) wl[(rr * NC + k) * BS + tid] = (rr < nlds && c < a.L) ? v[b][k] : (T)0;
+      }
+  }
 }
 
 // NRS rows of each block in registers, NLM in LDS, the rest streamed. The loop between two
