@@ -147,6 +147,12 @@ int relu_qp_set_warm(relu_qp_handle* h, int enabled);
  * read them after a stream synchronisation. */
 int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out);
 
+/* relu_qp_update_x0_device followed by relu_qp_solve, in one launch for the single-instance
+ * engine (the kernel forms q, l, u of its rows from x0 before iterating, with the same FP64
+ * products, and writes them back). x0: DEVICE FP64, batch*nx. RQP_ESTATE without parametric
+ * data. */
+int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out);
+
 /* ---- Serving (continuous batching; batched engine only).
  * The handle's `batch` instances are slots. A slot holds one request from its admission until
  * a final status; finished and idle slots cost nothing in a step. Warm starts follow the

@@ -28,12 +28,17 @@ constexpr int kBatchBlock = 256;
 
 struct BatchArgs {
   int n, m, L, B;
-  long ldk;                 // leading dimension (elements) of weights and operands, multiple of kTileK
+  // K-blocked layout of every GEMM operand: element (row, c) of a matrix with `rows` padded
+  // rows is at ((c / kTileK) * rows + row) * kTileK + c % kTileK, so one K stage of a tile is
+  // one contiguous block. ldk = columns (multiple of kTileK, with zero padding).
+  long ldk;
+  long lpad;                // padded rows of the weight and check matrices (multiple of kTileN)
+  long bpad;                // padded rows (list positions) of the operands V and CV
   int prec;                 // BatchPrec
-  const void* Wa;           // FP32 layer matrices, or BF16 high parts: n_rho x L x ldk
+  const void* Wa;           // FP32 layer matrices, or BF16 high parts: n_rho blocked lpad x ldk
   const void* Wb;           // BF16 low parts (kBatchBF16x3), else null
   long w_stride;            // elements between penalty matrices
-  const void* Ca;           // check matrix [P, A'; A, 0], same format (L x ldk)
+  const void* Ca;           // check matrix [P, A'; A, 0], same format (blocked lpad x ldk)
   const void* Cb;
   const float* Q;           // B x n
   const float* Lo;          // B x m
@@ -48,9 +53,11 @@ struct BatchArgs {
   float* X;                 // state B x n
   float* Z;                 // state B x m
   float* Y;                 // state B x m
-  void* Va;                 // layer inputs, 2 parities x B x ldk (FP32, or BF16 high)
+  // operand rows are list positions (the bucketed order of the running instances), so a tile's
+  // rows are contiguous
+  void* Va;                 // layer inputs, 2 parities x blocked bpad x ldk (FP32, or BF16 high)
   void* Vb;                 // BF16 low parts
-  void* CVa;                // check operand [x; y], B x ldk
+  void* CVa;                // check operand [x; y], blocked bpad x ldk
   void* CVb;
   int* jb;                  // B penalty indices (kept for running and warm-admitted slots)
   int* status;              // B slot states (kSlot* below, or a final status), persistent
@@ -61,6 +68,7 @@ struct BatchArgs {
   int max_checks;
   unsigned long long* norms;  // B x 8 (ordered FP64 bit patterns), zero at launch
   int* lists;               // B instance ids grouped by penalty index
+  int* pos_of;              // B list position of each running instance
   int* mtiles;              // per M-tile: {j, offset, count}, up to B/kTileM + n_rho entries, + count
   unsigned* bar;            // grid barrier words (zero at launch)
   const int* abort_flag;    // host-mapped
@@ -87,10 +95,11 @@ hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m
                        int* status, float* stage, hipStream_t st);
 hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st);
 
-// FP64 -> (BF16 high, BF16 low) split of a row-major matrix into ldk-padded rows.
-hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long ldk,
+// FP64 row-major rows x cols -> K-blocked lpad x ldk (zero padded): BF16 high and low parts,
+// or FP32.
+hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long lpad, long ldk,
                       hipStream_t st);
-// FP64 -> FP32 copy into ldk-padded rows.
-hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long ldk, hipStream_t st);
+hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long lpad, long ldk,
+                   hipStream_t st);
 
 }  // namespace rqp

@@ -86,6 +86,9 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_float(unsigned short h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
+// Element (row, c) of a K-blocked operand with `rows` padded rows.
+__device__ __forceinline__ long opidx(long rows, long row, int c) { return ((long)(c / TK) * rows + row) * TK + (c % TK); }
+
 template <int PREC>
 __device__ __forceinline__ void put_operand(void* va, void* vb, long idx, float v) {
   if constexpr (PREC == kBatchBF16x3) {
@@ -140,26 +143,27 @@ struct Frag<kBatchF32> {
 
 // Loads never branch: a row outside the tile's valid range reads a valid dummy row (its
 // products land in accumulator rows or columns that are discarded).
+// aoff / boff: offsets of the thread's rows inside a K block; as / bs: elements per K block.
 template <int PREC>
 __device__ __forceinline__ void fetch(Frag<PREC>& f, const void* Aa, const void* Ab, const void* Ba, const void* Bb,
                                       const long (&aoff)[Smem<PREC>::kRowsPerThread],
-                                      const long (&boff)[Smem<PREC>::kRowsPerThread], int stage) {
+                                      const long (&boff)[Smem<PREC>::kRowsPerThread], long as, long bs, int stage) {
   constexpr int RPT = Smem<PREC>::kRowsPerThread;
   if constexpr (PREC == kBatchBF16x3) {
-    const long k0 = (long)stage * TK + (threadIdx.x % 4) * 8;
+    const long ka = (long)stage * as + (threadIdx.x % 4) * 8, kb = (long)stage * bs + (threadIdx.x % 4) * 8;
 #pragma unroll
     for (int h = 0; h < RPT; ++h) {
-      f.a[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Aa) + aoff[h] + k0);
-      f.a[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ab) + aoff[h] + k0);
-      f.b[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ba) + boff[h] + k0);
-      f.b[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Bb) + boff[h] + k0);
+      f.a[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Aa) + aoff[h] + ka);
+      f.a[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ab) + aoff[h] + ka);
+      f.b[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ba) + boff[h] + kb);
+      f.b[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Bb) + boff[h] + kb);
     }
   } else {
-    const long k0 = (long)stage * TK + (threadIdx.x % 8) * 4;
+    const long ka = (long)stage * as + (threadIdx.x % 8) * 4, kb = (long)stage * bs + (threadIdx.x % 8) * 4;
 #pragma unroll
     for (int h = 0; h < RPT; ++h) {
-      f.a[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Aa) + aoff[h] + k0);
-      f.b[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Ba) + boff[h] + k0);
+      f.a[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Aa) + aoff[h] + ka);
+      f.b[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Ba) + boff[h] + kb);
     }
   }
 }
@@ -249,33 +253,41 @@ __device__ __forceinline__ void compute(const Smem<PREC>& sm, int buf, floatx16 
 }
 
 // acc = sum over k in [kb, ke) of A[row][k] B[col][k]. Stages of TK columns are double
-// buffered in LDS; the global loads run two stages ahead of the products.
+// buffered in LDS and fetched into a ring of kRing register stages, so that the global loads
+// run kRing - 1 stages ahead of the products. The stage count is rounded up to a multiple of
+// kRing and every fetch is issued unconditionally (past the end it re-reads the last stage),
+// so every step has the same instruction stream and the wait before an LDS store covers the
+// loads of that stage only; a scheduling barrier keeps each fetch at the top of its step. The
+// extra stages lie in the operands' zero padding (or are masked).
+constexpr int kRing = 4;
 template <int PREC, bool MASK>
 __device__ __forceinline__ void tile_gemm(Smem<PREC>& sm, const void* Aa, const void* Ab, const void* Ba,
                                           const void* Bb, const long (&aoff)[Smem<PREC>::kRowsPerThread],
-                                          const long (&boff)[Smem<PREC>::kRowsPerThread], int kb, int ke,
-                                          floatx16 (&acc)[2][2]) {
+                                          const long (&boff)[Smem<PREC>::kRowsPerThread], long as, long bs, int kb,
+                                          int ke, floatx16 (&acc)[2][2]) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
-  const int s0 = kb / TK, ns = (ke + TK - 1) / TK - s0;
-  Frag<PREC> f0, f1;
-  fetch<PREC>(f0, Aa, Ab, Ba, Bb, aoff, boff, s0);
-  if (ns > 1) fetch<PREC>(f1, Aa, Ab, Ba, Bb, aoff, boff, s0 + 1);
-  stash<PREC, MASK>(sm, 0, f0, s0, kb, ke);
+  const int s0 = kb / TK;
+  int ns = (ke + TK - 1) / TK - s0;
+  ns = (ns + kRing - 1) / kRing * kRing;
+  const int last = s0 + ns - 1;
+  Frag<PREC> f[kRing];
+#pragma unroll
+  for (int r = 0; r < kRing; ++r) fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, s0 + r);
+  stash<PREC, MASK>(sm, 0, f[0], s0, kb, ke);
   __syncthreads();
-  for (int s = 0; s < ns; s += 2) {
-    // stage s is in LDS buffer 0, stage s + 1 in flight in f1
-    if (s + 2 < ns) fetch<PREC>(f0, Aa, Ab, Ba, Bb, aoff, boff, s0 + s + 2);
-    compute<PREC>(sm, 0, acc);
-    if (s + 1 < ns) stash<PREC, MASK>(sm, 1, f1, s0 + s + 1, kb, ke);
-    __syncthreads();
-    if (s + 1 >= ns) break;
-    if (s + 3 < ns) fetch<PREC>(f1, Aa, Ab, Ba, Bb, aoff, boff, s0 + s + 3);
-    compute<PREC>(sm, 1, acc);
-    if (s + 2 < ns) stash<PREC, MASK>(sm, 0, f0, s0 + s + 2, kb, ke);
-    __syncthreads();
+  for (int s = s0; s < s0 + ns; s += kRing) {
+#pragma unroll
+    for (int r = 0; r < kRing; ++r) {
+      // stage s + r is in LDS buffer r & 1; f[r] is free again
+      fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, min(s + r + kRing, last));
+      __builtin_amdgcn_sched_barrier(0);
+      compute<PREC>(sm, r & 1, acc);
+      stash<PREC, MASK>(sm, (r + 1) & 1, f[(r + 1) % kRing], min(s + r + 1, last), kb, ke);
+      __syncthreads();
+    }
   }
 }
 
@@ -298,62 +310,153 @@ __device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt
 #pragma unroll
   for (int h = 0; h < RPT; ++h) {
     const int r = loader_row<PREC>(h);
-    // rows past the tile's instances or past L read row 0 (their results are discarded)
-    aoff[h] = abase + (r < mt.cnt ? (long)a.lists[mt.off + r] * a.ldk : 0);
-    const int row = nt * TN + r;
-    boff[h] = bbase + (row < a.L ? (long)row * a.ldk : 0);
+    // operand rows are list positions, matrix rows are rows; rows past the tile's instances or
+    // past L hold other instances or zero padding (their results are discarded)
+    aoff[h] = abase + (long)(mt.off + r) * TK;
+    boff[h] = bbase + (long)(nt * TN + r) * TK;
   }
 }
 
-// Counting sort of the slots in state `want` by penalty index into lists[] and the M-tile
-// table (one workgroup; stable, so the order inside a bucket is by slot id). Before counting,
-// slots in state `from` (if >= 0) move to state `to`.
+// XCD-aware walk over the grid of (M tile, N tile) pairs with N tiles in [n_begin, n_end).
+// Workgroup g runs on XCD g % 8 (consecutive workgroups of a launch go round-robin over the
+// eight XCDs); each XCD takes a contiguous range of M tiles (of N tiles when there are fewer M
+// tiles than XCDs) and walks it with the M index fastest, so that the workgroups of one XCD
+// work on a compact block of tiles at a time and share operand stages through its L2.
+struct TileWalk {
+  int per, count, mx, m0, n0, nmt;
+  bool by_m;
+  __device__ TileWalk(int nmt_, int n_begin, int n_end) : nmt(nmt_) {
+    const int G = gridDim.x, x = blockIdx.x % 8, nn = n_end - n_begin;
+    if (G % 8 != 0) {  // no XCD structure assumed: plain round robin
+      per = G;
+      by_m = true;
+      m0 = 0;
+      mx = nmt;
+      n0 = n_begin;
+      count = nmt * nn;
+      return;
+    }
+    per = G / 8;
+    by_m = nmt >= 8;
+    if (by_m) {
+      m0 = x * nmt / 8;
+      mx = (x + 1) * nmt / 8 - m0;
+      n0 = n_begin;
+      count = mx * nn;
+    } else {
+      const int nb = n_begin + x * nn / 8, ne = n_begin + (x + 1) * nn / 8;
+      m0 = 0;
+      mx = nmt;
+      n0 = nb;
+      count = nmt * (ne - nb);
+    }
+  }
+  __device__ int first() const { return gridDim.x % 8 != 0 ? blockIdx.x : blockIdx.x / 8; }
+  __device__ int mt(int j) const { return m0 + j % mx; }
+  __device__ int nt(int j) const { return n0 + j / mx; }
+};
+
+// Bucket sort of the slots in state `want` by penalty index into lists[] and the M-tile table
+// (one workgroup). Before counting, slots in state `from` (if >= 0) move to state `to`. Slots
+// are read in batches of kU per thread so that their loads overlap. The order inside a bucket
+// is not fixed (atomic cursors); an instance's arithmetic does not depend on it.
+constexpr int kU = 8;
 __device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */, int want, int from, int to) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, B = a.B;
   constexpr int kMaxRhoB = 64;
+  __shared__ int s_cur[kMaxRhoB];
   if (tid < kMaxRhoB) s_count[tid] = 0;
-  // per-thread contiguous chunk of slots
-  const int chunk = (a.B + BS - 1) / BS;
-  const int b0 = min(a.B, tid * chunk), b1 = min(a.B, b0 + chunk);
-  if (from >= 0)
-    for (int b = b0; b < b1; ++b)
-      if (a.status[b] == from) a.status[b] = to;
   __syncthreads();
-  for (int b = b0; b < b1; ++b)
-    if (a.status[b] == want) atomicAdd(&s_count[a.jb[b]], 1);
+  for (int base = 0; base < B; base += BS * kU) {
+    int st[kU], jj[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = min(base + u * BS + tid, B - 1);
+      st[u] = a.status[b];
+      jj[u] = a.jb[b];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = base + u * BS + tid;
+      if (b >= B) continue;
+      if (from >= 0 && st[u] == from) {
+        a.status[b] = to;
+        st[u] = to;
+      }
+      if (st[u] == want) atomicAdd(&s_count[jj[u]], 1);
+    }
+  }
   __syncthreads();
-  __shared__ int s_base[kMaxRhoB];
   if (tid == 0) {
     int off = 0, nt = 0;
     MTile* mt = reinterpret_cast<MTile*>(a.mtiles + 1);
     for (int j = 0; j < a.n_rho; ++j) {
-      s_base[j] = off;
+      s_cur[j] = off;
       for (int c = 0; c < s_count[j]; c += TM) mt[nt++] = MTile{j, off + c, min(TM, s_count[j] - c)};
       off += s_count[j];
     }
     a.mtiles[0] = nt;
   }
   __syncthreads();
-  // stable scatter: positions by an exclusive scan over threads, one bucket at a time
-  __shared__ int s_scan[BS];
-  for (int j = 0; j < a.n_rho; ++j) {
-    int mine = 0;
-    for (int b = b0; b < b1; ++b) mine += (a.status[b] == want && a.jb[b] == j);
-    s_scan[tid] = mine;
-    __syncthreads();
-    if (tid == 0) {
-      int acc = s_base[j];
-      for (int t = 0; t < BS; ++t) {
-        const int c = s_scan[t];
-        s_scan[t] = acc;
-        acc += c;
+  for (int base = 0; base < B; base += BS * kU) {
+    int st[kU], jj[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = min(base + u * BS + tid, B - 1);
+      st[u] = a.status[b];
+      jj[u] = a.jb[b];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = base + u * BS + tid;
+      if (b < B && st[u] == want) {
+        const int pos = atomicAdd(&s_cur[jj[u]], 1);
+        a.lists[pos] = b;
+        a.pos_of[b] = pos;
       }
     }
-    __syncthreads();
-    int pos = s_scan[tid];
-    for (int b = b0; b < b1; ++b)
-      if (a.status[b] == want && a.jb[b] == j) a.lists[pos++] = b;
-    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// Layer input w = [sigma x - q; rho z - y] of every running slot into operand parity `par`,
+// kU elements per thread at a time (their loads overlap).
+template <int PREC>
+__device__ void layer_input(const BatchArgs& a, const float* s_rho, long vofs) {
+  const int n = a.n, m = a.m, L = a.L;
+  const long total = (long)a.B * L, gstride = (long)gridDim.x * BS;
+  const float sigma = (float)a.sigma, eqs = (float)a.rho_eq_scale;
+  for (long base = (long)blockIdx.x * BS + threadIdx.x; base < total; base += gstride * kU) {
+    int st[kU], jj[kU], ps[kU];
+    float u0[kU], u1[kU];
+    unsigned char e[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long el = min(base + u * gstride, total - 1);
+      const int b = (int)(el / L), r = (int)(el % L);
+      const bool xr = r < n;
+      const long xi = (long)b * n + (xr ? r : 0), zi = (long)b * m + (xr ? 0 : r - n);
+      st[u] = a.status[b];
+      jj[u] = a.jb[b];
+      ps[u] = a.pos_of[b];
+      e[u] = a.eq[xr ? 0 : r - n];
+      u0[u] = xr ? a.X[xi] : a.Z[zi];
+      u1[u] = xr ? a.Q[xi] : a.Y[zi];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long el = base + u * gstride;
+      if (el >= total || st[u] != ST_RUNNING) continue;
+      const int b = (int)(el / L), r = (int)(el % L);
+      float w;
+      if (r < n) {
+        w = sigma * u0[u] - u1[u];
+      } else {
+        const float rho = s_rho[jj[u]] * (e[u] ? eqs : 1.0f);
+        w = rho * u0[u] - u1[u];
+      }
+      put_operand<PREC>(a.Va, a.Vb, vofs + opidx(a.bpad, ps[u], r), w);
+    }
   }
 }
 
@@ -362,16 +465,28 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Smem<PREC>& sm = *reinterpret_cast<Smem<PREC>*>(smem_raw);
   __shared__ int s_count[64];
+  __shared__ int s_list[TM];   // instance ids of the current M tile
+  __shared__ float s_rho[64];  // grid penalties in FP32
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
   const int G = gridDim.x, g = blockIdx.x;
-  const int n = a.n, L = a.L, B = a.B;
+  const int n = a.n, m = a.m, L = a.L, B = a.B;
   const long ldk = a.ldk;
-  const long vpar = (long)B * ldk;  // elements per parity of V
+  const long vpar = a.bpad * ldk;  // elements per parity of V
+  const long as = a.bpad * TK, bs = a.lpad * TK;  // elements per K block of operands / matrices
   const int ntiles_n = (L + TN - 1) / TN;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha), sigma = (float)a.sigma;
+  const float eqs = (float)a.rho_eq_scale;
   unsigned epoch = 0;
   const long gtid = (long)g * BS + tid, gstride = (long)G * BS;
+  if (tid < a.n_rho) s_rho[tid] = (float)a.grid[tid];
+
+  // M tile t's instance ids into s_list (entries past the tile's count repeat its first id)
+  auto load_list = [&](const MTile& mt) {
+    __syncthreads();  // the previous tile is done with s_list
+    if (tid < TM) s_list[tid] = a.lists[mt.off + (tid < mt.cnt ? tid : 0)];
+    __syncthreads();
+  };
 
   // ---- admitted slots: cold ones start from zero, warm ones from their x and y with z = A x
   for (long b = gtid; b < B; b += gstride) {
@@ -381,33 +496,60 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) a.norms[b * 8 + q] = 0ull;
   }
-  for (long e = gtid; e < (long)B * n; e += gstride)
-    if (a.status[e / n] == kSlotAdmitCold) a.X[e] = 0.0f;
-  for (long e = gtid; e < (long)B * a.m; e += gstride)
-    if (a.status[e / a.m] == kSlotAdmitCold) {
-      a.Z[e] = 0.0f;
-      a.Y[e] = 0.0f;
+  for (long base = gtid; base < (long)B * L; base += gstride * kU) {
+    int st[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) st[u] = a.status[min(base + u * gstride, (long)B * L - 1) / L];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long el = base + u * gstride;
+      if (el >= (long)B * L || st[u] != kSlotAdmitCold) continue;
+      const int b = (int)(el / L), r = (int)(el % L);
+      if (r < n) {
+        a.X[(long)b * n + r] = 0.0f;
+      } else {
+        a.Z[(long)b * m + (r - n)] = 0.0f;
+        a.Y[(long)b * m + (r - n)] = 0.0f;
+      }
     }
-  for (long e = gtid; e < (long)B * L; e += gstride) {
-    const int b = (int)(e / L), r = (int)(e % L);
-    if (a.status[b] == kSlotAdmitWarm)
-      put_operand<PREC>(a.CVa, a.CVb, (long)b * ldk + r, r < n ? a.X[(long)b * n + r] : a.Y[(long)b * a.m + (r - n)]);
   }
   if (!grid_barrier(a.bar, ++epoch)) return;
   if (g == 0) build_tiles(a, s_count, kSlotAdmitWarm, kSlotAdmitCold, ST_RUNNING);
   if (!grid_barrier(a.bar, ++epoch)) return;
   if (a.mtiles[0] > 0) {
-    // warm start (Sec. II-B): z = A x from the z rows of the check product over K in [0, n)
+    // warm start (Sec. II-B): check operand [x; y] of the warm slots at their list positions,
+    // then z = A x from the z rows of the check product over K in [0, n)
+    for (long base = gtid; base < (long)B * L; base += gstride * kU) {
+      int st[kU], ps[kU];
+      float xv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const long el = min(base + u * gstride, (long)B * L - 1);
+        const int b = (int)(el / L), r = (int)(el % L);
+        st[u] = a.status[b];
+        ps[u] = a.pos_of[b];
+        xv[u] = r < n ? a.X[(long)b * n + r] : a.Y[(long)b * m + (r - n)];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const long el = base + u * gstride;
+        if (el >= (long)B * L || st[u] != kSlotAdmitWarm) continue;
+        put_operand<PREC>(a.CVa, a.CVb, opidx(a.bpad, ps[u], (int)(el % L)), xv[u]);
+      }
+    }
+    if (!grid_barrier(a.bar, ++epoch)) return;
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
     const int nt0 = n / TN;  // first row tile holding constraint rows
-    for (int t = g; t < nmt * (ntiles_n - nt0); t += G) {
-      const MTile mt = mts[t % nmt];
-      const int nt = nt0 + t / nmt;
+    const TileWalk tw(nmt, nt0, ntiles_n);
+    for (int t = tw.first(); t < tw.count; t += tw.per) {
+      const MTile mt = mts[tw.mt(t)];
+      const int nt = tw.nt(t);
+      load_list(mt);
       long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
       tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
       floatx16 acc[2][2];
-      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc);
+      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -417,7 +559,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int ti = acc_row(wm, i, v, lane);
-            if (ti < mt.cnt) a.Z[(long)a.lists[mt.off + ti] * a.m + (r - n)] = acc[i][j][v];
+            if (ti < mt.cnt) a.Z[(long)s_list[ti] * m + (r - n)] = acc[i][j][v];
           }
         }
     }
@@ -427,20 +569,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   if (!grid_barrier(a.bar, ++epoch)) return;
   if (a.mtiles[0] == 0) return;  // nothing to run
   // ---- first layer input V_1 (parity 1)
-  for (long e = gtid; e < (long)B * L; e += gstride) {
-    const int b = (int)(e / L), r = (int)(e % L);
-    if (a.status[b] != ST_RUNNING) continue;
-    float w;
-    if (r < n) {
-      w = sigma * a.X[(long)b * n + r] - a.Q[(long)b * n + r];
-    } else {
-      const int i = r - n;
-      const long zi = (long)b * a.m + i;
-      const float rho = (float)(a.grid[a.jb[b]] * (a.eq[i] ? a.rho_eq_scale : 1.0));
-      w = rho * a.Z[zi] - a.Y[zi];
-    }
-    put_operand<PREC>(a.Va, a.Vb, vpar + (long)b * ldk + r, w);
-  }
+  layer_input<PREC>(a, s_rho, vpar);
   if (!grid_barrier(a.bar, ++epoch)) return;
 
   const int ci = a.check_interval;
@@ -449,52 +578,65 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
     const long vin = (long)(k & 1) * vpar, vout = (long)((k + 1) & 1) * vpar;
+    const TileWalk tw(nmt, 0, ntiles_n);
 
     // ---- layer GEMM + fused update
-    for (int t = g; t < nmt * ntiles_n; t += G) {
-      const MTile mt = mts[t % nmt];
-      const int nt = t / nmt;
+    for (int t = tw.first(); t < tw.count; t += tw.per) {
+      const MTile mt = mts[tw.mt(t)];
+      const int nt = tw.nt(t);
+      load_list(mt);
       long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
       tile_offsets<PREC>(a, mt, nt, vin, (long)mt.j * a.w_stride, aoff, boff);
       floatx16 acc[2][2];
-      tile_gemm<PREC, false>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, 0, L, acc);
-      const double rho_bar = a.grid[mt.j];
+      tile_gemm<PREC, false>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, as, bs, 0, L, acc);
+      const float rho_bar = s_rho[mt.j];
+      // epilogue, one 32 x 32 block at a time: the 16 elements' state loads are issued
+      // together, then the row-local update (relaxation, clamp, dual) and the stores
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int r = nt * TN + acc_col(wn, j, lane);
-          if (r >= L) continue;
+          const bool rin = r < L, xr = r < n;
+          const int ri = xr ? r : (rin ? r - n : 0);  // x index, or constraint index
+          const float rho = rho_bar * (!xr && a.eq[ri] ? eqs : 1.0f);
+          float u0[16], u1[16], u2[16], u3[16];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const long b = s_list[acc_row(wm, i, v, lane)];
+            const long xi = b * n + (xr ? ri : 0), zi = b * m + (xr ? 0 : ri);
+            u0[v] = xr ? a.X[xi] : a.Z[zi];
+            u1[v] = xr ? a.Q[xi] : a.Y[zi];
+            u2[v] = a.Lo[zi];
+            u3[v] = a.Up[zi];
+          }
+          if (!rin) continue;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int ti = acc_row(wm, i, v, lane);
             if (ti >= mt.cnt) continue;
-            const int b = a.lists[mt.off + ti];
+            const long b = s_list[ti];
             const float s = acc[i][j][v];
             float w, cv;
-            if (r < n) {
-              const long xi = (long)b * n + r;
-              const float x = alpha * s + oma * a.X[xi];
-              a.X[xi] = x;
-              w = sigma * x - a.Q[xi];
+            if (xr) {
+              const float x = alpha * s + oma * u0[v];
+              a.X[b * n + ri] = x;
+              w = sigma * x - u1[v];
               cv = x;
             } else {
-              const int ii = r - n;
-              const long zi = (long)b * a.m + ii;
-              const float rho = (float)(rho_bar * (a.eq[ii] ? a.rho_eq_scale : 1.0));
-              const float t2 = alpha * s + oma * a.Z[zi] + a.Y[zi] / rho;
-              const float lo = a.Lo[zi], up = a.Up[zi];
-              const float zn = t2 < lo ? lo : (t2 > up ? up : t2);
+              const float t2 = alpha * s + oma * u0[v] + u1[v] / rho;
+              const float zn = t2 < u2[v] ? u2[v] : (t2 > u3[v] ? u3[v] : t2);
               const float yn = rho * (t2 - zn);
-              a.Z[zi] = zn;
-              a.Y[zi] = yn;
+              a.Z[b * m + ri] = zn;
+              a.Y[b * m + ri] = yn;
               w = rho * zn - yn;
               cv = yn;
             }
+            const long oi = opidx(a.bpad, mt.off + ti, r);
             if (is_check)
-              put_operand<PREC>(a.CVa, a.CVb, (long)b * ldk + r, cv);
+              put_operand<PREC>(a.CVa, a.CVb, oi, cv);
             else
-              put_operand<PREC>(a.Va, a.Vb, vout + (long)b * ldk + r, w);
+              put_operand<PREC>(a.Va, a.Vb, vout + oi, w);
           }
         }
     }
@@ -502,22 +644,35 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (!is_check) continue;
 
     // ---- check GEMM: [P, A'; A, 0] [x; y]; K split at n keeps P x and A'y apart
-    for (int t = g; t < nmt * ntiles_n; t += G) {
-      const MTile mt = mts[t % nmt];
-      const int nt = t / nmt;
+    for (int t = tw.first(); t < tw.count; t += tw.per) {
+      const MTile mt = mts[tw.mt(t)];
+      const int nt = tw.nt(t);
+      load_list(mt);
       long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
       tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
       floatx16 acc_p[2][2], acc_a[2][2];
-      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, 0, n, acc_p);  // P x (x rows), A x (z rows)
-      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, n, L, acc_a);  // A'y (x rows), 0 (z rows)
+      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc_p);  // P x, A x
+      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, n, L, acc_a);  // A'y, 0
       // per instance (accumulator row) maxima over this tile's rows
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        // q (x rows) or z (z rows) of the block's 2 x 16 elements, loaded together
+        float ext[2][16];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int r = nt * TN + acc_col(wn, j, lane);
+          const bool xr = r < n;
+          const int ri = xr ? r : (r < L ? r - n : 0);
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const long b = s_list[acc_row(wm, i, v, lane)];
+            ext[j][v] = xr ? a.Q[b * n + ri] : a.Z[b * m + ri];
+          }
+        }
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int ti = acc_row(wm, i, v, lane);
           const bool valid_i = ti < mt.cnt;
-          const int b = valid_i ? a.lists[mt.off + ti] : 0;
           uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
@@ -525,7 +680,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
             if (!valid_i || r >= L) continue;
             const double pp = (double)acc_p[i][j][v], pa = (double)acc_a[i][j][v];
             if (r < n) {
-              const double q = (double)a.Q[(long)b * n + r];
+              const double q = (double)ext[j][v];
               const double rd = pp + pa + q;  // P x + A'y + q
               const uint64_t vrd = abs_bits(rd), vpx = abs_bits(pp), vat = abs_bits(pa), vq = abs_bits(q);
               nb[N_RD] = vrd > nb[N_RD] ? vrd : nb[N_RD];
@@ -533,7 +688,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
               nb[N_ATY] = vat > nb[N_ATY] ? vat : nb[N_ATY];
               nb[N_Q] = vq > nb[N_Q] ? vq : nb[N_Q];
             } else {
-              const double z = (double)a.Z[(long)b * a.m + (r - n)];
+              const double z = (double)ext[j][v];
               const uint64_t vrp = abs_bits(pp - z), vax = abs_bits(pp), vz = abs_bits(z);
               nb[N_RP] = vrp > nb[N_RP] ? vrp : nb[N_RP];
               nb[N_AX] = vax > nb[N_AX] ? vax : nb[N_AX];
@@ -552,11 +707,13 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
             nb[q] = x;
           }
           if (valid_i && (lane % 32) == 0) {
+            const long b = s_list[ti];
 #pragma unroll
             for (int q = 0; q < 7; ++q)
-              if (nb[q]) atomicMax(a.norms + (long)b * 8 + q, (unsigned long long)nb[q]);
+              if (nb[q]) atomicMax(a.norms + b * 8 + q, (unsigned long long)nb[q]);
           }
         }
+      }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
 
@@ -622,23 +779,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (k == a.steps) break;  // the next launch rebuilds the layer input from the state
 
     // ---- next layer input for the instances still running (penalty may have changed)
-    const int nmt2 = a.mtiles[0];
-    for (long e = gtid; e < (long)B * L; e += gstride) {
-      const int b = (int)(e / L), r = (int)(e % L);
-      if (a.status[b] != ST_RUNNING) continue;
-      float w;
-      if (r < n) {
-        const long xi = (long)b * n + r;
-        w = sigma * a.X[xi] - a.Q[xi];
-      } else {
-        const int ii = r - n;
-        const long zi = (long)b * a.m + ii;
-        const float rho = (float)(a.grid[a.jb[b]] * (a.eq[ii] ? a.rho_eq_scale : 1.0));
-        w = rho * a.Z[zi] - a.Y[zi];
-      }
-      put_operand<PREC>(a.Va, a.Vb, vout + (long)b * ldk + r, w);
-    }
-    (void)nmt2;
+    layer_input<PREC>(a, s_rho, vout);
     if (!grid_barrier(a.bar, ++epoch)) return;
   }
   // slots still running carry their iteration count into the next launch
@@ -673,26 +814,34 @@ hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st) 
 }
 
 namespace {
+// one thread per element of the blocked lpad x ldk destination
 __global__ void split_kernel(long rows, int cols, const double* __restrict__ src, long ld_src,
-                             unsigned short* __restrict__ hi, unsigned short* __restrict__ lo, long ldk) {
+                             unsigned short* __restrict__ hi, unsigned short* __restrict__ lo, long lpad, long ldk) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * ldk) return;
-  const long r = idx / ldk;
-  const int c = (int)(idx % ldk);
+  if (idx >= lpad * ldk) return;
+  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
+  const long r = rem / TK;
+  const int c = (int)(blk * TK + rem % TK);
+  if (r >= rows) {
+    hi[idx] = 0;
+    lo[idx] = 0;
+    return;
+  }
   const float v = c < cols ? (float)src[r * ld_src + c] : 0.0f;
   // split the FP64 value: hi from its FP32 rounding, lo from the remaining FP64 difference
   const unsigned short h = bf16_bits(v);
-  const double rem = c < cols ? src[r * ld_src + c] - (double)bf16_float(h) : 0.0;
+  const double diff = c < cols ? src[r * ld_src + c] - (double)bf16_float(h) : 0.0;
   hi[idx] = h;
-  lo[idx] = bf16_bits((float)rem);
+  lo[idx] = bf16_bits((float)diff);
 }
 __global__ void pad_kernel(long rows, int cols, const double* __restrict__ src, long ld_src, float* __restrict__ dst,
-                           long ldk) {
+                           long lpad, long ldk) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * ldk) return;
-  const long r = idx / ldk;
-  const int c = (int)(idx % ldk);
-  dst[idx] = c < cols ? (float)src[r * ld_src + c] : 0.0f;
+  if (idx >= lpad * ldk) return;
+  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
+  const long r = rem / TK;
+  const int c = (int)(blk * TK + rem % TK);
+  dst[idx] = (r < rows && c < cols) ? (float)src[r * ld_src + c] : 0.0f;
 }
 }  // namespace
 
@@ -799,18 +948,19 @@ hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m
   return hipGetLastError();
 }
 
-hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long ldk,
+hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long lpad, long ldk,
                       hipStream_t st) {
-  const long total = rows * ldk;
+  const long total = lpad * ldk;
   hipLaunchKernelGGL(split_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, src, ld_src,
-                     static_cast<unsigned short*>(hi), static_cast<unsigned short*>(lo), ldk);
+                     static_cast<unsigned short*>(hi), static_cast<unsigned short*>(lo), lpad, ldk);
   return hipGetLastError();
 }
 
-hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long ldk, hipStream_t st) {
-  const long total = rows * ldk;
+hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long lpad, long ldk,
+                   hipStream_t st) {
+  const long total = lpad * ldk;
   hipLaunchKernelGGL(pad_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, src, ld_src,
-                     dst, ldk);
+                     dst, lpad, ldk);
   return hipGetLastError();
 }
 

@@ -41,6 +41,14 @@ struct LayerArgs {
   const int* abort_flag;  // host-mapped int, polled at checks
   unsigned* err;        // device word: holds the tag of a solve whose exchange timed out
   int lds_rows;         // rows per block kept in LDS (set by launch_layer from the plan)
+  // optional in-kernel update from an initial state (x0 != null): q = F x0, l = lo - E x0,
+  // u = hi - E x0, written to q, l, u before the iteration starts
+  const double* x0;
+  const double* F;      // n x nx
+  const double* E;      // m x nx
+  const double* plo;    // m
+  const double* phi;    // m
+  int nx;
 };
 
 // Rows per workgroup are at most kMaxRows; the host picks the grid accordingly.

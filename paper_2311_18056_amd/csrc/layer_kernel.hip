@@ -428,6 +428,34 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   if (tid < a.n_rho - 1) rt.mid[tid] = a.mid[tid];
   __syncthreads();
 
+  // update from an initial state (Sec. IV): q = F x0 for x rows, l = lo - E x0 and
+  // u = hi - E x0 for constraint rows, FP64 products, one wave per row of the block; the values
+  // reach the owners through LDS and are written back for later solves
+  __shared__ T upd[kMaxRows][2];
+  if (a.x0) {
+    for (int rr = wave; rr < nrows; rr += NWAVE) {
+      const int R = r0 + rr;
+      const double* arow = R < n ? a.F + (long)R * a.nx : a.E + (long)(R - n) * a.nx;
+      double sv = 0.0;
+      for (int c = lane; c < a.nx; c += kWave) sv = fma(arow[c], a.x0[c], sv);
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) sv += __shfl_xor(sv, off, kWave);
+      if (lane == 0) {
+        if (R < n) {
+          upd[rr][0] = (T)sv;
+          static_cast<T*>(const_cast<void*>(a.q))[R] = (T)sv;
+        } else {
+          const int i = R - n;
+          upd[rr][0] = (T)(a.plo[i] - sv);
+          upd[rr][1] = (T)(a.phi[i] - sv);
+          static_cast<T*>(const_cast<void*>(a.l))[i] = upd[rr][0];
+          static_cast<T*>(const_cast<void*>(a.u))[i] = upd[rr][1];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
   // row-owner state
   RowState<T> rs;
   rs.own = tid < nrows;
@@ -438,12 +466,12 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   bool seq = false;
   if (rs.own) {
     if (rs.xrow) {
-      rs.sq = static_cast<const T*>(a.q)[rs.R];
+      rs.sq = a.x0 ? upd[tid][0] : static_cast<const T*>(a.q)[rs.R];
       if (a.warm) rs.sx = static_cast<const T*>(a.xs)[rs.R];
     } else {
       const int i = rs.R - n;
-      sl = static_cast<const T*>(a.l)[i];
-      su = static_cast<const T*>(a.u)[i];
+      sl = a.x0 ? upd[tid][0] : static_cast<const T*>(a.l)[i];
+      su = a.x0 ? upd[tid][1] : static_cast<const T*>(a.u)[i];
       seq = a.eq[i] != 0;
       if (a.warm) rs.sy = static_cast<const T*>(a.ys)[i];
     }

@@ -91,7 +91,7 @@ struct relu_qp_handle {
   // batched engine
   bool batched = false;
   int bprec = 0;
-  long ldk = 0;
+  long ldk = 0, lpad = 0, bpad = 0;
   void* bWa = nullptr;
   void* bWb = nullptr;
   void* bCa = nullptr;
@@ -106,6 +106,7 @@ struct relu_qp_handle {
   int* bjb = nullptr;
   unsigned long long* bnorms = nullptr;
   int* blists = nullptr;
+  int* bpos = nullptr;
   int* bmtiles = nullptr;
   unsigned* bbar = nullptr;
   int* bstatus = nullptr;   // slot states, persistent across launches
@@ -122,7 +123,7 @@ void free_handle(relu_qp_handle* h) {
                   h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,
                   h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
                   h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
-                  h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage};
+                  h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->abort_h) (void)hipHostFree(h->abort_h);
@@ -317,15 +318,16 @@ int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hip
     const size_t off = j * (size_t)h->w_stride * es;
     if (h->bprec == rqp::kBatchBF16x3)
       HIP_OR_FAIL(rqp::split_bf16(L, L, Wd.d(), L, static_cast<char*>(h->bWa) + off, static_cast<char*>(h->bWb) + off,
-                                  h->ldk, st));
+                                  h->lpad, h->ldk, st));
     else
-      HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, reinterpret_cast<float*>(static_cast<char*>(h->bWa) + off), h->ldk, st));
+      HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, reinterpret_cast<float*>(static_cast<char*>(h->bWa) + off), h->lpad,
+                               h->ldk, st));
   }
   HIP_OR_FAIL(rqp::assemble_check<double>(n, m, P_d.d(), A_d.d(), Wd.d(), L, st));
   if (h->bprec == rqp::kBatchBF16x3)
-    HIP_OR_FAIL(rqp::split_bf16(L, L, Wd.d(), L, h->bCa, h->bCb, h->ldk, st));
+    HIP_OR_FAIL(rqp::split_bf16(L, L, Wd.d(), L, h->bCa, h->bCb, h->lpad, h->ldk, st));
   else
-    HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, static_cast<float*>(h->bCa), h->ldk, st));
+    HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, static_cast<float*>(h->bCa), h->lpad, h->ldk, st));
   int hinfo = 0;
   HIP_OR_FAIL(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OR_FAIL(hipStreamSynchronize(st));
@@ -338,12 +340,17 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   const int n = h->n, m = h->m, L = h->L, B = h->batch;
   h->batched = true;
   h->bprec = h->s.precision == RQP_BF16X3 ? rqp::kBatchBF16x3 : rqp::kBatchF32;
-  h->ldk = (L + rqp::kTileK - 1) / rqp::kTileK * rqp::kTileK;
-  h->w_stride = (long)L * h->ldk;
+  // rows padded to a multiple of the K stage plus four stages (the GEMM may run up to three
+  // stages past the end, into zeros)
+  h->ldk = (L + rqp::kTileK - 1) / rqp::kTileK * rqp::kTileK + 4 * rqp::kTileK;
+  h->lpad = (L + rqp::kTileN - 1) / rqp::kTileN * rqp::kTileN;
+  // list positions of a tile may run up to kTileM past the last running instance
+  h->bpad = ((long)B + rqp::kTileM - 1) / rqp::kTileM * rqp::kTileM + rqp::kTileM;
+  h->w_stride = h->lpad * h->ldk;
   const size_t es = h->bprec == rqp::kBatchBF16x3 ? 2 : 4;
   const size_t nr = h->grid.size();
   const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->w_stride * es;
-  const size_t vbytes = (size_t)B * h->ldk * es;
+  const size_t vbytes = (size_t)h->bpad * h->ldk * es;
   const size_t ntile_max = (size_t)B / rqp::kTileM + nr + 1;
   auto al = [](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 8) == hipSuccess; };
   const bool two = h->bprec == rqp::kBatchBF16x3;
@@ -352,6 +359,7 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
       !al((void**)&h->bY, (size_t)B * m * 4) || !al(&h->bVa, 2 * vbytes) || (two && !al(&h->bVb, 2 * vbytes)) ||
       !al(&h->bCVa, vbytes) || (two && !al(&h->bCVb, vbytes)) || !al((void**)&h->bjb, (size_t)B * 4) ||
       !al((void**)&h->bnorms, (size_t)B * 8 * 8) || !al((void**)&h->blists, (size_t)B * 4) ||
+      !al((void**)&h->bpos, (size_t)B * 4) ||
       !al((void**)&h->bmtiles, (1 + 3 * ntile_max) * 4) || !al((void**)&h->bbar, 1024 * 4) ||
       !al(&h->q, (size_t)B * n * 4) || !al(&h->l, (size_t)B * m * 4) || !al(&h->u, (size_t)B * m * 4) ||
       !al((void**)&h->bstatus, (size_t)B * 4) || !al((void**)&h->biter, (size_t)B * 4) ||
@@ -395,6 +403,8 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.L = h->L;
   a.B = B;
   a.ldk = h->ldk;
+  a.lpad = h->lpad;
+  a.bpad = h->bpad;
   a.prec = h->bprec;
   a.Wa = h->bWa;
   a.Wb = h->bWb;
@@ -434,6 +444,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.max_checks = h->s.max_iter / h->s.check_interval + (h->s.max_iter % h->s.check_interval ? 1 : 0);
   a.norms = h->bnorms;
   a.lists = h->blists;
+  a.pos_of = h->bpos;
   a.mtiles = h->bmtiles;
   a.bar = h->bbar;
   a.abort_flag = h->abort_d;
@@ -730,12 +741,22 @@ int relu_qp_set_warm(relu_qp_handle* h, int enabled) {
   return RQP_OK;
 }
 
-int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
+}  // extern "C"
+
+namespace {
+// One persistent launch of the online loop; with x0, the launch first forms q, l, u from it.
+int solve_impl(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
     return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (h->batched) return solve_batched(h, st, out);
+  if (x0 && !h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
+  if (h->batched) {
+    if (x0) HIP_OR_FAIL(rqp::mpc_vectors<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
+                                                static_cast<float*>(h->q), static_cast<float*>(h->l),
+                                                static_cast<float*>(h->u), st));
+    return solve_batched(h, st, out);
+  }
   const uint32_t span = (uint32_t)h->s.max_iter + 2u;
   if ((uint64_t)h->tag + span >= 0xffffffffull) {
     // restart the tag sequence: clear every exchange word so no stale tag can match
@@ -790,6 +811,12 @@ int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
   a.tag = h->tag;
   a.abort_flag = h->abort_d;
   a.err = h->err;
+  a.x0 = x0;
+  a.F = h->F_d;
+  a.E = h->E_d;
+  a.plo = h->lo_d;
+  a.phi = h->hi_d;
+  a.nx = h->nx;
   hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->plan, h->grid_wg, st)
                                : rqp::launch_layer<float>(a, h->plan, h->grid_wg, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
@@ -797,6 +824,17 @@ int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
   h->warm_pending = false;
   h->have_prev = true;
   return RQP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) { return solve_impl(h, nullptr, stream, out); }
+
+int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out) {
+  if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
+  return solve_impl(h, x0, stream, out);
 }
 
 int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const double* q, const double* l,

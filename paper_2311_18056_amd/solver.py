@@ -142,6 +142,14 @@ class Solver:
         other device result buffers (a ``Result`` from ``result_slots``)."""
         check(lib().relu_qp_solve(self._h, _stream_handle(stream), byref(out if out is not None else self._res)))
 
+    def solve_x0(self, x0: torch.Tensor, stream=None, out: Result | None = None):
+        """Update q, l, u from initial states x0 (float64 cuda, batch x nx) and solve; one launch
+        on the single-instance engine."""
+        if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
+            raise ValueError("x0 must be a contiguous float64 cuda tensor")
+        check(lib().relu_qp_solve_x0(self._h, c_void_p(x0.data_ptr()), _stream_handle(stream),
+                                     byref(out if out is not None else self._res)))
+
     # ------------------------------------------------------------------ serving (batched engine)
     @staticmethod
     def _slot_array(slots):

@@ -253,3 +253,34 @@ def test_abort(rq):
     sol.close()
     assert res["status"] == rq.RQP_ABORTED
     assert 0 < res["iterations"] < 2_000_000 and res["iterations"] % 25 == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_x0_fuses_the_update(rq, c0, prec):
+    """relu_qp_solve_x0 (update from x0 inside the solve launch) gives the bit-identical result
+    of relu_qp_update_x0_device followed by relu_qp_solve, and matches the oracle."""
+    import torch
+
+    prob, x0 = c0
+    xs = 5.0 * x0_batch(prob.nx, 3, 1200)
+    q0, l0, u0 = prob.instance(xs[0])
+    kw = dict(precision=prec, n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=75)
+    a = rq.Solver(prob.P, q0, prob.A, l0, u0, **kw)
+    b = rq.Solver(prob.P, q0, prob.A, l0, u0, **kw)
+    for s in (a, b):
+        s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    for i in range(1, 3):
+        xd = torch.tensor(xs[i], dtype=torch.float64, device="cuda")
+        a.solve_x0(xd)
+        b.update_x0_device(xd)
+        b.solve()
+        ra, rb = a.result(), b.result()
+        assert ra["rho_hist"] == rb["rho_hist"] and ra["iterations"] == rb["iterations"] == 75
+        for name in ("x", "y", "z"):
+            assert np.array_equal(ra[name], rb[name]), (prec, i, name)
+        q, l, u = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, xs[i])
+        ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=75, n_rho=8),
+                           rho_replay=ra["rho_hist"])
+        _compare(ra, ref, TOL[prec])
+    a.close()
+    b.close()
