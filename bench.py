@@ -55,6 +55,27 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(iters_per_solve):
+    """HBM bytes per launch of the layer kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the counters read for a plain copy),
+    or None when the kernel sources changed since the counters were taken or the solves ran a
+    different number of iterations."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "layer_kernel_c1_n1600_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"] or abs(iters_per_solve - rec["iterations_per_dispatch"]) > 1e-9:
+        return None
+    return (rec["fetch_kib_per_dispatch"] * rec["fetch_factor"] + rec["write_kib_per_dispatch"] * rec["write_factor"]) * 1024
+
+
 def cpu_baseline(prob, x0s, budget_s):
     """The FP64 oracle (explicit-inverse layer form) on the host cores, same settings."""
     import oracle
@@ -184,6 +205,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, x0_host[args.warmup:], args.cpu_seconds)
 
+    traffic_bytes = measured_traffic(float(np.mean(it)))
+    avg_launch_s = float(np.mean(kern_ms)) * 1e-3
     out = {
         "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
         "value": solves_per_s,
@@ -217,7 +240,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            # measured HBM bytes per launch (rocprofv3 counters) over the same launch duration
+            "traffic": None if traffic_bytes is None else traffic_bytes / avg_launch_s / 1e9,
+            "traffic_bytes_per_launch": traffic_bytes,
             "kernel": "layer_kernel<float,4,8,8>",
             "alg_bytes_per_unit": bytes_per_unit,
             "avg_launch_us": float(np.mean(kern_ms) * 1e3),
