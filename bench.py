@@ -7,13 +7,17 @@ dense QP with n = 1600 controls and m = 1600 control limits; FP32 iteration with
 residuals; 8 log-spaced penalties 1e-3..1e3; sigma 1e-6, alpha 1.6, eps_abs = eps_rel = 1e-3,
 max 4000 iterations, check every 25. Synthetic, seeded inputs (no dataset).
 
-One step = one QP solve of the whole online path in one persistent kernel launch: the update of
-q, l, u from a new initial state x0, then all iterations, residual checks and penalty switches
-until eps = 1e-3. The x0 of every step are resident in HBM before the timed region starts.
+One step = one QP solve of the whole online path: the update of q, l, u from a new initial
+state x0, then all iterations, residual checks and penalty switches until eps = 1e-3. Steps run
+in persistent launches of --chunk solves each (relu_qp_solve_sequence: every solve reads its
+own x0 and writes its own results; the layer weights stay on chip between the solves of a
+launch). The x0 of every step are resident in HBM before the timed region starts. A separate
+probe times one solve per launch (relu_qp_solve_x0) for the per-solve latency.
 
 Prints one JSON line. `roofline` covers the persistent layer kernel: algorithmic bytes per
-launch = (iterations + checks) * (n^2 + 2 m n) * 4 B, over its average launch duration from
-HIP events recorded on the solve stream around each launch in the timed region.
+launch = sum over its solves of (iterations + checks) * (n^2 + 2 m n) * 4 B, over its average
+launch duration from HIP events recorded on the solve stream around each launch in the timed
+region.
 """
 
 from __future__ import annotations
@@ -43,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
+    ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
+    ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
     ap.add_argument("--workload", choices=["c1", "batch", "serve"], default="c1",
                     help="c1: one instance per solve (the headline); batch: 4096 instances of the same "
                          "family per solve on the matrix cores; serve: continuous batching of MPC requests")
@@ -55,7 +61,7 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(iters_per_solve):
+def measured_traffic(iters_per_solve, solves_per_launch):
     """HBM bytes per launch of the layer kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the counters read for a plain copy),
     or None when the kernel sources changed since the counters were taken or the solves ran a
@@ -71,7 +77,8 @@ def measured_traffic(iters_per_solve):
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    if h.hexdigest()[:16] != rec["source_sha256_16"] or abs(iters_per_solve - rec["iterations_per_dispatch"]) > 1e-9:
+    if (h.hexdigest()[:16] != rec["source_sha256_16"] or abs(iters_per_solve - rec["iterations_per_solve"]) > 1e-9
+            or solves_per_launch != rec["solves_per_dispatch"]):
         return None
     return (rec["fetch_kib_per_dispatch"] * rec["fetch_factor"] + rec["write_kib_per_dispatch"] * rec["write_factor"]) * 1024
 
@@ -144,34 +151,51 @@ def main():
     grid_wg, block = sol.launch()
 
     x0_dev = torch.tensor(x0_host, dtype=torch.float64, device=dev)  # resident before timing
-    slots, results = sol.result_slots(total)
     stream = torch.cuda.current_stream()
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(total)]
-    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(total)]
+    C = max(1, args.chunk)
+    if args.steps % C or args.warmup % C:
+        raise SystemExit("--steps and --warmup must be multiples of --chunk")
+    nl, nw = total // C, args.warmup // C
+    outs = [sol.sequence_slots(C) for _ in range(nl)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
 
-    def step(i):
-        ev1[i].record(stream)
-        sol.solve_x0(x0_dev[i], stream, out=results[i])
-        ev2[i].record(stream)
+    def launch(c):
+        ev1[c].record(stream)
+        sol.solve_sequence(x0_dev[c * C:(c + 1) * C], stream, out=outs[c])
+        ev2[c].record(stream)
 
-    for i in range(args.warmup):
-        step(i)
+    for c in range(nw):
+        launch(c)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.warmup, total):
-        step(i)
+    for c in range(nw, nl):
+        launch(c)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    it = slots["iterations"][args.warmup:].cpu().numpy().astype(np.int64)
-    st = slots["status"][args.warmup:].cpu().numpy()
-    kern_ms = np.array([ev1[i].elapsed_time(ev2[i]) for i in range(args.warmup, total)])
-    step_ms = kern_ms
+    it = torch.cat([o["iterations"] for o in outs[nw:]]).cpu().numpy().astype(np.int64)
+    st = torch.cat([o["status"] for o in outs[nw:]]).cpu().numpy()
+    kern_ms = np.array([ev1[c].elapsed_time(ev2[c]) for c in range(nw, nl)])
     solves_per_s = args.steps / wall
     checks = -(-it // 25)
     bytes_per_unit = (n * n + 2 * m * n) * 4
     alg_bytes = float(np.sum((it + checks) * bytes_per_unit))
     achieved_gbs = alg_bytes / (np.sum(kern_ms) * 1e-3) / 1e9
+
+    # per-solve latency: one solve per launch, arrival of x0 (in HBM) to results written
+    lat_ms = []
+    if args.latency_solves > 0:
+        slots1, res1 = sol.result_slots(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for i in range(args.latency_solves + 10):
+            e0.record(stream)
+            sol.solve_x0(x0_dev[i % total], stream, out=res1[0])
+            e1.record(stream)
+            e1.synchronize()
+            if i >= 10:
+                lat_ms.append(e0.elapsed_time(e1))
+    step_ms = np.array(lat_ms) if lat_ms else np.array([np.nan])
 
     # fixed-iteration probe: per-iteration time of the same kernel without the stopping test
     steady = None
@@ -205,7 +229,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, x0_host[args.warmup:], args.cpu_seconds)
 
-    traffic_bytes = measured_traffic(float(np.mean(it)))
+    traffic_bytes = measured_traffic(float(np.mean(it)), C)
     avg_launch_s = float(np.mean(kern_ms)) * 1e-3
     out = {
         "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
@@ -231,7 +255,8 @@ def main():
         "iters_per_solve": float(np.mean(it)),
         "status_counts": {rq.STATUS_NAMES[int(s)]: int(np.sum(st == s)) for s in np.unique(st)},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                       "kernel_p50": float(np.percentile(kern_ms, 50))},
+                       "note": "one solve per launch, events around the launch"},
+        "solves_per_launch": C,
         "setup_ms": setup_ms,
         "steady_state": steady,
         "roofline": {

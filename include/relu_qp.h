@@ -153,6 +153,15 @@ int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out);
  * data. */
 int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out);
 
+/* `count` solves one after another in ONE launch of the single-instance engine, solve s from
+ * initial state x0s[s*nx ..] (DEVICE FP64, count*nx). The layer weights stay on chip between
+ * the solves. Solve s writes its results at index s of out: x at s*n, y and z at s*m,
+ * iterations/status/rho_index at s, rho_hist/prim_res/dual_res at s*relu_qp_max_checks().
+ * The first solve starts as relu_qp_solve would; with relu_qp_set_warm(h, 1) each later solve
+ * starts warm from the previous one (the receding-horizon use), else cold. Needs parametric
+ * data; RQP_EINVAL if count < 1, on the batched engine, or count*(max_iter+2) >= 2^31. */
+int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out);
+
 /* ---- Serving (continuous batching; batched engine only).
  * The handle's `batch` instances are slots. A slot holds one request from its admission until
  * a final status; finished and idle slots cost nothing in a step. Warm starts follow the

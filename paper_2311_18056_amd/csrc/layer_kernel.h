@@ -25,10 +25,13 @@ struct LayerArgs {
   void* zs;
   void* ys;
   int* js;              // handle state penalty index
-  void* xo;             // caller outputs (device)
+  int count;            // solves run one after another in this launch (>= 1)
+  int chain;            // solves after the first start warm from the previous one
+  int max_checks;       // per-solve stride of rho_hist, prim_res, dual_res
+  void* xo;             // caller outputs (device), count solves: x count*n, z, y count*m
   void* zo;
   void* yo;
-  int* iterations;
+  int* iterations;      // count entries each
   int* status;
   int* rho_index;
   int* rho_hist;        // per check, may be null
@@ -37,12 +40,12 @@ struct LayerArgs {
   uint64_t* xw;         // exchange words: layer input, 2 parities x L x words
   uint64_t* xc;         // exchange words: check vector [x; y], 2 x L x words
   uint64_t* xn;         // exchange words: norm partials, 2 x G x 8 x 2
-  uint32_t tag;         // first tag of this solve (tags tag .. tag + max_iter + 1 are used)
+  uint32_t tag;         // first tag of the launch; solve s uses tag + s (max_iter + 2) onwards
   const int* abort_flag;  // host-mapped int, polled at checks
   unsigned* err;        // device word: holds the tag of a solve whose exchange timed out
   int lds_rows;         // rows per block kept in LDS (set by launch_layer from the plan)
-  // optional in-kernel update from an initial state (x0 != null): q = F x0, l = lo - E x0,
-  // u = hi - E x0, written to q, l, u before the iteration starts
+  // optional in-kernel update from initial states (x0 != null, count x nx): q = F x0,
+  // l = lo - E x0, u = hi - E x0, written to q, l, u before each solve starts
   const double* x0;
   const double* F;      // n x nx
   const double* E;      // m x nx

@@ -137,6 +137,7 @@ struct Cols {
 template <typename T>
 struct RowState {
   T sx, sz, sy, sq;
+  double ax;  // constraint rows: (A x)_i of the current x, carried along the iteration
   int R;
   bool own, xrow;
 };
@@ -212,8 +213,9 @@ struct CheckOut {
 // grid value, Sec. III-C) at iteration k, check number nchk. Every workgroup returns the same
 // result.
 template <typename T, int NC>
-__device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable& rt, RowState<T> rs, int r0,
-                                              int nrows, int k, int nchk, int j) {
+__device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable& rt, RowState<T> rs, int cb,
+                                              int nck, const T* cq, int k, int nchk, int j, uint32_t tag,
+                                              long hoff) {
   __shared__ uint64_t nred[NWAVE][8];
   __shared__ uint64_t nfin[8];
   constexpr int NW = LLWords<T>::kWords;
@@ -223,29 +225,32 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
   CheckOut out{ST_RUNNING, j, true};
 
   // [x; y] to every workgroup
-  const uint32_t ctag = a.tag + (uint32_t)k;
+  const uint32_t ctag = tag + (uint32_t)k;
   uint64_t* xc = a.xc + (long)(nchk & 1) * L * NW;
   if (rs.own) ll_store(xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, ctag);
   Cols<T, NC> cv;
-  const bool ok2 = gather<T, NC>(xc, L, ctag, cv.v, a.err, a.tag);
+  const bool ok2 = gather<T, NC>(xc, L, ctag, cv.v, a.err, tag);
   if (__syncthreads_or(!ok2)) {
     out.ok = false;
     return out;
   }
+  // dual side: rows cb .. cb + nck - 1 of [P, A'] [x; y] (this workgroup's even share of the x
+  // rows, whatever rows it owns in the layer), FP64 accumulation
   double pr, ar;
-  check_rows<T, NC>(a, r0, nrows, cv, pr, ar);
+  check_rows<T, NC>(a, cb, nck, cv, pr, ar);
   uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (rs.own) {
-    if (rs.xrow) {
-      nb[N_RD] = abs_bits(pr + (double)rs.sq + ar);
-      nb[N_PX] = abs_bits(pr);
-      nb[N_ATY] = abs_bits(ar);
-      nb[N_Q] = abs_bits((double)rs.sq);
-    } else {
-      nb[N_RP] = abs_bits(pr - (double)rs.sz);
-      nb[N_AX] = abs_bits(pr);
-      nb[N_Z] = abs_bits((double)rs.sz);
-    }
+  if (tid < nck) {
+    const double qv = (double)cq[tid];
+    nb[N_RD] = abs_bits(pr + qv + ar);
+    nb[N_PX] = abs_bits(pr);
+    nb[N_ATY] = abs_bits(ar);
+    nb[N_Q] = abs_bits(qv);
+  }
+  // primal side: A x is carried by the constraint-row owners (no product needed)
+  if (rs.own && !rs.xrow) {
+    nb[N_RP] = abs_bits(rs.ax - (double)rs.sz);
+    nb[N_AX] = abs_bits(rs.ax);
+    nb[N_Z] = abs_bits((double)rs.sz);
   }
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
@@ -262,13 +267,13 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
       // every kAbortEvery-th check only
       const bool ab = (nchk % kAbortEvery) == kAbortEvery - 1 && a.abort_flag &&
                       __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      v = err_set(a.err, a.tag) ? 2u : (ab ? 1u : 0u);
+      v = err_set(a.err, tag) ? 2u : (ab ? 1u : 0u);
     }
     ll_store_bits64(a.xn + ((long)(nchk & 1) * G * 8 + (long)g * 8 + tid) * 2, v, ctag);
   }
   __syncthreads();
   uint64_t mx;
-  const bool ok3 = gather_norms(a.xn + (long)(nchk & 1) * G * 8 * 2, G * 8, ctag, mx, a.err, a.tag);
+  const bool ok3 = gather_norms(a.xn + (long)(nchk & 1) * G * 8 * 2, G * 8, ctag, mx, a.err, tag);
   // lanes with equal tid % 8 hold the same norm index
 #pragma unroll
   for (int off = 8; off < kWave; off <<= 1) {
@@ -319,9 +324,9 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
       while (jn < a.n_rho - 1 && rh > rt.mid[jn]) ++jn;
     }
     if (g == 0) {
-      if (a.rho_hist) a.rho_hist[nchk] = jn;
-      if (a.prim_res) a.prim_res[nchk] = rp;
-      if (a.dual_res) a.dual_res[nchk] = rd;
+      if (a.rho_hist) a.rho_hist[hoff + nchk] = jn;
+      if (a.prim_res) a.prim_res[hoff + nchk] = rp;
+      if (a.dual_res) a.dual_res[hoff + nchk] = rd;
     }
     decision[0] = st;
     decision[1] = jn;
@@ -334,23 +339,23 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
 }
 
 template <typename T>
-__device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int k, int st, int j) {
+__device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int sv, int k, int st, int j) {
   if (rs.own) {
     if (rs.xrow) {
       static_cast<T*>(a.xs)[rs.R] = rs.sx;
-      static_cast<T*>(a.xo)[rs.R] = rs.sx;
+      static_cast<T*>(a.xo)[(long)sv * a.n + rs.R] = rs.sx;
     } else {
       const int i = rs.R - a.n;
       static_cast<T*>(a.zs)[i] = rs.sz;
       static_cast<T*>(a.ys)[i] = rs.sy;
-      static_cast<T*>(a.zo)[i] = rs.sz;
-      static_cast<T*>(a.yo)[i] = rs.sy;
+      static_cast<T*>(a.zo)[(long)sv * a.m + i] = rs.sz;
+      static_cast<T*>(a.yo)[(long)sv * a.m + i] = rs.sy;
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *a.iterations = k;
-    *a.status = st;
-    *a.rho_index = j;
+    a.iterations[sv] = k;
+    a.status[sv] = st;
+    a.rho_index[sv] = j;
     *a.js = j;
   }
 }
@@ -428,179 +433,214 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   if (tid < a.n_rho - 1) rt.mid[tid] = a.mid[tid];
   __syncthreads();
 
-  // update from an initial state (Sec. IV): q = F x0 for x rows, l = lo - E x0 and
-  // u = hi - E x0 for constraint rows, FP64 products, one wave per row of the block; the values
-  // reach the owners through LDS and are written back for later solves
-  __shared__ T upd[kMaxRows][2];
-  if (a.x0) {
-    for (int rr = wave; rr < nrows; rr += NWAVE) {
-      const int R = r0 + rr;
-      const double* arow = R < n ? a.F + (long)R * a.nx : a.E + (long)(R - n) * a.nx;
-      double sv = 0.0;
-      for (int c = lane; c < a.nx; c += kWave) sv = fma(arow[c], a.x0[c], sv);
-#pragma unroll
-      for (int off = kWave / 2; off > 0; off >>= 1) sv += __shfl_xor(sv, off, kWave);
-      if (lane == 0) {
-        if (R < n) {
-          upd[rr][0] = (T)sv;
-          static_cast<T*>(const_cast<void*>(a.q))[R] = (T)sv;
-        } else {
-          const int i = R - n;
-          upd[rr][0] = (T)(a.plo[i] - sv);
-          upd[rr][1] = (T)(a.phi[i] - sv);
-          static_cast<T*>(const_cast<void*>(a.l))[i] = upd[rr][0];
-          static_cast<T*>(const_cast<void*>(a.u))[i] = upd[rr][1];
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  // row-owner state
+  // Solves s = 0 .. count-1 run one after another in this launch; the weights of the active
+  // penalty stay on chip between them. Solve s uses tags tag0 + s * span, takes its data from
+  // x0 + s * nx (when given) and writes its results at index s of the outputs.
+  const uint32_t span = (uint32_t)a.max_iter + 2u;
+  const int ci = a.check_interval, max_iter = a.max_iter;
   RowState<T> rs;
   rs.own = tid < nrows;
   rs.R = r0 + tid;
   rs.xrow = rs.R < n;
   rs.sx = rs.sz = rs.sy = rs.sq = (T)0;
+  rs.ax = 0.0;
   T sl = 0, su = 0;
   bool seq = false;
-  if (rs.own) {
-    if (rs.xrow) {
-      rs.sq = a.x0 ? upd[tid][0] : static_cast<const T*>(a.q)[rs.R];
-      if (a.warm) rs.sx = static_cast<const T*>(a.xs)[rs.R];
-    } else {
-      const int i = rs.R - n;
-      sl = a.x0 ? upd[tid][0] : static_cast<const T*>(a.l)[i];
-      su = a.x0 ? upd[tid][1] : static_cast<const T*>(a.u)[i];
-      seq = a.eq[i] != 0;
-      if (a.warm) rs.sy = static_cast<const T*>(a.ys)[i];
-    }
-  }
+  if (rs.own && !rs.xrow) seq = a.eq[rs.R - n] != 0;
   int j = a.warm ? *a.js : a.j0;
-  T srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
-  load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
-  __syncthreads();  // fail_flag
+  int lds_j = -1;  // penalty index of the rows now in LDS
+  __shared__ T upd[kMaxRows][2];
+  // this workgroup's share of the x rows for the dual side of the check, and their q
+  const int cb = (int)((long)g * n / G), nck = (int)((long)(g + 1) * n / G) - cb;
+  __shared__ T cq[kMaxRows];
 
-  const uint32_t tag = a.tag;
-  const int ci = a.check_interval, max_iter = a.max_iter;
-  int nchk = 0;
+  for (int sv = 0; sv < a.count; ++sv) {
+    const uint32_t tag = a.tag + (uint32_t)sv * span;
+    const bool warm = sv == 0 ? a.warm != 0 : a.chain != 0;
 
-  // warm start: z = A x (Sec. II-B, warm starting)
-  if (a.warm) {
-    if (rs.own) ll_store(a.xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, tag);
-    Cols<T, NC> cv;
-    const bool ok = gather<T, NC>(a.xc, L, tag, cv.v, a.err, tag);
-    if (__syncthreads_or(!ok)) {
-      if (tid == 0) err_raise(a.err, tag);
-      finish<T>(a, rs, 0, ST_INTERNAL, j);
-      return;
-    }
-    double ax, unused;
-    check_rows<T, NC>(a, r0, nrows, cv, ax, unused);
-    if (rs.own && !rs.xrow) rs.sz = (T)ax;
-  }
-
-  // first layer input w_1
-  {
-    const T sigma = (T)a.sigma;
-    const T w1 = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
-    if (rs.own) ll_store(a.xw + ((long)L + rs.R) * NW, w1, tag + 1u);
-  }
-
-  int k = 0;
-  while (true) {
-    const int kend = (k / ci + 1) * ci < max_iter ? (k / ci + 1) * ci : max_iter;
-    {
-      T wst[NRS][NC];
-      load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
-      const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
-      uint64_t* xw = a.xw;
-      while (k < kend) {
-        ++k;
-        // layer matvec: rows of Wc_j times w_k
-        T wv[NC];
-        const bool ok = gather<T, NC>(xw + (long)(k & 1) * L * NW, L, tag + (uint32_t)k, wv, a.err, tag);
-        if (!ok) fail_flag = 1;
-        // all rows on chip, no per-row branches (rows past the block have zero weights)
-        // all on-chip rows, then one multi-row wave reduction (rows past the block are zero)
-        T acc[RON];
+    // update from an initial state (Sec. IV): q = F x0 for x rows, l = lo - E x0 and
+    // u = hi - E x0 for constraint rows, FP64 products, one wave per row of the block; the
+    // values reach the owners through LDS and are written back for later solves
+    __syncthreads();  // upd[] and cq[] of the previous solve have been read
+    if (a.x0) {
+      const double* x0 = a.x0 + (long)sv * a.nx;
+      // rows 0 .. nrows-1: owned layer rows; rows nrows .. nrows+nck-1: the check's x rows
+      for (int rr = wave; rr < nrows + nck; rr += NWAVE) {
+        const int R = rr < nrows ? r0 + rr : cb + (rr - nrows);
+        const double* arow = R < n ? a.F + (long)R * a.nx : a.E + (long)(R - n) * a.nx;
+        double dv = 0.0;
+        for (int c = lane; c < a.nx; c += kWave) dv = fma(arow[c], x0[c], dv);
 #pragma unroll
-        for (int rr = 0; rr < RON; ++rr) {
-          acc[rr] = 0;
-          if (rr < NRS) {
-#pragma unroll
-            for (int k2 = 0; k2 < NC; ++k2) acc[rr] = fma(wst[rr < NRS ? rr : 0][k2], wv[k2], acc[rr]);
+        for (int off = kWave / 2; off > 0; off >>= 1) dv += __shfl_xor(dv, off, kWave);
+        if (lane == 0) {
+          if (rr >= nrows) {
+            cq[rr - nrows] = (T)dv;
+          } else if (R < n) {
+            upd[rr][0] = (T)dv;
+            static_cast<T*>(const_cast<void*>(a.q))[R] = (T)dv;
           } else {
-#pragma unroll
-            for (int k2 = 0; k2 < NC; ++k2) acc[rr] = fma(wl[((rr - NRS) * NC + k2) * BS + tid], wv[k2], acc[rr]);
-          }
-        }
-        const T rsum = reduce_rows<RON>(acc);
-        if (writer) red[wave][my_row] = rsum;
-        if (nrows > nres) {
-          const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
-          for (int rr = nres; rr < nrows; ++rr) {
-            T acc = 0;
-#pragma unroll
-            for (int k2 = 0; k2 < NC; ++k2) {
-              const int c = tid + BS * k2;
-              acc = fma(c < L ? Wj[(long)(r0 + rr) * a.ldw + c] : (T)0, wv[k2], acc);
-            }
-            acc = wave_sum_to_last(acc);
-            if (lane == kLastLane) red[wave][rr] = acc;
-          }
-        }
-        __syncthreads();
-        if (fail_flag) {
-          if (tid == 0) err_raise(a.err, tag);
-          finish<T>(a, rs, k, ST_INTERNAL, j);
-          return;
-        }
-
-        // row-local update: relaxation, clamp (eq. clamp), dual update
-        if (rs.own) {
-          T v = 0;
-#pragma unroll
-          for (int w = 0; w < NWAVE; ++w) v += red[w][tid];
-          if (rs.xrow) {
-            rs.sx = alpha * v + oma * rs.sx;
-          } else {
-            const T t = alpha * v + oma * rs.sz + rs.sy / srho;
-            const T zn = box_clamp(t, sl, su);
-            rs.sy = srho * (t - zn);
-            rs.sz = zn;
-          }
-          // No barrier after this: a wave passes the next gather only after every row of the
-          // block was published, and each owner publishes after it has read red[][].
-          if (k < kend) {
-            const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
-            ll_store(xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
+            const int i = R - n;
+            upd[rr][0] = (T)(a.plo[i] - dv);
+            upd[rr][1] = (T)(a.phi[i] - dv);
+            static_cast<T*>(const_cast<void*>(a.l))[i] = upd[rr][0];
+            static_cast<T*>(const_cast<void*>(a.u))[i] = upd[rr][1];
           }
         }
       }
+    } else if (tid < nck) {
+      cq[tid] = static_cast<const T*>(a.q)[cb + tid];
+    }
+    __syncthreads();
+
+    // row-owner state: cold (zero, start penalty), warm from the handle (first solve) or from
+    // the previous solve of this launch
+    if (rs.own) {
+      if (rs.xrow) {
+        rs.sq = a.x0 ? upd[tid][0] : static_cast<const T*>(a.q)[rs.R];
+        if (!warm) rs.sx = (T)0;
+        else if (sv == 0) rs.sx = static_cast<const T*>(a.xs)[rs.R];
+      } else {
+        const int i = rs.R - n;
+        sl = a.x0 ? upd[tid][0] : static_cast<const T*>(a.l)[i];
+        su = a.x0 ? upd[tid][1] : static_cast<const T*>(a.u)[i];
+        rs.sz = (T)0;
+        rs.ax = 0.0;
+        if (!warm) rs.sy = (T)0;
+        else if (sv == 0) rs.sy = static_cast<const T*>(a.ys)[i];
+      }
+    }
+    if (!warm) j = a.j0;
+    T srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
+    if (j != lds_j) {
+      load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
+      lds_j = j;
+    }
+    __syncthreads();  // fail_flag, LDS rows
+    int nchk = 0;
+
+    // warm start: z = A x (Sec. II-B, warm starting)
+    if (warm) {
+      if (rs.own) ll_store(a.xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, tag);
+      Cols<T, NC> cv;
+      const bool ok = gather<T, NC>(a.xc, L, tag, cv.v, a.err, tag);
+      if (__syncthreads_or(!ok)) {
+        if (tid == 0) err_raise(a.err, tag);
+        finish<T>(a, rs, sv, 0, ST_INTERNAL, j);
+        return;
+      }
+      double ax, unused;
+      check_rows<T, NC>(a, r0, nrows, cv, ax, unused);
+      if (rs.own && !rs.xrow) {
+        rs.sz = (T)ax;
+        rs.ax = ax;
+      }
     }
 
-    // check at iteration k (every check_interval iterations and at max_iter)
-    __syncthreads();
-    const CheckOut co = run_check<T, NC>(a, rt, rs, r0, nrows, k, nchk, j);
-    ++nchk;
-    if (!co.ok) {
-      if (tid == 0) err_raise(a.err, tag);
-      finish<T>(a, rs, k, ST_INTERNAL, j);
-      return;
+    // first layer input w_1
+    {
+      const T sigma = (T)a.sigma;
+      const T w1 = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
+      if (rs.own) ll_store(a.xw + ((long)L + rs.R) * NW, w1, tag + 1u);
     }
-    if (co.status != ST_RUNNING) {
-      finish<T>(a, rs, k, co.status, j);
-      return;
+
+    int k = 0;
+    while (true) {
+      const int kend = (k / ci + 1) * ci < max_iter ? (k / ci + 1) * ci : max_iter;
+      {
+        T wst[NRS][NC];
+        load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+        const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
+        const double alpha_d = a.alpha, oma_d = 1.0 - a.alpha;
+        uint64_t* xw = a.xw;
+        while (k < kend) {
+          ++k;
+          // layer matvec: rows of Wc_j times w_k
+          T wv[NC];
+          const bool ok = gather<T, NC>(xw + (long)(k & 1) * L * NW, L, tag + (uint32_t)k, wv, a.err, tag);
+          if (!ok) fail_flag = 1;
+          // all on-chip rows, then one multi-row wave reduction (rows past the block are zero)
+          T acc[RON];
+#pragma unroll
+          for (int rr = 0; rr < RON; ++rr) {
+            acc[rr] = 0;
+            if (rr < NRS) {
+#pragma unroll
+              for (int k2 = 0; k2 < NC; ++k2) acc[rr] = fma(wst[rr < NRS ? rr : 0][k2], wv[k2], acc[rr]);
+            } else {
+#pragma unroll
+              for (int k2 = 0; k2 < NC; ++k2) acc[rr] = fma(wl[((rr - NRS) * NC + k2) * BS + tid], wv[k2], acc[rr]);
+            }
+          }
+          const T rsum = reduce_rows<RON>(acc);
+          if (writer) red[wave][my_row] = rsum;
+          if (nrows > nres) {
+            const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
+            for (int rr = nres; rr < nrows; ++rr) {
+              T acc1 = 0;
+#pragma unroll
+              for (int k2 = 0; k2 < NC; ++k2) {
+                const int c = tid + BS * k2;
+                acc1 = fma(c < L ? Wj[(long)(r0 + rr) * a.ldw + c] : (T)0, wv[k2], acc1);
+              }
+              acc1 = wave_sum_to_last(acc1);
+              if (lane == kLastLane) red[wave][rr] = acc1;
+            }
+          }
+          __syncthreads();
+          if (fail_flag) {
+            if (tid == 0) err_raise(a.err, tag);
+            finish<T>(a, rs, sv, k, ST_INTERNAL, j);
+            return;
+          }
+
+          // row-local update: relaxation, clamp (eq. clamp), dual update
+          if (rs.own) {
+            T v = 0;
+#pragma unroll
+            for (int w = 0; w < NWAVE; ++w) v += red[w][tid];
+            if (rs.xrow) {
+              rs.sx = alpha * v + oma * rs.sx;
+            } else {
+              // A x_{k+1} = alpha A x~ + (1 - alpha) A x_k, with A x~ the layer output v
+              rs.ax = fma(alpha_d, (double)v, oma_d * rs.ax);
+              const T t = alpha * v + oma * rs.sz + rs.sy / srho;
+              const T zn = box_clamp(t, sl, su);
+              rs.sy = srho * (t - zn);
+              rs.sz = zn;
+            }
+            // No barrier after this: a wave passes the next gather only after every row of the
+            // block was published, and each owner publishes after it has read red[][].
+            if (k < kend) {
+              const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
+              ll_store(xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
+            }
+          }
+        }
+      }
+
+      // check at iteration k (every check_interval iterations and at max_iter)
+      __syncthreads();
+      const CheckOut co = run_check<T, NC>(a, rt, rs, cb, nck, cq, k, nchk, j, tag, (long)sv * a.max_checks);
+      ++nchk;
+      if (!co.ok) {
+        if (tid == 0) err_raise(a.err, tag);
+        finish<T>(a, rs, sv, k, ST_INTERNAL, j);
+        return;
+      }
+      if (co.status != ST_RUNNING) {
+        finish<T>(a, rs, sv, k, co.status, j);
+        break;  // next solve of the sequence
+      }
+      if (co.jn != j) {
+        j = co.jn;
+        srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
+        load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
+        lds_j = j;
+      }
+      const T sigma = (T)a.sigma;
+      const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
+      if (rs.own) ll_store(a.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
     }
-    if (co.jn != j) {
-      j = co.jn;
-      srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
-      load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
-    }
-    const T sigma = (T)a.sigma;
-    const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
-    if (rs.own) ll_store(a.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
   }
 }
 

@@ -744,8 +744,9 @@ int relu_qp_set_warm(relu_qp_handle* h, int enabled) {
 }  // extern "C"
 
 namespace {
-// One persistent launch of the online loop; with x0, the launch first forms q, l, u from it.
-int solve_impl(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out) {
+// One persistent launch of `count` solves of the online loop; with x0 (count x nx), each solve
+// first forms its q, l, u from its own initial state.
+int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, relu_qp_result* out) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
     return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
@@ -757,8 +758,12 @@ int solve_impl(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result
                                                 static_cast<float*>(h->u), st));
     return solve_batched(h, st, out);
   }
+  if (count < 1) return fail(RQP_EINVAL, "count must be >= 1");
+  if (count > 1 && h->batched) return fail(RQP_EINVAL, "solve sequences run on the single-instance engine");
   const uint32_t span = (uint32_t)h->s.max_iter + 2u;
-  if ((uint64_t)h->tag + span >= 0xffffffffull) {
+  if ((uint64_t)span * (uint64_t)count >= 0x7fffffffull)
+    return fail(RQP_EINVAL, "count * (max_iter + 2) must stay below 2^31");
+  if ((uint64_t)h->tag + (uint64_t)span * count >= 0xffffffffull) {
     // restart the tag sequence: clear every exchange word so no stale tag can match
     HIP_OR_FAIL(hipMemsetAsync(h->xw, 0, h->xw_words * 8, st));
     HIP_OR_FAIL(hipMemsetAsync(h->xc, 0, h->xw_words * 8, st));
@@ -811,6 +816,9 @@ int solve_impl(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result
   a.tag = h->tag;
   a.abort_flag = h->abort_d;
   a.err = h->err;
+  a.count = count;
+  a.chain = h->warm_mode ? 1 : 0;
+  a.max_checks = h->s.max_iter / h->s.check_interval + (h->s.max_iter % h->s.check_interval ? 1 : 0);
   a.x0 = x0;
   a.F = h->F_d;
   a.E = h->E_d;
@@ -820,7 +828,7 @@ int solve_impl(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result
   hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->plan, h->grid_wg, st)
                                : rqp::launch_layer<float>(a, h->plan, h->grid_wg, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
-  h->tag += span;
+  h->tag += span * (uint32_t)count;
   h->warm_pending = false;
   h->have_prev = true;
   return RQP_OK;
@@ -830,11 +838,18 @@ int solve_impl(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result
 
 extern "C" {
 
-int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) { return solve_impl(h, nullptr, stream, out); }
+int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out) {
+  return solve_impl(h, nullptr, 1, stream, out);
+}
 
 int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out) {
   if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
-  return solve_impl(h, x0, stream, out);
+  return solve_impl(h, x0, 1, stream, out);
+}
+
+int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out) {
+  if (!x0s) return fail(RQP_EINVAL, "x0s is NULL");
+  return solve_impl(h, x0s, count, stream, out);
 }
 
 int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const double* q, const double* l,

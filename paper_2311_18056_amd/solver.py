@@ -150,6 +150,38 @@ class Solver:
         check(lib().relu_qp_solve_x0(self._h, c_void_p(x0.data_ptr()), _stream_handle(stream),
                                      byref(out if out is not None else self._res)))
 
+    def solve_sequence(self, x0s: torch.Tensor, stream=None, out=None):
+        """len(x0s) solves in one launch of the single-instance engine, each from its own x0
+        (float64 cuda, count x nx). Results go to ``out`` (a dict from ``sequence_slots``) or to
+        new tensors, returned as that dict."""
+        if x0s.dtype != torch.float64 or not x0s.is_cuda or not x0s.is_contiguous() or x0s.dim() != 2:
+            raise ValueError("x0s must be a contiguous (count, nx) float64 cuda tensor")
+        count = x0s.shape[0]
+        if out is None:
+            out = self.sequence_slots(count)
+        check(lib().relu_qp_solve_sequence(self._h, c_void_p(x0s.data_ptr()), count, _stream_handle(stream),
+                                           byref(out["_result"])))
+        return out
+
+    def sequence_slots(self, count: int) -> dict:
+        """Device result tensors for ``count`` solves of one sequence launch."""
+        dev = self.device
+        t = dict(
+            x=torch.zeros(count, self.n, dtype=self.dtype, device=dev),
+            y=torch.zeros(count, self.m, dtype=self.dtype, device=dev),
+            z=torch.zeros(count, self.m, dtype=self.dtype, device=dev),
+            iterations=torch.zeros(count, dtype=torch.int32, device=dev),
+            status=torch.zeros(count, dtype=torch.int32, device=dev),
+            rho_index=torch.zeros(count, dtype=torch.int32, device=dev),
+            rho_hist=torch.full((count, self.max_checks), -1, dtype=torch.int32, device=dev),
+            prim_res=torch.zeros(count, self.max_checks, dtype=torch.float64, device=dev),
+            dual_res=torch.zeros(count, self.max_checks, dtype=torch.float64, device=dev),
+        )
+        t["_result"] = Result(t["x"].data_ptr(), t["y"].data_ptr(), t["z"].data_ptr(), t["iterations"].data_ptr(),
+                              t["status"].data_ptr(), t["rho_index"].data_ptr(), t["rho_hist"].data_ptr(),
+                              t["prim_res"].data_ptr(), t["dual_res"].data_ptr())
+        return t
+
     # ------------------------------------------------------------------ serving (batched engine)
     @staticmethod
     def _slot_array(slots):

@@ -284,3 +284,47 @@ def test_solve_x0_fuses_the_update(rq, c0, prec):
         _compare(ra, ref, TOL[prec])
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("chain", [False, True])
+def test_solve_sequence_matches_separate_solves(rq, c0, prec, chain):
+    """count solves in one launch (weights kept on chip between them) give the bit-identical
+    results of the same solves launched one at a time, cold or warm-chained (each solve starts
+    from the previous solution); the per-solve histories land at their own offsets."""
+    import torch
+
+    prob, _ = c0
+    xs = 5.0 * x0_batch(prob.nx, 6, 1300)
+    q0, l0, u0 = prob.instance(xs[0])
+    kw = dict(precision=prec, n_rho=8, max_iter=400)
+    seq = rq.Solver(prob.P, q0, prob.A, l0, u0, **kw)
+    one = rq.Solver(prob.P, q0, prob.A, l0, u0, **kw)
+    for s in (seq, one):
+        s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+        s.set_warm(chain)
+    xd = torch.tensor(xs, dtype=torch.float64, device="cuda")
+    out = seq.solve_sequence(xd)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "_result"}
+    for i in range(len(xs)):
+        one.solve_x0(xd[i:i + 1])
+        r = one.result()
+        assert res["status"][i] == r["status"] == rq.RQP_SOLVED, i
+        assert res["iterations"][i] == r["iterations"] and res["rho_index"][i] == r["rho_index"], i
+        nck = len(r["rho_hist"])
+        assert res["rho_hist"][i][:nck].tolist() == r["rho_hist"], i
+        np.testing.assert_array_equal(res["prim_res"][i][:nck], r["prim_res"])
+        for name in ("x", "y", "z"):
+            assert np.array_equal(res[name][i].astype(np.float64), r[name]), (prec, chain, i, name)
+    # the chained solves also match the oracle's warm starts
+    if chain and prec == "fp64":
+        prev = None
+        for i in range(3):
+            q, l, u = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, xs[i])
+            ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(n_rho=8, max_iter=400), warm=prev)
+            assert ref.iterations == res["iterations"][i]
+            _compare({k: res[k][i] for k in ("x", "y", "z")}, ref, 1e-9)
+            prev = (ref.x, ref.y, ref.rho_index)
+    seq.close()
+    one.close()
