@@ -272,20 +272,21 @@ __device__ __forceinline__ void tile_gemm(Smem<PREC>& sm, const void* Aa, const 
   const int s0 = kb / TK;
   int ns = (ke + TK - 1) / TK - s0;
   ns = (ns + kRing - 1) / kRing * kRing;
-  const int last = s0 + ns - 1;
+  // stage of visit position p (positions past the end re-read the last one)
+  auto stage = [&](int p) { return s0 + min(p, ns - 1); };
   Frag<PREC> f[kRing];
 #pragma unroll
-  for (int r = 0; r < kRing; ++r) fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, s0 + r);
-  stash<PREC, MASK>(sm, 0, f[0], s0, kb, ke);
+  for (int r = 0; r < kRing; ++r) fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(r));
+  stash<PREC, MASK>(sm, 0, f[0], stage(0), kb, ke);
   __syncthreads();
-  for (int s = s0; s < s0 + ns; s += kRing) {
+  for (int p = 0; p < ns; p += kRing) {
 #pragma unroll
     for (int r = 0; r < kRing; ++r) {
-      // stage s + r is in LDS buffer r & 1; f[r] is free again
-      fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, min(s + r + kRing, last));
+      // position p + r is in LDS buffer r & 1; f[r] is free again
+      fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(p + r + kRing));
       __builtin_amdgcn_sched_barrier(0);
       compute<PREC>(sm, r & 1, acc);
-      stash<PREC, MASK>(sm, (r + 1) & 1, f[(r + 1) % kRing], min(s + r + 1, last), kb, ke);
+      stash<PREC, MASK>(sm, (r + 1) & 1, f[(r + 1) % kRing], stage(p + r + 1), kb, ke);
       __syncthreads();
     }
   }
@@ -351,6 +352,7 @@ struct TileWalk {
       count = nmt * (ne - nb);
     }
   }
+  // workgroup l of an XCD takes tiles l, l + per, ...
   __device__ int first() const { return gridDim.x % 8 != 0 ? blockIdx.x : blockIdx.x / 8; }
   __device__ int mt(int j) const { return m0 + j % mx; }
   __device__ int nt(int j) const { return n0 + j / mx; }
