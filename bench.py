@@ -409,7 +409,8 @@ def bench_serve(args):
     probs = [make_config(f) for f in args.families.split(",")]
     gens = [lambda rng, p=p: args.x0_scale * rng.uniform(-1.0, 1.0, p.nx) for p in probs]
     settings = dict(n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000, check_interval=25)
-    fams = [Family.from_mpc(p, slots=args.slots, precision=args.precision, **settings) for p in probs]
+    fams = [Family.from_mpc(p, slots=args.slots, precision=args.precision, **settings).attach_single(p, **settings)
+            for p in probs]
     singles = []
     for p in probs:
         q, l, u = p.instance(np.zeros(p.nx))
@@ -441,6 +442,8 @@ def bench_serve(args):
     }
     for f in fams:
         f.solver.close()
+        if f.single is not None:
+            f.single.close()
     for s in singles:
         s.close()
     print(json.dumps(out), flush=True)

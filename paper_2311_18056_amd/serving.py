@@ -8,6 +8,12 @@ most recent solution shifted by one stage (the receding-horizon warm start of Se
 Sec. V-B), runs one step (a persistent launch of ``n_checks`` check intervals) per family with
 work, and retires slots whose status became final. All arithmetic runs in the HIP library.
 
+With a single-instance handle attached (``Family.attach_single``), a family whose queue is
+short and whose slots are all free is served by one sequence launch of the single-instance
+engine instead (``relu_qp_solve_sequence``: the few queued requests back to back, cold starts):
+at light load a batched step over a nearly empty batch of a large family costs far more than a
+handful of single-instance solves.
+
 Latency is measured from a request's arrival time to the moment its result is on the host.
 """
 
@@ -47,6 +53,7 @@ class Family:
     busy: dict = field(default_factory=dict)  # slot -> Request
     queue: collections.deque = field(default_factory=collections.deque)
     pin: int | None = None      # slot holding the family's most recent solution
+    single: Solver | None = None  # optional single-instance handle for light load
 
     @classmethod
     def from_mpc(cls, prob, slots: int, precision: str = "fp32", keep_x: bool = False, **settings):
@@ -60,14 +67,33 @@ class Family:
         fam.keep_x = keep_x
         return fam
 
+    def attach_single(self, prob, **settings):
+        """Single-instance handle (FP32) of the same family, for light-load sequence launches."""
+        q, l, u = prob.instance(np.zeros(prob.nx))
+        s = Solver(prob.P, q, prob.A, l, u, precision="fp32", engine="single", **settings)
+        s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+        self.single = s
+        return self
+
 
 class Server:
     """Serves requests over families with continuous batching on one device stream."""
 
-    def __init__(self, families: list[Family], n_checks: int = 1, warm: bool = True):
+    def __init__(self, families: list[Family], n_checks: int = 1, warm: bool = True, light: int = 8):
+        """light: a family with at most this many queued requests and no busy slot is served by
+        a sequence launch of its single-instance handle (if attached)."""
         self.families = families
         self.n_checks = n_checks
         self.warm = warm
+        self.light = light
+
+    def _light_step(self, fam: Family):
+        """Solve the family's whole (short) queue in one single-instance sequence launch."""
+        reqs = list(fam.queue)
+        fam.queue.clear()
+        x0 = torch.tensor(np.stack([r.x0 for r in reqs]), dtype=torch.float64, device=fam.single.device)
+        out = fam.single.solve_sequence(x0)
+        return reqs, out
 
     def _admit(self, fam: Family):
         k = min(len(fam.queue), len(fam.free))
@@ -119,13 +145,24 @@ class Server:
                 # idle until the next arrival
                 time.sleep(max(0.0, pending[0].t_arrival - now) if pending else 0.0)
                 continue
+            light = []
             for fam in self.families:
-                self._admit(fam)
+                if fam.single is not None and not fam.busy and 0 < len(fam.queue) <= self.light:
+                    light.append(self._light_step(fam))
+                else:
+                    self._admit(fam)
             for fam in self.families:
                 if fam.busy:
                     fam.solver.step(self.n_checks)
             torch.cuda.synchronize()
             now = time.perf_counter() - t0
+            for reqs, out in light:
+                st = out["status"].cpu().numpy()
+                it = out["iterations"].cpu().numpy()
+                xs = out["x"].cpu().numpy()
+                for i, r in enumerate(reqs):
+                    r.t_done, r.status, r.iterations = now, int(st[i]), int(it[i])
+                    r.x = xs[i].astype(np.float64)
             for fam in self.families:
                 self._retire(fam, now)
         return requests

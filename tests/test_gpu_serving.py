@@ -160,14 +160,18 @@ def test_step_reaches_max_iter_across_launches(rq):
     sol.close()
 
 
-def test_server_two_families(rq):
+@pytest.mark.parametrize("light", [0, 8])
+def test_server_two_families(rq, light):
+    """End to end: Poisson requests over two families; light = 0 serves everything through the
+    batched slots, light = 8 lets short queues go through single-instance sequence launches."""
     from paper_2311_18056_amd.serving import Family, Server, latency_summary, poisson_requests
 
     probs = [make_config("c0"), make_config("c0", seed=7)]
-    fams = [Family.from_mpc(p, slots=8, precision="fp32", keep_x=True, n_rho=8) for p in probs]
+    fams = [Family.from_mpc(p, slots=8, precision="fp32", keep_x=True, n_rho=8).attach_single(p, n_rho=8)
+            for p in probs]
     gens = [lambda rng, p=p: 5.0 * rng.uniform(-1, 1, p.nx) for p in probs]
     reqs = poisson_requests(2000.0, 60, 10.0, gens, seed=4)
-    Server(fams, n_checks=1, warm=True).run(reqs, time_limit=60.0)
+    Server(fams, n_checks=1, warm=True, light=light).run(reqs, time_limit=60.0)
     for r in reqs:
         assert r.status == rq.RQP_SOLVED, r.rid
         p = probs[r.family]
@@ -178,3 +182,4 @@ def test_server_two_families(rq):
     assert summ["completed"] == len(reqs)
     for f in fams:
         f.solver.close()
+        f.single.close()
