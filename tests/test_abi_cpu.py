@@ -84,3 +84,76 @@ def test_settings_rules_for_engines():
         s = rq.default_settings(**kw)
         assert lib.relu_qp_setup(ctypes.byref(h), 2, 2, z, z, z, z, z, ctypes.byref(s), None) == rq._lib.RQP_EINVAL
         assert word in lib.relu_qp_last_error(), kw
+
+
+def _setup_rc(n, m, P, q, A, l, u, **settings):
+    """relu_qp_setup's return code and message for host arrays (validation runs before any
+    device call, so no GPU is needed for the rejected cases)."""
+    import ctypes
+
+    import numpy as np
+
+    import paper_2311_18056_amd as rq
+
+    lib = rq.lib()
+    s = rq.default_settings(**settings)
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)).ravel() for a in (P, q, A, l, u)]
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs]
+    h = ctypes.c_void_p()
+    rc = lib.relu_qp_setup(ctypes.byref(h), n, m, *ptrs, ctypes.byref(s), None)
+    assert h.value is None
+    return rc, lib.relu_qp_last_error().decode()
+
+
+def test_setup_rejects_bad_problems():
+    import numpy as np
+
+    import paper_2311_18056_amd as rq
+
+    E = rq._lib.RQP_EINVAL
+    P, q, A = np.eye(2), np.zeros(2), np.eye(2)
+    l, u = -np.ones(2), np.ones(2)
+    cases = [
+        ((0, 2, P, q, A, l, u), "n >= 1"),
+        ((2, 0, P, q, A, l, u), "m >= 1"),
+        ((2, 2, [[1, 0.5], [0.4, 1]], q, A, l, u), "symmetric"),
+        ((2, 2, [[1, np.inf], [np.inf, 1]], q, A, l, u), "non-finite"),
+        ((2, 2, P, q, [[1, np.nan], [0, 1]], l, u), "A has a non-finite"),
+        ((2, 2, P, q, A, [2.0, -1.0], u), "l[0] > u[0]"),
+        ((2, 2, P, q, A, [np.nan, -1.0], u), "NaN"),
+        ((2, 2, P, q, A, [np.inf, -1.0], [np.inf, 1.0]), "empty box"),
+        ((5000, 4000, np.eye(1), q, A, l, u), "exceeds"),
+    ]
+    for args, word in cases:
+        rc, msg = _setup_rc(*args)
+        assert rc == E and word in msg, (word, rc, msg)
+
+
+def test_setup_rejects_bad_settings():
+    import numpy as np
+
+    import paper_2311_18056_amd as rq
+
+    E = rq._lib.RQP_EINVAL
+    P, q, A = np.eye(2), np.zeros(2), np.eye(2)
+    l, u = -np.ones(2), np.ones(2)
+    for kw, word in ((dict(sigma=0.0), "sigma"), (dict(alpha=0.0), "alpha"), (dict(n_rho=0), "n_rho"),
+                     (dict(n_rho=65), "n_rho"), (dict(n_rho=8, rho_min=1.0, rho_max=0.5), "rho_min"),
+                     (dict(eps_abs=-1.0), "eps_abs"), (dict(max_iter=0), "max_iter"),
+                     (dict(check_interval=0), "check_interval"), (dict(precision=7), "precision"),
+                     (dict(engine=9), "engine"), (dict(batch=0), "batch"), (dict(rho_eq_scale=0.0), "rho_eq_scale")):
+        rc, msg = _setup_rc(2, 2, P, q, A, l, u, **kw)
+        assert rc == E and word in msg, (kw, rc, msg)
+
+
+def test_batched_setup_rejects_mixed_equality_patterns():
+    import numpy as np
+
+    import paper_2311_18056_amd as rq
+
+    P, A = np.eye(2), np.eye(2)
+    q = np.zeros((2, 2))
+    l = np.array([[0.0, -1.0], [-1.0, -1.0]])
+    u = np.array([[0.0, 1.0], [1.0, 1.0]])
+    rc, msg = _setup_rc(2, 2, P, q, A, l, u, batch=2, precision="fp32")
+    assert rc == rq._lib.RQP_EINVAL and "equality-row pattern" in msg

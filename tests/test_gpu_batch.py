@@ -189,3 +189,31 @@ def test_batch_nonfinite_instance_is_isolated(rq):
     sol.close()
     assert res["status"][1] == rq.RQP_NONFINITE and res["iterations"][1] == 25
     assert all(res["status"][b] == rq.RQP_SOLVED for b in (0, 2, 3))
+
+
+def test_batch_ragged_tiles_mixed_statuses(rq):
+    """B = 129 instances (a full and a one-instance M tile per bucket) of a QP with L = 1200 (not
+    a multiple of the 128-row tile), run to eps = 1e-3 so that instances finish at different
+    checks: every instance passes the FP64 residual test and sampled ones match the oracle with
+    their own schedules replayed for their own iteration counts."""
+    P, q0, A, l0, u0 = random_qp(700, 0, 500, seed=31)
+    B = 129
+    rng = np.random.default_rng(6)
+    q = q0[None, :] + rng.standard_normal((B, 700)) * rng.uniform(0.1, 3.0, (B, 1))
+    l = np.repeat(l0[None, :], B, axis=0)
+    u = np.repeat(u0[None, :], B, axis=0)
+    sol = rq.Solver(P, q, A, l, u, precision="fp32", engine="batch", n_rho=8)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    assert np.all(res["status"] == rq.RQP_SOLVED)
+    assert len(set(res["iterations"].tolist())) > 1, "expected instances to finish at different checks"
+    for b in list(range(0, B, 16)) + [B - 1]:
+        nm = admm.residual_norms(P, q[b], A, res["x"][b], res["z"][b], res["y"][b])
+        assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
+        assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+        it = int(res["iterations"][b])
+        ref = oracle.solve(P, q[b], A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=it),
+                           rho_replay=res["rho_hist"][b][: it // 25].tolist())
+        for name in ("x", "z", "y"):
+            assert _rel(res[name][b], getattr(ref, name)) <= 1e-4, (b, name)

@@ -328,3 +328,43 @@ def test_solve_sequence_matches_separate_solves(rq, c0, prec, chain):
             prev = (ref.x, ref.y, ref.rho_index)
     seq.close()
     one.close()
+
+
+def test_smallest_problem_and_infinite_bounds(rq):
+    """n = m = 1 (two layer rows on two workgroups), and a problem whose bounds are all
+    infinite, where the fixed point is the closed form x = -P^-1 q."""
+    P = np.array([[2.0]])
+    q = np.array([1.0])
+    A = np.array([[1.0]])
+    for prec in ("fp64", "fp32"):
+        res = _fixed_run(rq, P, q, A, np.array([-0.25]), np.array([0.25]), prec, 50)
+        ref = oracle.solve(P, q, A, np.array([-0.25]), np.array([0.25]),
+                           _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=50))
+        _compare(res, ref, TOL[prec])
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((30, 30))
+    P = M @ M.T / 30 + np.eye(30)
+    q = rng.standard_normal(30)
+    A = rng.standard_normal((12, 30))
+    inf = np.full(12, np.inf)
+    sol = rq.Solver(P, q, A, -inf, inf, precision="fp64", eps_abs=1e-9, eps_rel=1e-9, max_iter=4000)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    assert res["status"] == rq.RQP_SOLVED
+    np.testing.assert_allclose(res["x"], -np.linalg.solve(P, q), rtol=0, atol=1e-6)
+
+
+def test_wide_rows_streamed_fp32(rq):
+    """L = 5200 (eight columns per lane, part of each block's rows streamed from memory every
+    iteration) in FP32, 60 iterations against the oracle with the schedule replayed."""
+    P, q, A, l, u = random_qp(2600, 100, 2500, seed=13)
+    res = _fixed_run(rq, P, q, A, l, u, "fp32", 60, n_rho=8)
+    ref = oracle.solve(P, q, A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=60, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    _close(res["x"], ref.x, 1e-4, "x")
+    _close(res["z"], ref.z, 1e-4, "z")
+    # y of the equality rows carries rho_eq * FP32 rounding (see the batched multi-tile test)
+    kappa = max(1.0, max(admm.rho_grid(_oracle_settings(n_rho=8))[j] for j in res["rho_hist"] + [2]) * 1e3
+                * max(np.max(np.abs(ref.z)), 1.0) / max(np.max(np.abs(ref.y)), 1.0))
+    _close(res["y"], ref.y, 1e-4 * kappa, "y")
