@@ -390,7 +390,8 @@ def bench_batch(args):
             "alg_flops_per_unit": flops_per_unit,
             "avg_launch_us": float(np.mean(kern_ms) * 1e3),
         },
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(prob, x0_host[warmup:].reshape(-1, nx),
+                                                                       args.cpu_seconds),
     }
     sol.close()
     print(json.dumps(out), flush=True)

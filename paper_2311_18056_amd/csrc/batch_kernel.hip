@@ -873,30 +873,26 @@ __global__ void admit_kernel(SlotList sl, int warm, int sx, int sy, int n, int m
   }
 }
 // Parametric vectors of the listed slots (Sec. IV): q = F x0, l = lo - E x0, u = hi - E x0;
-// one wave per (listed slot, row).
+// one thread per (listed slot, row), one in-order FMA chain over the nx entries of x0 (the
+// order of the tiled whole-batch update, so a slot gets the same vectors either way).
 __global__ void __launch_bounds__(256) x0_slots_kernel(SlotList sl, int n, int m, int nx, const double* __restrict__ F,
                                                        const double* __restrict__ E, const double* __restrict__ lo,
                                                        const double* __restrict__ hi, const double* __restrict__ x0,
                                                        float* __restrict__ Q, float* __restrict__ Lo,
                                                        float* __restrict__ Up) {
-  const long grow = (long)blockIdx.x * 4 + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (grow >= (long)sl.n * (n + m)) return;
-  const int i = (int)(grow / (n + m)), row = (int)(grow % (n + m));
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)sl.n * (n + m)) return;
+  const int i = (int)(e / (n + m)), row = (int)(e % (n + m));
   const long s = sl.s[i];
   const double* arow = row < n ? F + (long)row * nx : E + (long)(row - n) * nx;
   const double* xi = x0 + (long)i * nx;
   double acc = 0.0;
-  for (int c = lane; c < nx; c += 64) acc = fma(arow[c], xi[c], acc);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) {
-    if (row < n) {
-      Q[s * n + row] = (float)acc;
-    } else {
-      Lo[s * m + (row - n)] = (float)(lo[row - n] - acc);
-      Up[s * m + (row - n)] = (float)(hi[row - n] - acc);
-    }
+  for (int c = 0; c < nx; ++c) acc = fma(arow[c], xi[c], acc);
+  if (row < n) {
+    Q[s * n + row] = (float)acc;
+  } else {
+    Lo[s * m + (row - n)] = (float)(lo[row - n] - acc);
+    Up[s * m + (row - n)] = (float)(hi[row - n] - acc);
   }
 }
 // q, l, u rows of the listed slots from FP64 device arrays (n_slots x n, n_slots x m)
@@ -920,8 +916,8 @@ hipError_t load_x0_slots(const SlotList& sl, int n, int m, int nx, const double*
                          const double* hi, const double* x0, float* Q, float* Lo, float* Up, hipStream_t st) {
   if (sl.n <= 0) return hipSuccess;
   const long rows = (long)sl.n * (n + m);
-  hipLaunchKernelGGL(x0_slots_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, sl, n, m, nx, F, E, lo, hi,
-                     x0, Q, Lo, Up);
+  hipLaunchKernelGGL(x0_slots_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, sl, n, m, nx, F, E, lo,
+                     hi, x0, Q, Lo, Up);
   return hipGetLastError();
 }
 

@@ -705,7 +705,11 @@ int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream) 
   if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
   if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (h->esize == 8)
+  if (h->batched)
+    HIP_OR_FAIL(rqp::mpc_vectors_tiled<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
+                                              static_cast<float*>(h->q), static_cast<float*>(h->l),
+                                              static_cast<float*>(h->u), st));
+  else if (h->esize == 8)
     HIP_OR_FAIL(rqp::mpc_vectors<double>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
                                          static_cast<double*>(h->q), static_cast<double*>(h->l),
                                          static_cast<double*>(h->u), st));
@@ -753,7 +757,7 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (x0 && !h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
   if (h->batched) {
-    if (x0) HIP_OR_FAIL(rqp::mpc_vectors<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
+    if (x0) HIP_OR_FAIL(rqp::mpc_vectors_tiled<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
                                                 static_cast<float*>(h->q), static_cast<float*>(h->l),
                                                 static_cast<float*>(h->u), st));
     return solve_batched(h, st, out);

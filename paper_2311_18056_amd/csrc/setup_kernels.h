@@ -36,6 +36,11 @@ hipError_t assemble_check(int n, int m, const double* P, const double* A, T* C, 
 template <typename T>
 hipError_t mpc_vectors(int B, int n, int m, int nx, const double* F, const double* E, const double* lo,
                        const double* hi, const double* x0, T* q, T* l, T* u, hipStream_t st);
+// The same for many instances as a tiled FP64 product; each output is one in-order FMA chain
+// over the nx entries of x0 (the batched engine and its slot loader use this order).
+template <typename T>
+hipError_t mpc_vectors_tiled(int B, int n, int m, int nx, const double* F, const double* E, const double* lo,
+                             const double* hi, const double* x0, T* q, T* l, T* u, hipStream_t st);
 
 // y = x cast to T (count elements).
 template <typename T>

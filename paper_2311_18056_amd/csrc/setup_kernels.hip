@@ -304,6 +304,51 @@ __global__ void __launch_bounds__(256) mpc_vectors_kernel(long B, int n, int m, 
   }
 }
 
+// Many instances at once: the same vectors as a tiled FP64 product [F; E] X0' (64 rows x 64
+// instances per block, nx in chunks of 32 through LDS); every output is one FMA chain over
+// k = 0 .. nx-1 in order, the order a thread-per-output loop gives too.
+constexpr int MT = 64, MK = 32;
+template <typename T>
+__global__ void __launch_bounds__(256) mpc_tiled_kernel(int B, int n, int m, int nx, const double* __restrict__ F,
+                                                        const double* __restrict__ E, const double* __restrict__ lo,
+                                                        const double* __restrict__ hi, const double* __restrict__ x0,
+                                                        T* __restrict__ q, T* __restrict__ l, T* __restrict__ u) {
+  __shared__ double fe[MT][MK + 1];
+  __shared__ double xs[MT][MK + 1];
+  const int L = n + m, r0 = blockIdx.x * MT, b0 = blockIdx.y * MT, tid = threadIdx.x;
+  const int tr = tid % 16, tb = tid / 16;  // rows tr + 16 i, instances tb + 16 j
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < nx; k0 += MK) {
+    for (int e = tid; e < MT * MK; e += 256) {
+      const int rr = e / MK, kk = e % MK, R = r0 + rr, b = b0 + rr, k = k0 + kk;
+      fe[rr][kk] = (R < L && k < nx) ? (R < n ? F[(long)R * nx + k] : E[(long)(R - n) * nx + k]) : 0.0;
+      xs[rr][kk] = (b < B && k < nx) ? x0[(long)b * nx + k] : 0.0;
+    }
+    __syncthreads();
+    const int kn = min(MK, nx - k0);
+    for (int kk = 0; kk < kn; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(fe[tr + 16 * i][kk], xs[tb + 16 * j][kk], acc[i][j]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int R = r0 + tr + 16 * i, b = b0 + tb + 16 * j;
+      if (R >= L || b >= B) continue;
+      if (R < n) {
+        q[(long)b * n + R] = (T)acc[i][j];
+      } else {
+        const int ii = R - n;
+        l[(long)b * m + ii] = (T)(lo[ii] - acc[i][j]);
+        u[(long)b * m + ii] = (T)(hi[ii] - acc[i][j]);
+      }
+    }
+}
+
 inline unsigned blocks_for(long count, int bs) { return (unsigned)((count + bs - 1) / bs); }
 
 }  // namespace
@@ -367,6 +412,14 @@ hipError_t mpc_vectors(int B, int n, int m, int nx, const double* F, const doubl
 }
 
 template <typename T>
+hipError_t mpc_vectors_tiled(int B, int n, int m, int nx, const double* F, const double* E, const double* lo,
+                             const double* hi, const double* x0, T* q, T* l, T* u, hipStream_t st) {
+  const dim3 grid((unsigned)((n + m + MT - 1) / MT), (unsigned)((B + MT - 1) / MT));
+  hipLaunchKernelGGL(mpc_tiled_kernel<T>, grid, dim3(256), 0, st, B, n, m, nx, F, E, lo, hi, x0, q, l, u);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t cast_from_f64(long count, const double* x, T* y, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(cast_kernel<T>, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, x, y);
@@ -383,6 +436,8 @@ template hipError_t mpc_vectors<float>(int, int, int, int, const double*, const 
                                        const double*, const double*, float*, float*, float*, hipStream_t);
 template hipError_t mpc_vectors<double>(int, int, int, int, const double*, const double*, const double*,
                                         const double*, const double*, double*, double*, double*, hipStream_t);
+template hipError_t mpc_vectors_tiled<float>(int, int, int, int, const double*, const double*, const double*,
+                                             const double*, const double*, float*, float*, float*, hipStream_t);
 template hipError_t cast_from_f64<float>(long, const double*, float*, hipStream_t);
 template hipError_t cast_from_f64<double>(long, const double*, double*, hipStream_t);
 
