@@ -49,9 +49,10 @@ def parse():
     ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
     ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
     ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
-    ap.add_argument("--workload", choices=["c1", "batch", "serve"], default="c1",
-                    help="c1: one instance per solve (the headline); batch: 4096 instances of the same "
-                         "family per solve on the matrix cores; serve: continuous batching of MPC requests")
+    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve"], default="c1",
+                    help="c1: one instance per solve (the headline, n = m = 1600); c2: one instance per solve "
+                         "of the n = 600, m = 1800 family; batch: 4096 instances of the c1 family per solve on "
+                         "the matrix cores; serve: continuous batching of MPC requests")
     ap.add_argument("--precision", choices=["bf16x3", "fp32"], default="bf16x3", help="batched engine precision")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000", help="serve: request rates per second")
@@ -135,7 +136,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    prob = make_config("c1")
+    prob = make_config(args.workload)
     n, m, nx = prob.n, prob.m, prob.nx
     total = args.warmup + args.steps
     x0_host = x0_batch(nx, total, 1000, scale=args.x0_scale)
@@ -229,7 +230,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, x0_host[args.warmup:], args.cpu_seconds)
 
-    traffic_bytes = measured_traffic(float(np.mean(it)), C)
+    traffic_bytes = measured_traffic(float(np.mean(it)), C) if args.workload == "c1" else None
     avg_launch_s = float(np.mean(kern_ms)) * 1e-3
     out = {
         "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
@@ -245,8 +246,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "random linear MPC, LQR-condensed dense QP, n=1600, m=1600 (nx=120, nu=40, N=40)",
-            "x0": f"{args.x0_scale:g} * U[-1,1]^120, seed 1000",
+            "workload": (f"random linear MPC, LQR-condensed dense QP, n={n}, m={m} "
+                         f"(nx={nx}, nu={prob.nu}, N={prob.N})"),
+            "x0": f"{args.x0_scale:g} * U[-1,1]^{nx}, seed 1000",
             "penalties": "8 log-spaced 1e-3..1e3",
             "eps": 1e-3,
             "launch": {"grid": grid_wg, "block": block},

@@ -43,6 +43,8 @@ EXPORTS = [
     "relu_qp_load_slots_x0",
     "relu_qp_admit",
     "relu_qp_step",
+    "relu_qp_get_tile",
+    "relu_qp_set_tile",
     "relu_qp_abort",
     "relu_qp_max_checks",
     "relu_qp_get_rho_grid",
@@ -122,6 +124,8 @@ def lib():
     L.relu_qp_load_slots_x0.argtypes = [h, _ip, c_int, c_void_p, c_void_p]
     L.relu_qp_admit.argtypes = [h, _ip, c_int, c_int, c_int, c_int, c_void_p]
     L.relu_qp_step.argtypes = [h, c_int, c_void_p, POINTER(Result)]
+    L.relu_qp_get_tile.argtypes = [h, POINTER(c_int), POINTER(c_double)]
+    L.relu_qp_set_tile.argtypes = [h, c_int]
     L.relu_qp_abort.argtypes = [h]
     L.relu_qp_max_checks.argtypes = [h]
     L.relu_qp_get_rho_grid.argtypes = [h, _dp, POINTER(c_int)]

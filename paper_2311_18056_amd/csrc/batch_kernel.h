@@ -22,7 +22,7 @@ struct SlotList {
 };
 
 constexpr int kTileM = 128;   // instances per tile
-constexpr int kTileN = 128;   // layer rows per tile
+constexpr int kTileN = 128;   // layer rows per tile (largest tile shape; 64 also exists)
 constexpr int kTileK = 32;    // k per LDS stage
 constexpr int kBatchBlock = 256;
 
@@ -77,9 +77,12 @@ struct BatchArgs {
 struct BatchPlan {
   const void* fn;
   int grid;
+  size_t smem;
+  int tn;  // matrix rows per tile (128 or 64)
 };
 
-BatchPlan plan_batch(int prec);
+// Kernel of the given precision and tile rows (128 or 64); fn == null if unavailable.
+BatchPlan plan_batch(int prec, int tn);
 // Set every slot's state (e.g. admit all for a whole-batch solve).
 hipError_t fill_status(int B, int value, int* status, hipStream_t st);
 // q, l, u of the listed slots: from initial states x0 (n_slots x nx, FP64, device) with the

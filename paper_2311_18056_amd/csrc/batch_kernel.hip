@@ -101,23 +101,24 @@ __device__ __forceinline__ void put_operand(void* va, void* vb, long idx, float 
 }
 
 // ------------------------------------------------------------------------------------------
-// GEMM tile: acc[mb][nb] (each 32 x 32, lane layout of v_mfma_f32_32x32x*) for the 64 x 64
-// quarter of the 128 x 128 tile owned by this wave. Operand A rows are instances (element
-// offsets, -1 = zero row), B rows are matrix rows; both are K-contiguous with ld = ldk.
+// GEMM tile of TM instances x TNV matrix rows (TNV = 128 or 64): four waves in a 2 x 2 grid,
+// each owning 64 instances x TNV/2 rows as 2 x BJ blocks of 32 x 32 accumulators (lane layout
+// of v_mfma_f32_32x32x*). Operand A rows are list positions (instances), B rows are matrix
+// rows; both K-blocked (one K stage of a tile is one contiguous block).
 
-template <int PREC>
+template <int PREC, int TNV>
 struct Smem;
-template <>
-struct Smem<kBatchBF16x3> {
-  static constexpr int kRowsPerThread = 2;  // rows tid/4 and tid/4 + 64, 8 bf16 each
-  unsigned short a[2][2][TM][TK + PADB];    // [stage][hi/lo][row][k]
-  unsigned short b[2][2][TN][TK + PADB];
+template <int TNV>
+struct Smem<kBatchBF16x3, TNV> {
+  static constexpr int kRowsA = TM / 64, kRowsB = TNV / 64;  // rows tid/4 + 64 q, 8 bf16 each
+  unsigned short a[2][2][TM][TK + PADB];                     // [stage][hi/lo][row][k]
+  unsigned short b[2][2][TNV][TK + PADB];
 };
-template <>
-struct Smem<kBatchF32> {
-  static constexpr int kRowsPerThread = 4;  // rows tid/8 + 32 q, 4 floats each
+template <int TNV>
+struct Smem<kBatchF32, TNV> {
+  static constexpr int kRowsA = TM / 32, kRowsB = TNV / 32;  // rows tid/8 + 32 q, 4 floats each
   float a[2][TM][TK + PADF];
-  float b[2][TN][TK + PADF];
+  float b[2][TNV][TK + PADF];
 };
 
 template <int PREC>
@@ -130,54 +131,62 @@ __device__ __forceinline__ int loader_row(int q) {
 
 // One K stage of this thread's operand rows, held in registers between its global loads and
 // its LDS stores (so that the loads of the next stages are in flight during the products).
-template <int PREC>
+template <int PREC, int TNV>
 struct Frag;
-template <>
-struct Frag<kBatchBF16x3> {
-  ushort8 a[2][2], b[2][2];  // [hi/lo][row]
+template <int TNV>
+struct Frag<kBatchBF16x3, TNV> {
+  ushort8 a[2][TM / 64], b[2][TNV / 64];  // [hi/lo][row]
 };
-template <>
-struct Frag<kBatchF32> {
-  floatx4 a[4], b[4];
+template <int TNV>
+struct Frag<kBatchF32, TNV> {
+  floatx4 a[TM / 32], b[TNV / 32];
 };
 
 // Loads never branch: a row outside the tile's valid range reads a valid dummy row (its
 // products land in accumulator rows or columns that are discarded).
 // aoff / boff: offsets of the thread's rows inside a K block; as / bs: elements per K block.
-template <int PREC>
-__device__ __forceinline__ void fetch(Frag<PREC>& f, const void* Aa, const void* Ab, const void* Ba, const void* Bb,
-                                      const long (&aoff)[Smem<PREC>::kRowsPerThread],
-                                      const long (&boff)[Smem<PREC>::kRowsPerThread], long as, long bs, int stage) {
-  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+template <int PREC, int TNV>
+__device__ __forceinline__ void fetch(Frag<PREC, TNV>& f, const void* Aa, const void* Ab, const void* Ba,
+                                      const void* Bb, const long (&aoff)[Smem<PREC, TNV>::kRowsA],
+                                      const long (&boff)[Smem<PREC, TNV>::kRowsB], long as, long bs, int stage) {
+  constexpr int RA = Smem<PREC, TNV>::kRowsA, RB = Smem<PREC, TNV>::kRowsB;
   if constexpr (PREC == kBatchBF16x3) {
     const long ka = (long)stage * as + (threadIdx.x % 4) * 8, kb = (long)stage * bs + (threadIdx.x % 4) * 8;
 #pragma unroll
-    for (int h = 0; h < RPT; ++h) {
+    for (int h = 0; h < RA; ++h) {
       f.a[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Aa) + aoff[h] + ka);
       f.a[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ab) + aoff[h] + ka);
+    }
+#pragma unroll
+    for (int h = 0; h < RB; ++h) {
       f.b[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ba) + boff[h] + kb);
       f.b[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Bb) + boff[h] + kb);
     }
   } else {
     const long ka = (long)stage * as + (threadIdx.x % 8) * 4, kb = (long)stage * bs + (threadIdx.x % 8) * 4;
 #pragma unroll
-    for (int h = 0; h < RPT; ++h) {
+    for (int h = 0; h < RA; ++h)
       f.a[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Aa) + aoff[h] + ka);
+#pragma unroll
+    for (int h = 0; h < RB; ++h)
       f.b[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Ba) + boff[h] + kb);
-    }
   }
 }
 
 // LDS stores of one stage; with MASK, matrix entries with k outside [kb, ke) become zero.
-template <int PREC, bool MASK>
-__device__ __forceinline__ void stash(Smem<PREC>& sm, int buf, const Frag<PREC>& f, int stage, int kb, int ke) {
-  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+template <int PREC, int TNV, bool MASK>
+__device__ __forceinline__ void stash(Smem<PREC, TNV>& sm, int buf, const Frag<PREC, TNV>& f, int stage, int kb,
+                                      int ke) {
+  constexpr int RA = Smem<PREC, TNV>::kRowsA, RB = Smem<PREC, TNV>::kRowsB;
   if constexpr (PREC == kBatchBF16x3) {
     const int kc = (threadIdx.x % 4) * 8;
     const int k0 = stage * TK + kc;
 #pragma unroll
-    for (int h = 0; h < RPT; ++h) {
-      const int row = loader_row<PREC>(h);
+    for (int h = 0; h < RA; ++h)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) *reinterpret_cast<ushort8*>(&sm.a[buf][p][loader_row<PREC>(h)][kc]) = f.a[p][h];
+#pragma unroll
+    for (int h = 0; h < RB; ++h)
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
         ushort8 bv = f.b[p][h];
@@ -185,50 +194,52 @@ __device__ __forceinline__ void stash(Smem<PREC>& sm, int buf, const Frag<PREC>&
 #pragma unroll
           for (int e = 0; e < 8; ++e) bv[e] = (k0 + e >= kb && k0 + e < ke) ? bv[e] : (unsigned short)0;
         }
-        *reinterpret_cast<ushort8*>(&sm.a[buf][p][row][kc]) = f.a[p][h];
-        *reinterpret_cast<ushort8*>(&sm.b[buf][p][row][kc]) = bv;
+        *reinterpret_cast<ushort8*>(&sm.b[buf][p][loader_row<PREC>(h)][kc]) = bv;
       }
-    }
   } else {
     const int kc = (threadIdx.x % 8) * 4;
     const int k0 = stage * TK + kc;
 #pragma unroll
-    for (int h = 0; h < RPT; ++h) {
-      const int row = loader_row<PREC>(h);
+    for (int h = 0; h < RA; ++h) *reinterpret_cast<floatx4*>(&sm.a[buf][loader_row<PREC>(h)][kc]) = f.a[h];
+#pragma unroll
+    for (int h = 0; h < RB; ++h) {
       floatx4 bv = f.b[h];
       if constexpr (MASK) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) bv[e] = (k0 + e >= kb && k0 + e < ke) ? bv[e] : 0.0f;
       }
-      *reinterpret_cast<floatx4*>(&sm.a[buf][row][kc]) = f.a[h];
-      *reinterpret_cast<floatx4*>(&sm.b[buf][row][kc]) = bv;
+      *reinterpret_cast<floatx4*>(&sm.b[buf][loader_row<PREC>(h)][kc]) = bv;
     }
   }
 }
 
-// Products of one LDS stage into this wave's 64 x 64 quarter.
-template <int PREC>
-__device__ __forceinline__ void compute(const Smem<PREC>& sm, int buf, floatx16 (&acc)[2][2]) {
+// Products of one LDS stage into this wave's 64 x TNV/2 part.
+template <int PREC, int TNV>
+__device__ __forceinline__ void compute(const Smem<PREC, TNV>& sm, int buf, floatx16 (&acc)[2][TNV / 64]) {
+  constexpr int BJ = TNV / 64;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int wm = wave / 2, wn = wave % 2;
   if constexpr (PREC == kBatchBF16x3) {
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 16) {
       const int kq = kk + 8 * (lane / 32);
-      bf16x8 fa[2][2], fb[2][2];  // [block][hi/lo]
+      bf16x8 fa[2][2], fb[BJ][2];  // [block][hi/lo]
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < 2; ++p)
           fa[i][p] = __builtin_bit_cast(
               bf16x8, *reinterpret_cast<const ushort8*>(&sm.a[buf][p][wm * 64 + i * 32 + lane % 32][kq]));
-          fb[i][p] = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const ushort8*>(&sm.b[buf][p][wn * 64 + i * 32 + lane % 32][kq]));
-        }
+#pragma unroll
+      for (int j = 0; j < BJ; ++j)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          fb[j][p] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const ushort8*>(&sm.b[buf][p][wn * (TNV / 2) + j * 32 + lane % 32][kq]));
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < BJ; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][0], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][1], fb[j][0], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i][0], fb[j][1], acc[i][j], 0, 0, 0);
@@ -238,16 +249,15 @@ __device__ __forceinline__ void compute(const Smem<PREC>& sm, int buf, floatx16 
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 2) {
       const int kq = kk + lane / 32;
-      float fa[2], fb[2];
+      float fa[2], fb[BJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        fa[i] = sm.a[buf][wm * 64 + i * 32 + lane % 32][kq];
-        fb[i] = sm.b[buf][wn * 64 + i * 32 + lane % 32][kq];
-      }
+      for (int i = 0; i < 2; ++i) fa[i] = sm.a[buf][wm * 64 + i * 32 + lane % 32][kq];
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) fb[j] = sm.b[buf][wn * (TNV / 2) + j * 32 + lane % 32][kq];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
   }
 }
@@ -260,62 +270,62 @@ __device__ __forceinline__ void compute(const Smem<PREC>& sm, int buf, floatx16 
 // loads of that stage only; a scheduling barrier keeps each fetch at the top of its step. The
 // extra stages lie in the operands' zero padding (or are masked).
 constexpr int kRing = 4;
-template <int PREC, bool MASK>
-__device__ __forceinline__ void tile_gemm(Smem<PREC>& sm, const void* Aa, const void* Ab, const void* Ba,
-                                          const void* Bb, const long (&aoff)[Smem<PREC>::kRowsPerThread],
-                                          const long (&boff)[Smem<PREC>::kRowsPerThread], long as, long bs, int kb,
-                                          int ke, floatx16 (&acc)[2][2]) {
+template <int PREC, int TNV, bool MASK>
+__device__ __forceinline__ void tile_gemm(Smem<PREC, TNV>& sm, const void* Aa, const void* Ab, const void* Ba,
+                                          const void* Bb, const long (&aoff)[Smem<PREC, TNV>::kRowsA],
+                                          const long (&boff)[Smem<PREC, TNV>::kRowsB], long as, long bs, int kb,
+                                          int ke, floatx16 (&acc)[2][TNV / 64]) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
+    for (int j = 0; j < TNV / 64; ++j) acc[i][j] = floatx16{};
   const int s0 = kb / TK;
   int ns = (ke + TK - 1) / TK - s0;
   ns = (ns + kRing - 1) / kRing * kRing;
   // stage of visit position p (positions past the end re-read the last one)
   auto stage = [&](int p) { return s0 + min(p, ns - 1); };
-  Frag<PREC> f[kRing];
+  Frag<PREC, TNV> f[kRing];
 #pragma unroll
-  for (int r = 0; r < kRing; ++r) fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(r));
-  stash<PREC, MASK>(sm, 0, f[0], stage(0), kb, ke);
+  for (int r = 0; r < kRing; ++r) fetch<PREC, TNV>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(r));
+  stash<PREC, TNV, MASK>(sm, 0, f[0], stage(0), kb, ke);
   __syncthreads();
   for (int p = 0; p < ns; p += kRing) {
 #pragma unroll
     for (int r = 0; r < kRing; ++r) {
       // position p + r is in LDS buffer r & 1; f[r] is free again
-      fetch<PREC>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(p + r + kRing));
+      fetch<PREC, TNV>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(p + r + kRing));
       __builtin_amdgcn_sched_barrier(0);
-      compute<PREC>(sm, r & 1, acc);
-      stash<PREC, MASK>(sm, (r + 1) & 1, f[(r + 1) % kRing], stage(p + r + 1), kb, ke);
+      compute<PREC, TNV>(sm, r & 1, acc);
+      stash<PREC, TNV, MASK>(sm, (r + 1) & 1, f[(r + 1) % kRing], stage(p + r + 1), kb, ke);
       __syncthreads();
     }
   }
 }
 
-// Position in the 128 x 128 tile of accumulator element v of block (i, j) for this lane.
+// Position in the tile of accumulator element v of block (i, j) for this lane.
 __device__ __forceinline__ int acc_row(int wm, int i, int v, int lane) {
   return wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane / 32) + (v % 4);
 }
-__device__ __forceinline__ int acc_col(int wn, int j, int lane) { return wn * 64 + j * 32 + lane % 32; }
+template <int TNV>
+__device__ __forceinline__ int acc_col(int wn, int j, int lane) {
+  return wn * (TNV / 2) + j * 32 + lane % 32;
+}
 
 // M-tile descriptor: {penalty index, offset into lists, instance count}
 struct MTile {
   int j, off, cnt;
 };
 
-template <int PREC>
+template <int PREC, int TNV>
 __device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt, int nt, long abase, long bbase,
-                                             long (&aoff)[Smem<PREC>::kRowsPerThread],
-                                             long (&boff)[Smem<PREC>::kRowsPerThread]) {
-  constexpr int RPT = Smem<PREC>::kRowsPerThread;
+                                             long (&aoff)[Smem<PREC, TNV>::kRowsA],
+                                             long (&boff)[Smem<PREC, TNV>::kRowsB]) {
+  // operand rows are list positions, matrix rows are rows; rows past the tile's instances or
+  // past L hold other instances or zero padding (their results are discarded)
 #pragma unroll
-  for (int h = 0; h < RPT; ++h) {
-    const int r = loader_row<PREC>(h);
-    // operand rows are list positions, matrix rows are rows; rows past the tile's instances or
-    // past L hold other instances or zero padding (their results are discarded)
-    aoff[h] = abase + (long)(mt.off + r) * TK;
-    boff[h] = bbase + (long)(nt * TN + r) * TK;
-  }
+  for (int h = 0; h < Smem<PREC, TNV>::kRowsA; ++h) aoff[h] = abase + (long)(mt.off + loader_row<PREC>(h)) * TK;
+#pragma unroll
+  for (int h = 0; h < Smem<PREC, TNV>::kRowsB; ++h) boff[h] = bbase + (long)(nt * TNV + loader_row<PREC>(h)) * TK;
 }
 
 // XCD-aware walk over the grid of (M tile, N tile) pairs with N tiles in [n_begin, n_end).
@@ -462,10 +472,12 @@ __device__ void layer_input(const BatchArgs& a, const float* s_rho, long vofs) {
   }
 }
 
-template <int PREC>
+template <int PREC, int TNV>
 __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
+  constexpr int BJ = TNV / 64;
+  using SM = Smem<PREC, TNV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Smem<PREC>& sm = *reinterpret_cast<Smem<PREC>*>(smem_raw);
+  SM& sm = *reinterpret_cast<SM*>(smem_raw);
   __shared__ int s_count[64];
   __shared__ int s_list[TM];   // instance ids of the current M tile
   __shared__ float s_rho[64];  // grid penalties in FP32
@@ -476,7 +488,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   const long ldk = a.ldk;
   const long vpar = a.bpad * ldk;  // elements per parity of V
   const long as = a.bpad * TK, bs = a.lpad * TK;  // elements per K block of operands / matrices
-  const int ntiles_n = (L + TN - 1) / TN;
+  const int ntiles_n = (L + TNV - 1) / TNV;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha), sigma = (float)a.sigma;
   const float eqs = (float)a.rho_eq_scale;
   unsigned epoch = 0;
@@ -542,21 +554,21 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (!grid_barrier(a.bar, ++epoch)) return;
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
-    const int nt0 = n / TN;  // first row tile holding constraint rows
+    const int nt0 = n / TNV;  // first row tile holding constraint rows
     const TileWalk tw(nmt, nt0, ntiles_n);
     for (int t = tw.first(); t < tw.count; t += tw.per) {
       const MTile mt = mts[tw.mt(t)];
       const int nt = tw.nt(t);
       load_list(mt);
-      long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
-      tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
-      floatx16 acc[2][2];
-      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc);
+      long aoff[SM::kRowsA], boff[SM::kRowsB];
+      tile_offsets<PREC, TNV>(a, mt, nt, 0, 0, aoff, boff);
+      floatx16 acc[2][BJ];
+      tile_gemm<PREC, TNV, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int r = nt * TN + acc_col(wn, j, lane);
+        for (int j = 0; j < BJ; ++j) {
+          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
           if (r < n || r >= L) continue;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
@@ -587,18 +599,18 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       const MTile mt = mts[tw.mt(t)];
       const int nt = tw.nt(t);
       load_list(mt);
-      long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
-      tile_offsets<PREC>(a, mt, nt, vin, (long)mt.j * a.w_stride, aoff, boff);
-      floatx16 acc[2][2];
-      tile_gemm<PREC, false>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, as, bs, 0, L, acc);
+      long aoff[SM::kRowsA], boff[SM::kRowsB];
+      tile_offsets<PREC, TNV>(a, mt, nt, vin, (long)mt.j * a.w_stride, aoff, boff);
+      floatx16 acc[2][BJ];
+      tile_gemm<PREC, TNV, false>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, as, bs, 0, L, acc);
       const float rho_bar = s_rho[mt.j];
       // epilogue, one 32 x 32 block at a time: the 16 elements' state loads are issued
       // together, then the row-local update (relaxation, clamp, dual) and the stores
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int r = nt * TN + acc_col(wn, j, lane);
+        for (int j = 0; j < BJ; ++j) {
+          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
           const bool rin = r < L, xr = r < n;
           const int ri = xr ? r : (rin ? r - n : 0);  // x index, or constraint index
           const float rho = rho_bar * (!xr && a.eq[ri] ? eqs : 1.0f);
@@ -650,19 +662,19 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       const MTile mt = mts[tw.mt(t)];
       const int nt = tw.nt(t);
       load_list(mt);
-      long aoff[Smem<PREC>::kRowsPerThread], boff[Smem<PREC>::kRowsPerThread];
-      tile_offsets<PREC>(a, mt, nt, 0, 0, aoff, boff);
-      floatx16 acc_p[2][2], acc_a[2][2];
-      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc_p);  // P x, A x
-      tile_gemm<PREC, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, n, L, acc_a);  // A'y, 0
+      long aoff[SM::kRowsA], boff[SM::kRowsB];
+      tile_offsets<PREC, TNV>(a, mt, nt, 0, 0, aoff, boff);
+      floatx16 acc_p[2][BJ], acc_a[2][BJ];
+      tile_gemm<PREC, TNV, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc_p);  // P x, A x
+      tile_gemm<PREC, TNV, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, n, L, acc_a);  // A'y, 0
       // per instance (accumulator row) maxima over this tile's rows
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         // q (x rows) or z (z rows) of the block's 2 x 16 elements, loaded together
-        float ext[2][16];
+        float ext[BJ][16];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int r = nt * TN + acc_col(wn, j, lane);
+        for (int j = 0; j < BJ; ++j) {
+          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
           const bool xr = r < n;
           const int ri = xr ? r : (r < L ? r - n : 0);
 #pragma unroll
@@ -677,8 +689,8 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
           const bool valid_i = ti < mt.cnt;
           uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int r = nt * TN + acc_col(wn, j, lane);
+          for (int j = 0; j < BJ; ++j) {
+            const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
             if (!valid_i || r >= L) continue;
             const double pp = (double)acc_p[i][j][v], pa = (double)acc_a[i][j][v];
             if (r < n) {
@@ -791,11 +803,25 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
 
 }  // namespace
 
-BatchPlan plan_batch(int prec) {
-  BatchPlan p{nullptr, 0};
-  const void* fn = prec == kBatchBF16x3 ? reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3>)
-                                        : reinterpret_cast<const void*>(&batch_kernel<kBatchF32>);
-  const size_t smem = prec == kBatchBF16x3 ? sizeof(Smem<kBatchBF16x3>) : sizeof(Smem<kBatchF32>);
+BatchPlan plan_batch(int prec, int tn) {
+  BatchPlan p{nullptr, 0, 0, tn};
+  const void* fn = nullptr;
+  size_t smem = 0;
+  if (prec == kBatchBF16x3 && tn == 128) {
+    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 128>);
+    smem = sizeof(Smem<kBatchBF16x3, 128>);
+  } else if (prec == kBatchBF16x3 && tn == 64) {
+    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 64>);
+    smem = sizeof(Smem<kBatchBF16x3, 64>);
+  } else if (prec == kBatchF32 && tn == 128) {
+    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 128>);
+    smem = sizeof(Smem<kBatchF32, 128>);
+  } else if (prec == kBatchF32 && tn == 64) {
+    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 64>);
+    smem = sizeof(Smem<kBatchF32, 64>);
+  } else {
+    return p;
+  }
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return p;
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return p;
@@ -804,48 +830,16 @@ BatchPlan plan_batch(int prec) {
   if (per_cu < 1) return p;
   p.fn = fn;
   p.grid = cus;  // one workgroup per compute unit
+  p.smem = smem;
   return p;
 }
 
 hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st) {
   if (!p.fn) return hipErrorInvalidValue;
-  const size_t smem = a.prec == kBatchBF16x3 ? sizeof(Smem<kBatchBF16x3>) : sizeof(Smem<kBatchF32>);
   BatchArgs copy = a;
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(p.fn, dim3(p.grid), dim3(BS), args, smem, st);
+  return hipLaunchCooperativeKernel(p.fn, dim3(p.grid), dim3(BS), args, p.smem, st);
 }
-
-namespace {
-// one thread per element of the blocked lpad x ldk destination
-__global__ void split_kernel(long rows, int cols, const double* __restrict__ src, long ld_src,
-                             unsigned short* __restrict__ hi, unsigned short* __restrict__ lo, long lpad, long ldk) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= lpad * ldk) return;
-  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
-  const long r = rem / TK;
-  const int c = (int)(blk * TK + rem % TK);
-  if (r >= rows) {
-    hi[idx] = 0;
-    lo[idx] = 0;
-    return;
-  }
-  const float v = c < cols ? (float)src[r * ld_src + c] : 0.0f;
-  // split the FP64 value: hi from its FP32 rounding, lo from the remaining FP64 difference
-  const unsigned short h = bf16_bits(v);
-  const double diff = c < cols ? src[r * ld_src + c] - (double)bf16_float(h) : 0.0;
-  hi[idx] = h;
-  lo[idx] = bf16_bits((float)diff);
-}
-__global__ void pad_kernel(long rows, int cols, const double* __restrict__ src, long ld_src, float* __restrict__ dst,
-                           long lpad, long ldk) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= lpad * ldk) return;
-  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
-  const long r = rem / TK;
-  const int c = (int)(blk * TK + rem % TK);
-  dst[idx] = (r < rows && c < cols) ? (float)src[r * ld_src + c] : 0.0f;
-}
-}  // namespace
 
 namespace {
 __global__ void fill_status_kernel(int B, int value, int* __restrict__ status) {
@@ -945,6 +939,39 @@ hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m
                      jb, status, stage);
   return hipGetLastError();
 }
+
+namespace {
+// one thread per element of the blocked lpad x ldk destination
+__global__ void split_kernel(long rows, int cols, const double* __restrict__ src, long ld_src,
+                             unsigned short* __restrict__ hi, unsigned short* __restrict__ lo, long lpad, long ldk) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= lpad * ldk) return;
+  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
+  const long r = rem / TK;
+  const int c = (int)(blk * TK + rem % TK);
+  if (r >= rows) {
+    hi[idx] = 0;
+    lo[idx] = 0;
+    return;
+  }
+  const float v = c < cols ? (float)src[r * ld_src + c] : 0.0f;
+  // split the FP64 value: hi from its FP32 rounding, lo from the remaining FP64 difference
+  const unsigned short h = bf16_bits(v);
+  const double diff = c < cols ? src[r * ld_src + c] - (double)bf16_float(h) : 0.0;
+  hi[idx] = h;
+  lo[idx] = bf16_bits((float)diff);
+}
+__global__ void pad_kernel(long rows, int cols, const double* __restrict__ src, long ld_src, float* __restrict__ dst,
+                           long lpad, long ldk) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= lpad * ldk) return;
+  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
+  const long r = rem / TK;
+  const int c = (int)(blk * TK + rem % TK);
+  dst[idx] = (r < rows && c < cols) ? (float)src[r * ld_src + c] : 0.0f;
+}
+}  // namespace
+
 
 hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void* hi, void* lo, long lpad, long ldk,
                       hipStream_t st) {

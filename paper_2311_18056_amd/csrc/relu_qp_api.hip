@@ -112,7 +112,9 @@ struct relu_qp_handle {
   int* bstatus = nullptr;   // slot states, persistent across launches
   int* biter = nullptr;     // iterations since admission
   float* bstage = nullptr;  // warm-start staging: n + m floats and one int
-  rqp::BatchPlan bplan{};
+  rqp::BatchPlan bplan{};            // the tile shape in use
+  rqp::BatchPlan bplans[2]{};        // tile rows 128 and 64
+  double tile_us[2] = {0.0, 0.0};    // autotuner: microseconds per iteration of each shape
 };
 
 namespace {
@@ -335,6 +337,9 @@ int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hip
   return RQP_OK;
 }
 
+int autotune_tiles(relu_qp_handle* h, hipStream_t st);
+int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out, bool copy_out);
+
 int setup_batched(relu_qp_handle* h, const double* P, const double* q, const double* A, const double* l,
                   const double* u, hipStream_t st) {
   const int n = h->n, m = h->m, L = h->L, B = h->batch;
@@ -386,14 +391,16 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
       (rc = upload_f32(static_cast<float*>(h->u), u, (size_t)B * m)))
     return rc;
   if ((rc = build_batch_weights(h, P, A, st))) return rc;
-  h->bplan = rqp::plan_batch(h->bprec);
-  if (!h->bplan.fn) return fail(RQP_EHIP, "no resources for the batched kernel");
-  return RQP_OK;
+  h->bplans[0] = rqp::plan_batch(h->bprec, 128);
+  h->bplans[1] = rqp::plan_batch(h->bprec, 64);
+  if (!h->bplans[0].fn || !h->bplans[1].fn) return fail(RQP_EHIP, "no resources for the batched kernel");
+  h->bplan = h->bplans[0];
+  return autotune_tiles(h, st);
 }
 
 // One persistent launch of the batched kernel over every running or admitted slot, for at most
 // `steps` iterations, then copies of the slot results into out.
-int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out) {
+int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out, bool copy_out) {
   const int B = h->batch;
   HIP_OR_FAIL(hipMemsetAsync(h->bbar, 0, 1024 * 4, st));
   __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
@@ -450,6 +457,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.abort_flag = h->abort_d;
   hipError_t e = rqp::launch_batch(a, h->bplan, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+  if (!copy_out) return RQP_OK;
   HIP_OR_FAIL(hipMemcpyAsync(out->x, h->bX, (size_t)B * h->n * 4, hipMemcpyDeviceToDevice, st));
   HIP_OR_FAIL(hipMemcpyAsync(out->z, h->bZ, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
   HIP_OR_FAIL(hipMemcpyAsync(out->y, h->bY, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
@@ -459,10 +467,59 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   return RQP_OK;
 }
 
+// Autotuner of the batched GEMM's tile shape (128 or 64 matrix rows per tile): each shape runs
+// two check intervals of every slot from a cold start on the handle's own data, timed with HIP
+// events; the faster one is kept. Slots, statuses and state are reset to idle afterwards. The
+// shapes agree to rounding (every accumulator element sees the same products, in another
+// interleaving on the matrix cores): few tiles (small batches) favour 64 rows, many 128.
+int autotune_tiles(relu_qp_handle* h, hipStream_t st) {
+  const int B = h->batch, steps = 2 * h->s.check_interval;
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(hipEventCreate(&e0));
+  HIP_OR_FAIL(hipEventCreate(&e1));
+  relu_qp_result tmp{h->bX, h->bY, h->bZ, h->biter, h->bstatus, h->bjb, nullptr, nullptr, nullptr};
+  int rc = RQP_OK;
+  for (int v = 0; v < 2 && rc == RQP_OK; ++v) {
+    h->bplan = h->bplans[v];
+    float best = 1e30f;
+    for (int rep = 0; rep < 2 && rc == RQP_OK; ++rep) {  // the first run also warms caches
+      if (hipSuccess != rqp::fill_status(B, rqp::kSlotAdmitCold, h->bstatus, st) ||
+          hipSuccess != hipEventRecord(e0, st)) {
+        rc = fail(RQP_EHIP, "autotuner launch failed");
+        break;
+      }
+      rc = launch_batched(h, steps, st, &tmp, /*copy_out=*/false);
+      if (rc) break;
+      float ms = 0.0f;
+      if (hipSuccess != hipEventRecord(e1, st) || hipSuccess != hipEventSynchronize(e1) ||
+          hipSuccess != hipEventElapsedTime(&ms, e0, e1)) {
+        rc = fail(RQP_EHIP, "autotuner timing failed");
+        break;
+      }
+      best = ms < best ? ms : best;
+    }
+    h->tile_us[v] = best * 1e3 / steps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  h->bplan = h->tile_us[1] < h->tile_us[0] ? h->bplans[1] : h->bplans[0];
+  // back to idle slots with a zero state
+  std::vector<int> j0(B, h->j0);
+  HIP_OR_FAIL(rqp::fill_status(B, rqp::kSlotIdle, h->bstatus, st));
+  HIP_OR_FAIL(hipMemsetAsync(h->biter, 0, (size_t)B * 4, st));
+  HIP_OR_FAIL(hipMemsetAsync(h->bX, 0, (size_t)B * h->n * 4, st));
+  HIP_OR_FAIL(hipMemsetAsync(h->bZ, 0, (size_t)B * h->m * 4, st));
+  HIP_OR_FAIL(hipMemsetAsync(h->bY, 0, (size_t)B * h->m * 4, st));
+  HIP_OR_FAIL(hipMemcpyAsync(h->bjb, j0.data(), (size_t)B * 4, hipMemcpyHostToDevice, st));
+  HIP_OR_FAIL(hipStreamSynchronize(st));
+  return RQP_OK;
+}
+
 int solve_batched(relu_qp_handle* h, hipStream_t st, relu_qp_result* out) {
   const bool warm = h->warm_pending || (h->warm_mode && h->have_prev);
   HIP_OR_FAIL(rqp::fill_status(h->batch, warm ? rqp::kSlotAdmitWarm : rqp::kSlotAdmitCold, h->bstatus, st));
-  const int rc = launch_batched(h, h->s.max_iter, st, out);
+  const int rc = launch_batched(h, h->s.max_iter, st, out, true);
   if (rc) return rc;
   h->warm_pending = false;
   h->have_prev = true;
@@ -913,7 +970,28 @@ int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* 
     return fail(RQP_EINVAL, "serving needs max_iter to be a multiple of check_interval");
   if (n_checks < 1 || n_checks > h->s.max_iter / h->s.check_interval)
     return fail(RQP_EINVAL, "n_checks must be in [1, max_iter / check_interval]");
-  return launch_batched(h, n_checks * h->s.check_interval, static_cast<hipStream_t>(stream), out);
+  return launch_batched(h, n_checks * h->s.check_interval, static_cast<hipStream_t>(stream), out, true);
+}
+
+int relu_qp_get_tile(const relu_qp_handle* h, int* tile_rows, double* us_per_iter) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!h->batched) return fail(RQP_ESTATE, "tile shapes exist only with the batched engine");
+  if (tile_rows) *tile_rows = h->bplan.tn;
+  if (us_per_iter) {
+    us_per_iter[0] = h->tile_us[0];
+    us_per_iter[1] = h->tile_us[1];
+  }
+  return RQP_OK;
+}
+
+int relu_qp_set_tile(relu_qp_handle* h, int tile_rows) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!h->batched) return fail(RQP_ESTATE, "tile shapes exist only with the batched engine");
+  if (tile_rows == 128) h->bplan = h->bplans[0];
+  else if (tile_rows == 64) h->bplan = h->bplans[1];
+  else if (tile_rows == 0) h->bplan = h->tile_us[1] < h->tile_us[0] ? h->bplans[1] : h->bplans[0];
+  else return fail(RQP_EINVAL, "tile_rows must be 128, 64 or 0 (the autotuner's choice)");
+  return RQP_OK;
 }
 
 int relu_qp_abort(relu_qp_handle* h) {

@@ -240,6 +240,16 @@ class Solver:
         ]
         return t, res
 
+    def tile(self):
+        """(tile rows in use, {128: us/iter, 64: us/iter} from the autotuner) of a batched handle."""
+        t = c_int()
+        us = (c_double * 2)()
+        check(lib().relu_qp_get_tile(self._h, byref(t), us))
+        return t.value, {128: us[0], 64: us[1]}
+
+    def set_tile(self, tile_rows: int):
+        check(lib().relu_qp_set_tile(self._h, int(tile_rows)))
+
     def abort(self):
         check(lib().relu_qp_abort(self._h))
 

@@ -217,3 +217,33 @@ def test_batch_ragged_tiles_mixed_statuses(rq):
                            rho_replay=res["rho_hist"][b][: it // 25].tolist())
         for name in ("x", "z", "y"):
             assert _rel(res[name][b], getattr(ref, name)) <= 1e-4, (b, name)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
+    """The autotuner times both tile shapes at setup and keeps the faster; each shape, forced,
+    matches the oracle with its own schedule replayed. (The shapes agree to rounding only: the
+    matrix cores are fed the same products per element, but in another interleaving.)"""
+    P, q0, A, l0, u0 = random_qp(150, 0, 80, seed=41)
+    B = 140
+    rng = np.random.default_rng(8)
+    q = q0[None, :] + 0.5 * rng.standard_normal((B, 150))
+    l = np.repeat(l0[None, :], B, axis=0)
+    u = np.repeat(u0[None, :], B, axis=0)
+    sol = rq.Solver(P, q, A, l, u, precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60)
+    tn, us = sol.tile()
+    assert tn in (64, 128) and us[128] > 0 and us[64] > 0
+    assert tn == (64 if us[64] < us[128] else 128)
+    tol = 1e-4 if prec == "fp32" else 5e-3
+    for shape in (128, 64):
+        sol.set_tile(shape)
+        assert sol.tile()[0] == shape
+        sol.solve()
+        res = sol.result()
+        for b in (0, 77, B - 1):
+            ref = oracle.solve(P, q[b], A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60),
+                               rho_replay=res["rho_hist"][b][:3].tolist())
+            for name in ("x", "z", "y"):
+                assert _rel(res[name][b], getattr(ref, name)) <= tol, (prec, shape, b, name)
+    sol.close()
+    print(f"\n{prec}: autotuner us/iteration {us}, chose {tn}")

@@ -368,3 +368,30 @@ def test_wide_rows_streamed_fp32(rq):
     kappa = max(1.0, max(admm.rho_grid(_oracle_settings(n_rho=8))[j] for j in res["rho_hist"] + [2]) * 1e3
                 * max(np.max(np.abs(ref.z)), 1.0) / max(np.max(np.abs(ref.y)), 1.0))
     _close(res["y"], ref.y, 1e-4 * kappa, "y")
+
+
+def test_c2_humanoid_shape_fp32(rq):
+    """Configuration 2 (n = 600 controls, m = 1800: control limits and condensed state limits),
+    FP32: 100 fixed iterations against the oracle with the GPU's schedule replayed, and a solve
+    to eps = 1e-3 that passes the FP64 residual test and lies near the oracle's solution."""
+    prob = make_config("c2")
+    x0 = x0_batch(prob.nx, 2, 1020, scale=3.0)  # scaled so that limits bind (1-2 % active rows)
+    q, l, u = prob.instance(x0[0])
+    res = _fixed_run(rq, prob.P, q, prob.A, l, u, "fp32", 100, n_rho=8)
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=100, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    _compare(res, ref, TOL["fp32"])
+    q, l, u = prob.instance(x0[1])
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp32", n_rho=8)
+    sol.solve()
+    r = sol.result()
+    sol.close()
+    assert r["status"] == rq.RQP_SOLVED
+    nm = admm.residual_norms(prob.P, q, prob.A, r["x"], r["z"], r["y"])
+    assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
+    assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+    xs = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=1e-10, eps_rel=1e-10, n_rho=8,
+                                                                max_iter=40000)).x
+    err = np.max(np.abs(r["x"] - xs)) / max(np.max(np.abs(xs)), 1.0)
+    print(f"\nc2 FP32 solution error at eps=1e-3: {err:.2e} ({r['iterations']} iterations)")
+    assert err < 5e-2
