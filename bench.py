@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals per rate")
     ap.add_argument("--slots", type=int, default=256, help="serve: slots per family")
     ap.add_argument("--families", default="f200,f800,f1600,f3200")
+    ap.add_argument("--hbm-budget-gib", type=float, default=0.0,
+                    help="serve: device memory the families' handles may hold together (0 = all resident)")
     return ap.parse_args()
 
 
@@ -341,6 +343,7 @@ def bench_batch(args):
     if args.steady_iters > 0:
         k = min(args.steady_iters, 200)
         fx = rq.Solver(prob.P, q0, prob.A, l0, u0, **dict(settings, eps_abs=0.0, eps_rel=0.0, max_iter=k))
+        fx.set_tile(sol.tile()[0])  # the shape the timed solves ran with
         fx.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
         fx.update_x0_device(x0_dev[0], stream)
         fx.solve(stream)
@@ -380,6 +383,7 @@ def bench_batch(args):
         "iters_per_solve": float(np.mean(it)),
         "status_counts": {rq.STATUS_NAMES[int(s)]: int(np.sum(st == s)) for s in np.unique(st)},
         "setup_ms": setup_ms,
+        "tile_autotuner": {"rows": sol.tile()[0], "us_per_iter": sol.tile()[1]},
         "steady_state": steady,
         "roofline": {
             "bound": "mfma",
@@ -388,7 +392,7 @@ def bench_batch(args):
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": None,
-            "kernel": f"batch_kernel<{1 if args.precision == 'bf16x3' else 0}>",
+            "kernel": f"batch_kernel<{1 if args.precision == 'bf16x3' else 0}, {sol.tile()[0]}>",
             "alg_flops_per_unit": flops_per_unit,
             "avg_launch_us": float(np.mean(kern_ms) * 1e3),
         },
@@ -412,8 +416,9 @@ def bench_serve(args):
     probs = [make_config(f) for f in args.families.split(",")]
     gens = [lambda rng, p=p: args.x0_scale * rng.uniform(-1.0, 1.0, p.nx) for p in probs]
     settings = dict(n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000, check_interval=25)
-    fams = [Family.from_mpc(p, slots=args.slots, precision=args.precision, **settings).attach_single(p, **settings)
-            for p in probs]
+    budget = int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib > 0 else None
+    fams = [Family.from_mpc(p, slots=args.slots, precision=args.precision, lazy=budget is not None,
+                            **settings).attach_single(p, **settings) for p in probs]
     singles = []
     for p in probs:
         q, l, u = p.instance(np.zeros(p.nx))
@@ -427,8 +432,12 @@ def bench_serve(args):
         for f in fams:
             f.pin = None
         warm_s = 0.1 * max(r.t_arrival for r in reqs)  # arrivals in the first 10 % are warm-up
-        Server(fams, n_checks=1, warm=True).run(reqs, time_limit=args.duration * 3)
+        srv = Server(fams, n_checks=1, warm=True, hbm_budget=budget)
+        srv.run(reqs, time_limit=args.duration * 3)
         served = latency_summary(reqs, warmup=warm_s)
+        mem = srv.memory
+        served["memory"] = {"budget_gib": None if budget is None else budget / 2**30,
+                            "peak_resident_gib": mem.peak / 2**30, "loads": mem.loads, "evictions": mem.evictions}
         reqs = poisson_requests(rate, count, args.duration, gens, seed=4 + i)
         serve_plain(singles, reqs, time_limit=args.duration * 3)
         plain = latency_summary(reqs, warmup=warm_s)
@@ -440,13 +449,13 @@ def bench_serve(args):
         "n_gpus": 1,
         "data": "synthetic",
         "config": {"workload": "MPC families " + args.families + ", Poisson arrivals, family uniform",
-                   "slots_per_family": args.slots, "precision": args.precision, "x0_scale": args.x0_scale},
+                   "slots_per_family": args.slots, "precision": args.precision, "x0_scale": args.x0_scale,
+                   "family_gib": {name: f.bytes / 2**30 for name, f in zip(args.families.split(","), fams)}},
         "rates": rows,
     }
     for f in fams:
-        f.solver.close()
-        if f.single is not None:
-            f.single.close()
+        if f.resident:
+            f.unload()
     for s in singles:
         s.close()
     print(json.dumps(out), flush=True)

@@ -205,6 +205,18 @@ int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* 
 int relu_qp_get_tile(const relu_qp_handle* h, int* tile_rows, double* us_per_iter);
 int relu_qp_set_tile(relu_qp_handle* h, int tile_rows);
 
+/* Device memory, for admission by memory (a server keeps problem families resident in HBM
+ * while their sizes fit a budget).
+ * relu_qp_device_bytes: the bytes the handle holds now (requested sizes of its resident
+ * allocations: layer and check weights for every penalty, state, operand and exchange buffers,
+ * parametric data). RQP_ESTATE on NULL.
+ * relu_qp_footprint: the same figure for a handle that relu_qp_setup(n, m, s) would create,
+ * plus F, E, lo, hi if nx > 0 (relu_qp_set_parametric), computed on the host without any
+ * device call; *setup_extra (may be NULL) receives the FP64 workspace setup holds on top of
+ * that while it factors. RQP_EINVAL for bad sizes or settings (as relu_qp_setup). */
+int relu_qp_device_bytes(const relu_qp_handle* h, size_t* bytes);
+int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* bytes, size_t* setup_extra);
+
 /* Ask a running solve to stop with status RQP_ABORTED (any thread). The flag lives in host
  * memory and a kernel polls it at every 16th check of a launch (every 400 iterations with the
  * default check_interval), since each poll is a PCIe round trip. */

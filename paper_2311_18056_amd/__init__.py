@@ -21,4 +21,4 @@ from ._lib import (  # noqa: F401
     ReluQPError,
     lib,
 )
-from .solver import STATUS_NAMES, Solver, default_settings  # noqa: F401
+from .solver import STATUS_NAMES, Solver, default_settings, footprint  # noqa: F401

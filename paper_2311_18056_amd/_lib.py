@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_void_p
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_size_t, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librelu_qp.so")
@@ -45,6 +45,8 @@ EXPORTS = [
     "relu_qp_step",
     "relu_qp_get_tile",
     "relu_qp_set_tile",
+    "relu_qp_device_bytes",
+    "relu_qp_footprint",
     "relu_qp_abort",
     "relu_qp_max_checks",
     "relu_qp_get_rho_grid",
@@ -126,6 +128,8 @@ def lib():
     L.relu_qp_step.argtypes = [h, c_int, c_void_p, POINTER(Result)]
     L.relu_qp_get_tile.argtypes = [h, POINTER(c_int), POINTER(c_double)]
     L.relu_qp_set_tile.argtypes = [h, c_int]
+    L.relu_qp_device_bytes.argtypes = [h, POINTER(c_size_t)]
+    L.relu_qp_footprint.argtypes = [c_int, c_int, POINTER(Settings), c_int, POINTER(c_size_t), POINTER(c_size_t)]
     L.relu_qp_abort.argtypes = [h]
     L.relu_qp_max_checks.argtypes = [h]
     L.relu_qp_get_rho_grid.argtypes = [h, _dp, POINTER(c_int)]

@@ -115,6 +115,7 @@ struct relu_qp_handle {
   rqp::BatchPlan bplan{};            // the tile shape in use
   rqp::BatchPlan bplans[2]{};        // tile rows 128 and 64
   double tile_us[2] = {0.0, 0.0};    // autotuner: microseconds per iteration of each shape
+  size_t dev_bytes = 0;              // requested bytes of the resident device allocations
 };
 
 namespace {
@@ -130,6 +131,18 @@ void free_handle(relu_qp_handle* h) {
     if (p) (void)hipFree(p);
   if (h->abort_h) (void)hipHostFree(h->abort_h);
   delete h;
+}
+
+// Resident device allocation of a handle (counted in h->dev_bytes; freed by free_handle).
+hipError_t dmalloc(relu_qp_handle* h, void** p, size_t bytes) {
+  const size_t b = bytes ? bytes : 8;
+  hipError_t e = hipMalloc(p, b);
+  if (e == hipSuccess) h->dev_bytes += b;
+  return e;
+}
+template <typename T>
+hipError_t dmalloc(relu_qp_handle* h, T** p, size_t bytes) {
+  return dmalloc(h, reinterpret_cast<void**>(p), bytes);
 }
 
 int validate_settings(const relu_qp_settings* s) {
@@ -277,9 +290,9 @@ int alloc_exchange(relu_qp_handle* h) {
   const size_t words = h->esize == 8 ? 2 : 1;
   h->xw_words = 2 * (size_t)h->L * words;
   h->xn_words = 2 * (size_t)h->L * 8 * 2;  // any grid has at most L workgroups
-  HIP_OR_FAIL(hipMalloc(&h->xw, h->xw_words * 8));
-  HIP_OR_FAIL(hipMalloc(&h->xc, h->xw_words * 8));
-  HIP_OR_FAIL(hipMalloc(&h->xn, h->xn_words * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->xw, h->xw_words * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->xc, h->xw_words * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->xn, h->xn_words * 8));
   HIP_OR_FAIL(hipMemset(h->xw, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xc, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xn, 0, h->xn_words * 8));
@@ -338,7 +351,8 @@ int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hip
 }
 
 int autotune_tiles(relu_qp_handle* h, hipStream_t st);
-int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out, bool copy_out);
+int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out, bool copy_out,
+                   bool fixed_iters = false);
 
 int setup_batched(relu_qp_handle* h, const double* P, const double* q, const double* A, const double* l,
                   const double* u, hipStream_t st) {
@@ -357,7 +371,7 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->w_stride * es;
   const size_t vbytes = (size_t)h->bpad * h->ldk * es;
   const size_t ntile_max = (size_t)B / rqp::kTileM + nr + 1;
-  auto al = [](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 8) == hipSuccess; };
+  auto al = [h](void** p, size_t bytes) { return dmalloc(h, p, bytes) == hipSuccess; };
   const bool two = h->bprec == rqp::kBatchBF16x3;
   if (!al(&h->bWa, wbytes) || (two && !al(&h->bWb, wbytes)) || !al(&h->bCa, cbytes) || (two && !al(&h->bCb, cbytes)) ||
       !al((void**)&h->bX, (size_t)B * n * 4) || !al((void**)&h->bZ, (size_t)B * m * 4) ||
@@ -399,8 +413,10 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
 }
 
 // One persistent launch of the batched kernel over every running or admitted slot, for at most
-// `steps` iterations, then copies of the slot results into out.
-int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out, bool copy_out) {
+// `steps` iterations, then copies of the slot results into out. fixed_iters: no instance stops
+// at a check (every one runs all `steps` iterations, as the timing of the autotuner needs).
+int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result* out, bool copy_out,
+                   bool fixed_iters) {
   const int B = h->batch;
   HIP_OR_FAIL(hipMemsetAsync(h->bbar, 0, 1024 * 4, st));
   __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
@@ -432,7 +448,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.rho_eq_scale = h->s.rho_eq_scale;
   a.max_iter = h->s.max_iter;
   a.check_interval = h->s.check_interval;
-  a.terminate = !(h->s.eps_abs == 0.0 && h->s.eps_rel == 0.0);
+  a.terminate = !fixed_iters && !(h->s.eps_abs == 0.0 && h->s.eps_rel == 0.0);
   a.j0 = h->j0;
   a.steps = steps;
   a.X = h->bX;
@@ -488,7 +504,7 @@ int autotune_tiles(relu_qp_handle* h, hipStream_t st) {
         rc = fail(RQP_EHIP, "autotuner launch failed");
         break;
       }
-      rc = launch_batched(h, steps, st, &tmp, /*copy_out=*/false);
+      rc = launch_batched(h, steps, st, &tmp, /*copy_out=*/false, /*fixed_iters=*/true);
       if (rc) break;
       float ms = 0.0f;
       if (hipSuccess != hipEventRecord(e1, st) || hipSuccess != hipEventSynchronize(e1) ||
@@ -619,8 +635,8 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
     return code;
   };
   const size_t nr = h->grid.size();
-  if (hipMalloc(&h->eq_d, (size_t)m) != hipSuccess || hipMalloc(&h->grid_d, nr * 8) != hipSuccess ||
-      hipMalloc(&h->mid_d, h->mid.size() * 8) != hipSuccess) {
+  if (dmalloc(h, &h->eq_d, (size_t)m) != hipSuccess || dmalloc(h, &h->grid_d, nr * 8) != hipSuccess ||
+      dmalloc(h, &h->mid_d, h->mid.size() * 8) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(RQP_ENOMEM, "device allocation failed"));
   }
@@ -642,12 +658,12 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
     return RQP_OK;
   }
 
-  if (hipMalloc(&h->W, nr * h->w_stride * h->esize) != hipSuccess ||
-      hipMalloc(&h->C, (size_t)h->w_stride * h->esize) != hipSuccess ||
-      hipMalloc(&h->q, (size_t)n * h->esize) != hipSuccess || hipMalloc(&h->l, (size_t)m * h->esize) != hipSuccess ||
-      hipMalloc(&h->u, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->xs, (size_t)n * h->esize) != hipSuccess ||
-      hipMalloc(&h->zs, (size_t)m * h->esize) != hipSuccess || hipMalloc(&h->ys, (size_t)m * h->esize) != hipSuccess ||
-      hipMalloc(&h->js, sizeof(int)) != hipSuccess || hipMalloc(&h->err, sizeof(unsigned)) != hipSuccess) {
+  if (dmalloc(h, &h->W, nr * h->w_stride * h->esize) != hipSuccess ||
+      dmalloc(h, &h->C, (size_t)h->w_stride * h->esize) != hipSuccess ||
+      dmalloc(h, &h->q, (size_t)n * h->esize) != hipSuccess || dmalloc(h, &h->l, (size_t)m * h->esize) != hipSuccess ||
+      dmalloc(h, &h->u, (size_t)m * h->esize) != hipSuccess || dmalloc(h, &h->xs, (size_t)n * h->esize) != hipSuccess ||
+      dmalloc(h, &h->zs, (size_t)m * h->esize) != hipSuccess || dmalloc(h, &h->ys, (size_t)m * h->esize) != hipSuccess ||
+      dmalloc(h, &h->js, sizeof(int)) != hipSuccess || dmalloc(h, &h->err, sizeof(unsigned)) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(RQP_ENOMEM, "device allocation failed (n=%d, m=%d, %zu penalties)", n, m, nr));
   }
@@ -740,16 +756,21 @@ int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const dou
   if (rc) return rc;
   for (int i = 0; i < h->m; ++i)
     if ((lo[i] == hi[i]) != (h->eq[i] != 0)) return fail(RQP_EINVAL, "equality pattern of lo/hi differs at %d", i);
-  for (void** p : {(void**)&h->F_d, (void**)&h->E_d, (void**)&h->lo_d, (void**)&h->hi_d})
+  const size_t sizes[4] = {(size_t)h->n * h->nx * 8, (size_t)h->m * h->nx * 8, (size_t)h->m * 8, (size_t)h->m * 8};
+  int k = 0;
+  for (void** p : {(void**)&h->F_d, (void**)&h->E_d, (void**)&h->lo_d, (void**)&h->hi_d}) {
     if (*p) {
       (void)hipFree(*p);
       *p = nullptr;
+      h->dev_bytes -= sizes[k] ? sizes[k] : 8;
     }
+    ++k;
+  }
   h->nx = nx;
-  HIP_OR_FAIL(hipMalloc(&h->F_d, (size_t)h->n * nx * 8));
-  HIP_OR_FAIL(hipMalloc(&h->E_d, (size_t)h->m * nx * 8));
-  HIP_OR_FAIL(hipMalloc(&h->lo_d, (size_t)h->m * 8));
-  HIP_OR_FAIL(hipMalloc(&h->hi_d, (size_t)h->m * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->F_d, (size_t)h->n * nx * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->E_d, (size_t)h->m * nx * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->lo_d, (size_t)h->m * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->hi_d, (size_t)h->m * 8));
   HIP_OR_FAIL(hipMemcpy(h->F_d, F, (size_t)h->n * nx * 8, hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(h->E_d, E, (size_t)h->m * nx * 8, hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(h->lo_d, lo, (size_t)h->m * 8, hipMemcpyHostToDevice));
@@ -1022,6 +1043,63 @@ int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (grid) *grid = h->batched ? h->bplan.grid : h->grid_wg;
   if (block) *block = h->batched ? rqp::kBatchBlock : rqp::kLayerBlock;
+  return RQP_OK;
+}
+
+int relu_qp_device_bytes(const relu_qp_handle* h, size_t* bytes) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!bytes) return fail(RQP_EINVAL, "bytes is NULL");
+  *bytes = h->dev_bytes;
+  return RQP_OK;
+}
+
+// The resident allocations of relu_qp_setup (and relu_qp_set_parametric), size by size, with
+// the same expressions the allocating code uses, and the FP64 workspace setup holds on top of
+// them while it factors; no device call.
+int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* bytes, size_t* setup_extra) {
+  if (!bytes) return fail(RQP_EINVAL, "bytes is NULL");
+  if (n < 1 || m < 1 || nx < 0) return fail(RQP_EINVAL, "need n >= 1, m >= 1, nx >= 0");
+  int rc = validate_settings(s);
+  if (rc) return rc;
+  std::vector<double> grid, mid;
+  int j0 = 0;
+  make_grid(*s, grid, mid, j0);
+  const size_t nr = grid.size(), L = (size_t)n + m;
+  auto a8 = [](size_t b) { return b ? b : (size_t)8; };
+  size_t t = a8(m) + a8(nr * 8) + a8(mid.size() * 8);
+  if (is_batched(*s)) {
+    const size_t B = s->batch;
+    const bool two = s->precision == RQP_BF16X3;
+    const size_t es = two ? 2 : 4;
+    const size_t ldk = (L + rqp::kTileK - 1) / rqp::kTileK * rqp::kTileK + 4 * rqp::kTileK;
+    const size_t lpad = (L + rqp::kTileN - 1) / rqp::kTileN * rqp::kTileN;
+    const size_t bpad = (B + rqp::kTileM - 1) / rqp::kTileM * rqp::kTileM + rqp::kTileM;
+    const size_t w_stride = lpad * ldk, vbytes = bpad * ldk * es;
+    const size_t ntile_max = B / rqp::kTileM + nr + 1;
+    const size_t nw = two ? 2 : 1;
+    t += nw * (nr * w_stride * es + w_stride * es + 3 * vbytes);  // layer and check weights, V, CV
+    t += B * n * 4 + 2 * B * m * 4;                                // x, z, y
+    t += B * 4 + B * 64 + B * 4 + B * 4;                           // penalty index, norms, lists, positions
+    t += (1 + 3 * ntile_max) * 4 + 1024 * 4;                       // tile lists, barrier words
+    t += B * n * 4 + 2 * B * m * 4;                                // q, l, u
+    t += 2 * B * 4 + (L + 1) * 4;                                  // status, iterations, staging
+  } else {
+    const size_t es = s->precision == RQP_FP64 ? 8 : 4;
+    const size_t ldw = (L + 3) / 4 * 4, w_stride = L * ldw;
+    t += nr * w_stride * es + w_stride * es;  // layer and check matrices
+    t += 2 * ((size_t)n + 2 * m) * es;        // q, l, u and x, z, y
+    t += 4 + 4;                               // penalty index, error word
+    const size_t words = es == 8 ? 2 : 1;
+    t += 2 * (2 * L * words * 8) + 2 * L * 8 * 2 * 8;  // exchange buffers
+  }
+  if (nx > 0) t += ((size_t)n + m) * nx * 8 + 2 * (size_t)m * 8;
+  *bytes = t;
+  if (setup_extra) {
+    const size_t nn = (size_t)n * n, mn = (size_t)m * n, mm = (size_t)m * m;
+    size_t w = (3 * nn + 2 * mn + mm + 2 * 32 * (size_t)n + 32 * 32 + m) * 8 + sizeof(int);
+    if (is_batched(*s)) w += L * L * 8;
+    *setup_extra = w;
+  }
   return RQP_OK;
 }
 

@@ -14,6 +14,12 @@ engine instead (``relu_qp_solve_sequence``: the few queued requests back to back
 at light load a batched step over a nearly empty batch of a large family costs far more than a
 handful of single-instance solves.
 
+Admission by memory: with an HBM budget, a family's handles (layer weights for every penalty,
+slot state, result buffers; ``footprint`` gives their bytes before any is created) are resident
+only while they fit. A family with queued requests is loaded when its bytes fit beside the
+resident ones, after unloading idle families (no busy slot) least recently used first; if it
+cannot fit yet, families whose queued work is newer stop admitting, drain, and become idle.
+
 Latency is measured from a request's arrival time to the moment its result is on the host.
 """
 
@@ -27,7 +33,7 @@ import numpy as np
 import torch
 
 from ._lib import RQP_RUNNING
-from .solver import Solver
+from .solver import Solver, footprint
 
 
 @dataclass
@@ -46,7 +52,7 @@ class Request:
 class Family:
     """One QP family: its batched handle, slot bookkeeping and warm-start source."""
 
-    solver: Solver
+    solver: Solver | None
     stage: int                  # entries per horizon stage of x and of the constraint rows
     nx: int
     free: list = field(default_factory=list)
@@ -54,38 +60,152 @@ class Family:
     queue: collections.deque = field(default_factory=collections.deque)
     pin: int | None = None      # slot holding the family's most recent solution
     single: Solver | None = None  # optional single-instance handle for light load
+    bytes: int = 0              # device bytes of the family's handles while resident
+    last_used: float = 0.0
+    keep_x: bool = False
+    spec: dict = field(default_factory=dict)  # what load() builds
 
     @classmethod
-    def from_mpc(cls, prob, slots: int, precision: str = "fp32", keep_x: bool = False, **settings):
-        zq = np.zeros((slots, prob.n))
-        lo = np.repeat(prob.lo[None, :], slots, axis=0)
-        hi = np.repeat(prob.hi[None, :], slots, axis=0)
-        s = Solver(prob.P, zq, prob.A, lo, hi, precision=precision, engine="batch", **settings)
-        s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
-        fam = cls(solver=s, stage=prob.nu, nx=prob.nx)
-        fam.free = list(range(slots))
-        fam.keep_x = keep_x
+    def from_mpc(cls, prob, slots: int, precision: str = "fp32", keep_x: bool = False, lazy: bool = False,
+                 **settings):
+        """lazy: only size the family (``footprint``); its handles are built by load()."""
+        fam = cls(solver=None, stage=prob.nu, nx=prob.nx, keep_x=keep_x)
+        fam.spec = dict(prob=prob, slots=slots, precision=precision, settings=settings, single=None)
+        fam.bytes = footprint(prob.n, prob.m, prob.nx, batch=slots, precision=precision, engine="batch",
+                              **settings)["resident"]
+        if not lazy:
+            fam.load()
         return fam
+
+    @property
+    def resident(self) -> bool:
+        return self.solver is not None
 
     def attach_single(self, prob, **settings):
         """Single-instance handle (FP32) of the same family, for light-load sequence launches."""
+        self.spec["single"] = settings
+        self.bytes += footprint(prob.n, prob.m, prob.nx, batch=1, precision="fp32", engine="single",
+                                **settings)["resident"]
+        if self.resident:
+            self._load_single()
+        return self
+
+    def _load_single(self):
+        prob, settings = self.spec["prob"], self.spec["single"]
         q, l, u = prob.instance(np.zeros(prob.nx))
         s = Solver(prob.P, q, prob.A, l, u, precision="fp32", engine="single", **settings)
         s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
         self.single = s
-        return self
+
+    def load(self):
+        """Build the family's device handles (setup on the device: factorizations per penalty)."""
+        if self.resident:
+            return
+        sp = self.spec
+        prob, slots = sp["prob"], sp["slots"]
+        zq = np.zeros((slots, prob.n))
+        lo = np.repeat(prob.lo[None, :], slots, axis=0)
+        hi = np.repeat(prob.hi[None, :], slots, axis=0)
+        s = Solver(prob.P, zq, prob.A, lo, hi, precision=sp["precision"], engine="batch", **sp["settings"])
+        s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+        self.solver = s
+        self.free, self.busy, self.pin = list(range(slots)), {}, None
+        if sp["single"] is not None:
+            self._load_single()
+
+    def unload(self):
+        """Free the family's device handles (no slot may be busy); queued requests stay queued."""
+        assert not self.busy, "unload with busy slots"
+        for s in (self.solver, self.single):
+            if s is not None:
+                s.close()
+        self.solver, self.single, self.pin = None, None, None
+        self.free = []
+        torch.cuda.empty_cache()  # hand the result tensors' memory back for the next handle
+
+
+class MemoryPolicy:
+    """Which families are resident under an HBM budget (host logic only).
+
+    Works on any objects with ``bytes``, ``resident``, ``busy``, ``queue`` (requests with
+    ``t_arrival``), ``last_used``, ``load()`` and ``unload()``."""
+
+    def __init__(self, budget: int | None):
+        self.budget = budget
+        self.loads = 0
+        self.evictions = 0
+        self.peak = 0
+
+    def used(self, families) -> int:
+        return sum(f.bytes for f in families if f.resident)
+
+    def check(self, families):
+        if self.budget is None:
+            return
+        for f in families:
+            if f.bytes > self.budget:
+                raise ValueError(f"a family needs {f.bytes} bytes, more than the budget {self.budget}")
+        if self.used(families) > self.budget:
+            raise ValueError("the families already resident exceed the budget")
+
+    def _fit(self, fam, families) -> bool:
+        used = self.used(families)
+        if used + fam.bytes <= self.budget:
+            return True
+        head = fam.queue[0].t_arrival
+        cands = [g for g in families if g is not fam and g.resident and not g.busy
+                 and (not g.queue or g.queue[0].t_arrival > head)]
+        cands.sort(key=lambda g: (bool(g.queue), g.last_used))
+        free_able = sum(g.bytes for g in cands)
+        if used - free_able + fam.bytes > self.budget:
+            return False  # not even with every candidate gone: unload nothing yet
+        for g in cands:
+            g.unload()
+            self.evictions += 1
+            used -= g.bytes
+            if used + fam.bytes <= self.budget:
+                break
+        return True
+
+    def schedule(self, families) -> set:
+        """Load waiting families that fit (oldest queued request first); returns the ids of the
+        resident families that must not admit new work this round (so that they drain)."""
+        if self.budget is None:
+            return set()
+        gated = set()
+        waiting = sorted((f for f in families if f.queue and not f.resident), key=lambda f: f.queue[0].t_arrival)
+        for fam in waiting:
+            if self._fit(fam, families):
+                fam.load()
+                self.loads += 1
+                self.peak = max(self.peak, self.used(families))
+                continue
+            head = fam.queue[0].t_arrival
+            for g in families:
+                if g.resident and (not g.queue or g.queue[0].t_arrival > head):
+                    gated.add(id(g))
+            break
+        return gated
 
 
 class Server:
     """Serves requests over families with continuous batching on one device stream."""
 
-    def __init__(self, families: list[Family], n_checks: int = 1, warm: bool = True, light: int = 8):
+    def __init__(self, families: list[Family], n_checks: int = 1, warm: bool = True, light: int = 8,
+                 hbm_budget: int | None = None):
         """light: a family with at most this many queued requests and no busy slot is served by
-        a sequence launch of its single-instance handle (if attached)."""
+        a sequence launch of its single-instance handle (if attached). hbm_budget: device bytes
+        the families' handles may hold together (None: every family stays resident)."""
         self.families = families
         self.n_checks = n_checks
         self.warm = warm
         self.light = light
+        self.memory = MemoryPolicy(hbm_budget)
+        self.memory.check(families)
+        if hbm_budget is None:
+            for f in families:
+                f.load()
+        self.memory.peak = self.memory.used(families)
 
     def _light_step(self, fam: Family):
         """Solve the family's whole (short) queue in one single-instance sequence launch."""
@@ -145,15 +265,20 @@ class Server:
                 # idle until the next arrival
                 time.sleep(max(0.0, pending[0].t_arrival - now) if pending else 0.0)
                 continue
+            gated = self.memory.schedule(self.families)
             light = []
             for fam in self.families:
+                if not fam.resident or id(fam) in gated:
+                    continue
                 if fam.single is not None and not fam.busy and 0 < len(fam.queue) <= self.light:
                     light.append(self._light_step(fam))
+                    fam.last_used = now
                 else:
                     self._admit(fam)
             for fam in self.families:
                 if fam.busy:
                     fam.solver.step(self.n_checks)
+                    fam.last_used = now
             torch.cuda.synchronize()
             now = time.perf_counter() - t0
             for reqs, out in light:

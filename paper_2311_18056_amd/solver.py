@@ -7,7 +7,7 @@ provides the device memory of the result buffers and the stream.
 from __future__ import annotations
 
 import ctypes
-from ctypes import POINTER, byref, c_double, c_int, c_void_p
+from ctypes import POINTER, byref, c_double, c_int, c_size_t, c_void_p
 
 import numpy as np
 import torch
@@ -48,6 +48,26 @@ def default_settings(**overrides) -> Settings:
             raise AttributeError(k)
         setattr(s, k, v)
     return s
+
+
+def _result_bytes(n: int, m: int, batch: int, fp64: bool, max_checks: int) -> int:
+    """Device bytes of a Solver's result tensors (x, y, z, counters, per-check histories)."""
+    es = 8 if fp64 else 4
+    return batch * ((n + 2 * m) * es + 3 * 4 + max_checks * (4 + 8 + 8))
+
+
+def footprint(n: int, m: int, nx: int = 0, **settings) -> dict:
+    """Device bytes a ``Solver`` of this size holds once set up (plus F, E, lo, hi when nx > 0):
+    ``resident`` = the library's allocations + the result tensors; ``setup_extra`` = the FP64
+    workspace the setup holds on top of that while it factors. No device call."""
+    s = default_settings(**settings)
+    lib_bytes, extra = c_size_t(), c_size_t()
+    check(lib().relu_qp_footprint(int(n), int(m), byref(s), int(nx), byref(lib_bytes), byref(extra)))
+    ci = max(int(s.check_interval), 1)
+    max_checks = -(-int(s.max_iter) // ci)
+    res = _result_bytes(n, m, int(s.batch), s.precision == RQP_FP64, max_checks)
+    return {"resident": lib_bytes.value + res, "library": lib_bytes.value, "results": res,
+            "setup_extra": extra.value}
 
 
 class Solver:
@@ -246,6 +266,12 @@ class Solver:
         us = (c_double * 2)()
         check(lib().relu_qp_get_tile(self._h, byref(t), us))
         return t.value, {128: us[0], 64: us[1]}
+
+    def device_bytes(self) -> int:
+        """Device bytes this solver holds: the library's resident allocations + result tensors."""
+        b = c_size_t()
+        check(lib().relu_qp_device_bytes(self._h, byref(b)))
+        return b.value + _result_bytes(self.n, self.m, self.batch, self.fp64, self.max_checks)
 
     def set_tile(self, tile_rows: int):
         check(lib().relu_qp_set_tile(self._h, int(tile_rows)))

@@ -181,5 +181,59 @@ def test_server_two_families(rq, light):
     summ = latency_summary(reqs)
     assert summ["completed"] == len(reqs)
     for f in fams:
-        f.solver.close()
-        f.single.close()
+        f.unload()
+
+
+@pytest.mark.parametrize("kw", [dict(precision="fp64", engine="single"), dict(precision="fp32", engine="single"),
+                                dict(precision="fp32", engine="batch", batch=5),
+                                dict(precision="bf16x3", engine="batch", batch=130)])
+def test_footprint_matches_the_bytes_a_handle_holds(rq, kw):
+    """The host-side footprint (used to admit families by memory) equals what setup allocates."""
+    rng = np.random.default_rng(5)
+    n, m, nx = 30, 50, 4
+    G = rng.standard_normal((n, n))
+    P = G @ G.T + np.eye(n)
+    A = rng.standard_normal((m, n))
+    B = kw.get("batch", 1)
+    q = rng.standard_normal((B, n)) if B > 1 else rng.standard_normal(n)
+    lo, hi = -np.ones(m), np.ones(m)
+    l, u = (np.repeat(lo[None], B, 0), np.repeat(hi[None], B, 0)) if B > 1 else (lo, hi)
+    settings = dict(kw, n_rho=8)
+    sol = rq.Solver(P, q, A, l, u, **settings)
+    assert sol.device_bytes() == rq.footprint(n, m, 0, **settings)["resident"]
+    sol.set_parametric(rng.standard_normal((n, nx)), rng.standard_normal((m, nx)), lo, hi)
+    assert sol.device_bytes() == rq.footprint(n, m, nx, **settings)["resident"]
+    sol.set_parametric(rng.standard_normal((n, nx)), rng.standard_normal((m, nx)), lo, hi)  # replaces, no growth
+    assert sol.device_bytes() == rq.footprint(n, m, nx, **settings)["resident"]
+    sol.close()
+
+
+def test_server_admits_families_by_memory(rq):
+    """A budget that holds one family at a time: families are loaded and unloaded as their
+    requests come, the budget is never exceeded, and every result still matches the oracle."""
+    from paper_2311_18056_amd.serving import Family, Server, latency_summary, poisson_requests
+
+    probs = [make_config("c0"), make_config("c0", seed=7), make_config("c0", seed=9)]
+    fams = [Family.from_mpc(p, slots=8, precision="fp32", keep_x=True, lazy=True, n_rho=8).attach_single(p, n_rho=8)
+            for p in probs]
+    budget = max(f.bytes for f in fams) + 1
+    assert sum(f.bytes for f in fams) > budget
+    gens = [lambda rng, p=p: 5.0 * rng.uniform(-1, 1, p.nx) for p in probs]
+    reqs = poisson_requests(3000.0, 90, 10.0, gens, seed=6)
+    srv = Server(fams, n_checks=1, warm=True, light=8, hbm_budget=budget)
+    assert not any(f.resident for f in fams)
+    srv.run(reqs, time_limit=60.0)
+    assert srv.memory.evictions >= 1 and srv.memory.loads >= 3
+    assert srv.memory.peak <= budget
+    held = sum(f.solver.device_bytes() + f.single.device_bytes() for f in fams if f.resident)
+    assert held <= budget
+    for r in reqs:
+        assert r.status == rq.RQP_SOLVED, r.rid
+        p = probs[r.family]
+        q, l, u = qp_vectors(p.F, p.E, p.lo, p.hi, r.x0)
+        xs = oracle.solve(p.P, q, p.A, l, u, _os(n_rho=8, eps_abs=1e-9, eps_rel=1e-9, max_iter=40000)).x
+        assert _rel(r.x, xs) < 5e-2, r.rid
+    assert latency_summary(reqs)["completed"] == len(reqs)
+    for f in fams:
+        if f.resident:
+            f.unload()
