@@ -49,10 +49,14 @@ def parse():
     ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
     ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
     ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
-    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve"], default="c1",
+    ap.add_argument("--dense-problems", type=int, default=10, help="dense: problems per size")
+    ap.add_argument("--dense-reps", type=int, default=3, help="dense: timed solves per problem")
+    ap.add_argument("--dense-precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "dense"], default="c1",
                     help="c1: one instance per solve (the headline, n = m = 1600); c2: one instance per solve "
                          "of the n = 600, m = 1800 family; batch: 4096 instances of the c1 family per solve on "
-                         "the matrix cores; serve: continuous batching of MPC requests")
+                         "the matrix cores; serve: continuous batching of MPC requests; dense: random dense QPs "
+                         "with equality rows to eps 1e-6")
     ap.add_argument("--precision", choices=["bf16x3", "fp32"], default="bf16x3", help="batched engine precision")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000", help="serve: request rates per second")
@@ -130,6 +134,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "dense":
+        return bench_dense(args)
 
     import torch
 
@@ -401,6 +407,109 @@ def bench_batch(args):
     }
     sol.close()
     print(json.dumps(out), flush=True)
+
+
+def dense_sizes(count: int = 10):
+    """n log-spaced from 10 to 2000 (Sec. V-A), rounded to multiples of 4 above 10."""
+    return [10] + [int(round(v / 4.0)) * 4 for v in np.logspace(1, np.log10(2000), count)[1:]]
+
+
+def bench_dense(args):
+    """Random dense QPs with n/4 equality and n/4 inequality rows (Sec. V-A): for each size,
+    ``--dense-problems`` problems, each solved ``--dense-reps`` times from a cold start to
+    residuals below eps_abs = eps_rel = 1e-6 (equality rows at 1e3 times the penalty, 8 penalties).
+    Solve time = the persistent launch (HIP events), problem data resident; setup reported apart."""
+    import torch
+
+    import paper_2311_18056_amd as rq
+    from workloads import random_qp
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    settings = dict(precision=args.dense_precision, n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-6, eps_rel=1e-6,
+                    max_iter=20000, check_interval=25)
+    rows = []
+    es = 8 if args.dense_precision == "fp64" else 4
+    for n in dense_sizes():
+        me = mi = n // 4
+        ms_all, its, sts, setup = [], [], [], []
+        for k in range(args.dense_problems):
+            P, q, A, l, u = random_qp(n, me, mi, seed=10_000 * n + k)
+            t0 = time.perf_counter()
+            sol = rq.Solver(P, q, A, l, u, **settings)
+            setup.append((time.perf_counter() - t0) * 1e3)
+            sol.solve(stream)  # warm-up (kernel load, weights to L2)
+            for _ in range(args.dense_reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sol.solve(stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms_all.append(e0.elapsed_time(e1))
+            r = sol.result()
+            its.append(int(r["iterations"]))
+            sts.append(int(r["status"]))
+            sol.close()
+        m = me + mi
+        it = np.array(its)
+        ms = float(np.mean(ms_all))
+        bytes_iter = (n * n + 2 * m * n) * es
+        rows.append({"n": n, "m_eq": me, "m_ineq": mi, "solve_ms_mean": ms, "solve_ms_median": float(np.median(ms_all)),
+                     "iterations_mean": float(it.mean()), "iterations_max": int(it.max()),
+                     "solved": int(sum(1 for x in sts if x == rq.RQP_SOLVED)), "problems": len(sts),
+                     "setup_ms_mean": float(np.mean(setup)),
+                     "effective_GBs": float((it.mean() + np.ceil(it.mean() / 25)) * bytes_iter / (ms * 1e-3) / 1e9)})
+        print(json.dumps(rows[-1]), flush=True)
+    big = rows[-1]
+    paper_s = 1.62e-2  # the paper's solve time at n = 2000 (Fig. 2; RTX 3080, precision not stated)
+    out = {
+        "metric": "random dense QP solve time to eps 1e-6 (Sec. V-A sizes)",
+        "value": 1e3 / big["solve_ms_mean"],
+        "unit": "solves/s at n=2000",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": (1e3 / big["solve_ms_mean"]) / (1.0 / paper_s),
+        "baseline": {"value": 1.0 / paper_s, "source": "paper Fig. 2, n = 2000, RTX 3080 (context, other hardware)"},
+        "dtype": "f64" if args.dense_precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "random dense QPs, n log-spaced 10..2000, n/4 equality + n/4 inequality rows, "
+                               "eps_abs = eps_rel = 1e-6, 8 penalties, cold starts",
+                   "problems_per_size": args.dense_problems, "reps": args.dense_reps},
+        "sizes": rows,
+        "roofline": {"bound": "hbm", "achieved": big["effective_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": big["effective_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"layer_kernel ({args.dense_precision}), n = 2000",
+                     "alg_bytes_per_unit": (2000 * 2000 + 2 * 1000 * 2000) * es},
+        "cpu_baseline": None if args.no_cpu_baseline else dense_cpu_baseline(settings, args.cpu_seconds),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def dense_cpu_baseline(settings, budget_s):
+    """The FP64 oracle on the same problems (largest size first), offline stage excluded."""
+    import oracle
+    from oracle import admm
+    from workloads import random_qp
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    s = admm.Settings(n_rho=8, eps_abs=settings["eps_abs"], eps_rel=settings["eps_rel"], max_iter=settings["max_iter"])
+    n = dense_sizes()[-1]
+    done, dt = 0, 0.0
+    while dt < budget_s and done < 10:
+        P, q, A, l, u = random_qp(n, n // 4, n // 4, seed=10_000 * n + done)
+        cache = {}
+        oracle.solve(P, q, A, l, u, s, cache=cache)  # offline stage, not timed
+        t0 = time.perf_counter()
+        oracle.solve(P, q, A, l, u, s, cache=cache)
+        dt += time.perf_counter() - t0
+        done += 1
+    return {"value": done / dt, "unit": "solves/s at n=2000", "cores": int(cores), "kind": "oracle",
+            "sample": f"{done} of the n = 2000 problems, each solved once to 1e-6 after an untimed setup"}
 
 
 def bench_serve(args):
