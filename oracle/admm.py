@@ -280,7 +280,7 @@ def _validate(P, q, A, l, u, s):
 
 
 def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=None, record=False,
-          cache: dict | None = None) -> Result:
+          cache: dict | None = None, final_check: bool = True) -> Result:
     """ReLU-QP solve (Algorithm 1, online part), in FP64.
 
     ``warm``: None for a cold start (x = z = y = 0), or (x, y, rho_index): the previous primal,
@@ -290,6 +290,8 @@ def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=
     schedule).
     ``cache``: optional dict that keeps the factorisations of the offline stage between calls
     on the same P, A, settings and equality pattern (Algorithm 1 computes them once).
+    ``final_check=False``: a max_iter that is not a multiple of check_interval ends the solve
+    with MAX_ITER and no check (a fixed iteration budget per MPC step, Sec. V-B).
     """
     P = np.asarray(P, np.float64)
     q = np.asarray(q, np.float64)
@@ -338,6 +340,10 @@ def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=
             res.history.append((x.copy(), z.copy(), y.copy()))
         if k % s.check_interval != 0 and k != s.max_iter:
             continue
+        if k % s.check_interval != 0 and not final_check:
+            res.status = MAX_ITER
+            res.iterations = k
+            break
         nm = residual_norms(P, q, A, x, z, y)
         res.prim_res.append(nm["r_p"])
         res.dual_res.append(nm["r_d"])
