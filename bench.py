@@ -49,14 +49,19 @@ def parse():
     ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
     ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
     ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
+    ap.add_argument("--closed-nu", default="10,40,50", help="closed: control dimensions")
+    ap.add_argument("--budgets", default="1,2,15", help="closed: ADMM iterations per MPC step")
+    ap.add_argument("--closed-steps", type=int, default=1000, help="closed: MPC steps per launch")
+    ap.add_argument("--closed-reps", type=int, default=3)
+    ap.add_argument("--x0-scale-closed", type=float, default=20.0)
     ap.add_argument("--dense-problems", type=int, default=10, help="dense: problems per size")
     ap.add_argument("--dense-reps", type=int, default=3, help="dense: timed solves per problem")
     ap.add_argument("--dense-precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "dense"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "dense", "closed"], default="c1",
                     help="c1: one instance per solve (the headline, n = m = 1600); c2: one instance per solve "
                          "of the n = 600, m = 1800 family; batch: 4096 instances of the c1 family per solve on "
                          "the matrix cores; serve: continuous batching of MPC requests; dense: random dense QPs "
-                         "with equality rows to eps 1e-6")
+                         "with equality rows to eps 1e-6; closed: closed-loop MPC, fixed iterations per step")
     ap.add_argument("--precision", choices=["bf16x3", "fp32"], default="bf16x3", help="batched engine precision")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000", help="serve: request rates per second")
@@ -136,6 +141,8 @@ def main():
         return bench_serve(args)
     if args.workload == "dense":
         return bench_dense(args)
+    if args.workload == "closed":
+        return bench_closed(args)
 
     import torch
 
@@ -510,6 +517,78 @@ def dense_cpu_baseline(settings, budget_s):
         done += 1
     return {"value": done / dt, "unit": "solves/s at n=2000", "cores": int(cores), "kind": "oracle",
             "sample": f"{done} of the n = 2000 problems, each solved once to 1e-6 after an untimed setup"}
+
+
+# MPC step times the paper reports for one ADMM iteration per step (Fig. 1, RTX 3080; context)
+PAPER_MPC_STEP_S = {10: 1.204e-4, 50: 7.376e-4}
+
+
+def bench_closed(args):
+    """Closed-loop MPC of random linear systems (Sec. V-B): nu controls, nx = 3 nu states,
+    horizon 40, control limits, LQR-preconditioned condensing; x0 = scale * U[-1,1]^nx. Each
+    launch runs --closed-steps MPC steps (relu_qp_closed_loop: update, --budget warm-started
+    iterations, applied control, plant step, all on the device); time per MPC step = launch time
+    (HIP events) / steps."""
+    import torch
+
+    import paper_2311_18056_amd as rq
+    from workloads import random_mpc, x0_batch
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for nu in [int(v) for v in args.closed_nu.split(",")]:
+        prob = random_mpc(3 * nu, nu, 40, seed=60 + nu, radius=1.05, q_kind="identity", r_scale=0.1)
+        x0 = args.x0_scale_closed * x0_batch(prob.nx, 1, 70 + nu)[0]
+        q, l, u = prob.instance(x0)
+        for budget in [int(b) for b in args.budgets.split(",")]:
+            sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp32", engine="single", n_rho=8, eps_abs=0.0,
+                            eps_rel=0.0, max_iter=budget)
+            sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+            T = args.closed_steps
+            xd = torch.tensor(x0, dtype=torch.float64, device="cuda")
+            Ad = torch.tensor(prob.A_dyn, dtype=torch.float64, device="cuda")
+            Bd = torch.tensor(prob.B, dtype=torch.float64, device="cuda")
+            out = sol.closed_loop(xd, T, Ad, Bd, nu, stream)  # warm-up launch
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(args.closed_reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sol.closed_loop(xd, T, Ad, Bd, nu, stream, out=out)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            us_ = out["traj_u"].cpu().numpy()
+            xs_ = out["traj_x"].cpu().numpy()
+            step_s = float(np.mean(ms)) * 1e-3 / T
+            row = {"nu": nu, "nx": prob.nx, "n": prob.n, "m": prob.m, "budget": budget, "steps": T,
+                   "step_us": step_s * 1e6, "steps_per_s": 1.0 / step_s,
+                   "active_frac": float(np.mean(np.max(np.abs(us_), axis=1) > 0.999)),
+                   "x_norm_first_last": [float(np.max(np.abs(xs_[0]))), float(np.max(np.abs(xs_[-1])))]}
+            if budget == 1 and nu in PAPER_MPC_STEP_S:
+                row["paper_step_us"] = PAPER_MPC_STEP_S[nu] * 1e6
+                row["vs_paper"] = PAPER_MPC_STEP_S[nu] / step_s
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            sol.close()
+    head = next((r for r in rows if r["nu"] == 50 and r["budget"] == 1), rows[-1])
+    out = {
+        "metric": "closed-loop MPC step time, one warm-started ADMM iteration per step (Fig. 1 workload)",
+        "value": head["steps_per_s"],
+        "unit": f"MPC steps/s at nu={head['nu']}, budget {head['budget']}",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": head.get("vs_paper"),
+        "baseline": {"value_s": PAPER_MPC_STEP_S.get(head["nu"]), "source": "paper Fig. 1, RTX 3080 (context)"},
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "random linear MPC closed loop, nx = 3 nu, N = 40, control limits, LQR-condensed, "
+                               f"x0 = {args.x0_scale_closed:g} * U[-1,1]^nx, plant = model",
+                   "steps_per_launch": args.closed_steps},
+        "runs": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_serve(args):

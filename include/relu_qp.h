@@ -162,6 +162,23 @@ int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_
  * data; RQP_EINVAL if count < 1, on the batched engine, or count*(max_iter+2) >= 2^31. */
 int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out);
 
+/* Closed-loop MPC (the receding-horizon use of Sec. V-B) in ONE launch of the single-instance
+ * engine: `steps` MPC steps, step s from the plant state x_s (x_0 = x0, DEVICE FP64, nx):
+ * q, l, u from x_s as in relu_qp_solve_x0, then settings.max_iter iterations (the per-step
+ * budget; a budget that is not a multiple of check_interval ends without a check, status
+ * RQP_MAX_ITER; with eps > 0 a check may also end a step early), warm from the previous step
+ * (x, y and penalty index; z = A x) — the first step starts as relu_qp_solve would — then
+ * the applied control u_s = z[0:nu] + (E x_s)[0:nu] (the first nu constraint rows hold the
+ * first stage's control, as the condensed form lays them out) and the plant step
+ * x_{s+1} = Ad x_s + Bd u_s, all on the device.
+ * Ad: nx*nx, Bd: nx*nu row-major (DEVICE FP64); traj_x: (steps+1)*nx, traj_u: steps*nu
+ * (DEVICE FP64, caller-owned, written asynchronously on stream); out: results of each step at
+ * index s as in relu_qp_solve_sequence. Needs parametric data (RQP_ESTATE); RQP_EINVAL for
+ * NULL pointers, steps < 1, nu outside [1, min(m, 256)], nx > 256, or on the batched engine
+ * (RQP_ESTATE). */
+int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const double* Ad, const double* Bd, int nu,
+                        double* traj_x, double* traj_u, void* stream, relu_qp_result* out);
+
 /* ---- Serving (continuous batching; batched engine only).
  * The handle's `batch` instances are slots. A slot holds one request from its admission until
  * a final status; finished and idle slots cost nothing in a step. Warm starts follow the

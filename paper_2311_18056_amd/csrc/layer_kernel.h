@@ -25,6 +25,8 @@ struct LayerArgs {
   void* zs;
   void* ys;
   int* js;              // handle state penalty index
+  double* axs;          // handle state A x (m, FP64): the constraint-row owners' carried product
+  int warm_ax;          // a warm first solve takes z = A x from axs (the state came from a solve)
   int count;            // solves run one after another in this launch (>= 1)
   int chain;            // solves after the first start warm from the previous one
   int max_checks;       // per-solve stride of rho_hist, prim_res, dual_res
@@ -52,7 +54,25 @@ struct LayerArgs {
   const double* plo;    // m
   const double* phi;    // m
   int nx;
+  // optional closed loop (Ad != null, needs x0): solve s starts from the plant state x_s, with
+  // x_0 = x0 and x_{s+1} = Ad x_s + Bd u_s, where u_s = z_s[0:nu] + (E x_s)[0:nu] is the first
+  // stage's applied control. The owners of constraint rows 0..nu-1 publish u_s in xu
+  // (2 parities x nu x 2 words) and every workgroup steps the plant itself, in FP64, in one
+  // fixed order (so every copy of x_{s+1} is the same). Trajectories go to traj_x
+  // ((count + 1) x nx) and traj_u (count x nu), FP64.
+  const double* Ad;     // nx x nx
+  const double* Bd;     // nx x nu
+  int nu;
+  uint64_t* xu;
+  double* xpl;          // each workgroup's copy of the plant state: 2 parities x grid x kMaxPlant
+  double* traj_x;
+  double* traj_u;
+  int final_check;      // 0: a max_iter that is not a multiple of check_interval ends unchecked
 };
+
+// nx and nu of a closed loop are at most kMaxPlant; grids are at most kMaxGrid workgroups.
+constexpr int kMaxPlant = 256;
+constexpr int kMaxGrid = 256;
 
 // Rows per workgroup are at most kMaxRows; the host picks the grid accordingly.
 constexpr int kLayerBlock = 1024;

@@ -128,6 +128,74 @@ __device__ __forceinline__ bool gather_norms(const uint64_t* buf, int count, uin
   return ok;
 }
 
+// Poll one FP64 value (two words) until both tags equal `tag`.
+__device__ __forceinline__ bool wait_f64(const uint64_t* p, uint32_t tag, double& v, const unsigned* err,
+                                         uint32_t etag) {
+  uint64_t w0 = ll_load_word(p), w1 = ll_load_word(p + 1);
+  unsigned spins = 0;
+  bool ok = true;
+  while (ll_tag(w0) != tag || ll_tag(w1) != tag) {
+    w0 = ll_load_word(p);
+    w1 = ll_load_word(p + 1);
+    if ((++spins & 255u) == 0u && (spins > kSpinLimit || err_set(err, etag))) {
+      ok = false;
+      break;
+    }
+  }
+  v = bits_to_double(ll_bits64(w0, w1));
+  return ok;
+}
+
+// Closed loop: the plant state after solve sv - 1, x_sv = Ad x_{sv-1} + Bd u_{sv-1}. Each
+// workgroup keeps its own copy of the state in xpl (parity sv & 1); u comes from the words the
+// first nu constraint-row owners published at the end of solve sv - 1 (tag utag), staged in
+// ucur. Each wave forms kPlantRows state entries per pass (their loads in flight together):
+// per entry, lane-strided FP64 products then a butterfly sum, the same order in every
+// workgroup, so every copy is the same. Returns false if the wait for u timed out.
+constexpr int kPlantRows = 4;
+template <int NWV>
+__device__ __forceinline__ bool plant_step(const LayerArgs& a, int sv, uint32_t utag, double* ucur, int* flag) {
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const uint64_t* uw = a.xu + (long)((sv - 1) & 1) * a.nu * 2;
+  if (tid < a.nu) {
+    double v;
+    if (!wait_f64(uw + 2L * tid, utag, v, a.err, utag)) *flag = 1;
+    ucur[tid] = v;
+  }
+  __syncthreads();
+  if (*flag) return false;
+  const double* xc = a.xpl + ((long)((sv - 1) & 1) * gridDim.x + blockIdx.x) * kMaxPlant;
+  double* xn = a.xpl + ((long)(sv & 1) * gridDim.x + blockIdx.x) * kMaxPlant;
+  const int nx = a.nx, nu = a.nu;
+  for (int rb = wave * kPlantRows; rb < nx; rb += NWV * kPlantRows) {
+    double dv[kPlantRows];
+    int rc[kPlantRows];  // a valid row index for every slot (entries past nx are not stored)
+#pragma unroll
+    for (int b = 0; b < kPlantRows; ++b) {
+      dv[b] = 0.0;
+      rc[b] = rb + b < nx ? rb + b : nx - 1;
+    }
+    for (int c = lane; c < nx; c += kWave) {
+      const double xv = xc[c];
+#pragma unroll
+      for (int b = 0; b < kPlantRows; ++b) dv[b] = fma(a.Ad[(long)rc[b] * nx + c], xv, dv[b]);
+    }
+    for (int c = lane; c < nu; c += kWave) {
+      const double uv = ucur[c];
+#pragma unroll
+      for (int b = 0; b < kPlantRows; ++b) dv[b] = fma(a.Bd[(long)rc[b] * nu + c], uv, dv[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < kPlantRows; ++b) {
+#pragma unroll
+      for (int off = kWave / 2; off > 0; off >>= 1) dv[b] += __shfl_xor(dv[b], off, kWave);
+      if (lane == 0 && rb + b < nx) xn[rb + b] = dv[b];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 template <typename T, int NC>
 struct Cols {
   T v[NC];
@@ -339,7 +407,8 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
 }
 
 template <typename T>
-__device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int sv, int k, int st, int j) {
+__device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int sv, int k, int st, int j,
+                                       uint32_t tag, const double* exs) {
   if (rs.own) {
     if (rs.xrow) {
       static_cast<T*>(a.xs)[rs.R] = rs.sx;
@@ -348,8 +417,15 @@ __device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int s
       const int i = rs.R - a.n;
       static_cast<T*>(a.zs)[i] = rs.sz;
       static_cast<T*>(a.ys)[i] = rs.sy;
+      a.axs[i] = rs.ax;
       static_cast<T*>(a.zo)[(long)sv * a.m + i] = rs.sz;
       static_cast<T*>(a.yo)[(long)sv * a.m + i] = rs.sy;
+      if (a.Ad && i < a.nu) {
+        // the first stage's applied control (the clamped constraint row plus its E x_s part)
+        const double uv = (double)rs.sz + exs[threadIdx.x];
+        a.traj_u[(long)sv * a.nu + i] = uv;
+        ll_store(a.xu + ((long)(sv & 1) * a.nu + i) * 2, uv, tag);
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -453,6 +529,10 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   // this workgroup's share of the x rows for the dual side of the check, and their q
   const int cb = (int)((long)g * n / G), nck = (int)((long)(g + 1) * n / G) - cb;
   __shared__ T cq[kMaxRows];
+  // closed loop: (E x_s)_i of the owned constraint rows; the applied control
+  __shared__ double exs[kMaxRows];
+  __shared__ double ucur[kMaxPlant];
+  const bool closed = a.Ad != nullptr;
 
   for (int sv = 0; sv < a.count; ++sv) {
     const uint32_t tag = a.tag + (uint32_t)sv * span;
@@ -462,8 +542,21 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
     // u = hi - E x0 for constraint rows, FP64 products, one wave per row of the block; the
     // values reach the owners through LDS and are written back for later solves
     __syncthreads();  // upd[] and cq[] of the previous solve have been read
+    double* xpl = closed ? a.xpl + ((long)(sv & 1) * G + g) * kMaxPlant : nullptr;
+    if (closed) {
+      if (sv == 0) {
+        for (int c = tid; c < a.nx; c += BS) xpl[c] = a.x0[c];
+        __syncthreads();
+      } else if (!plant_step<NWAVE>(a, sv, tag - span, ucur, &fail_flag)) {
+        if (tid == 0) err_raise(a.err, tag);
+        finish<T>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
+        return;
+      }
+      if (g == 0)
+        for (int c = tid; c < a.nx; c += BS) a.traj_x[(long)sv * a.nx + c] = xpl[c];
+    }
     if (a.x0) {
-      const double* x0 = a.x0 + (long)sv * a.nx;
+      const double* x0 = closed ? xpl : a.x0 + (long)sv * a.nx;
       // rows 0 .. nrows-1: owned layer rows; rows nrows .. nrows+nck-1: the check's x rows
       for (int rr = wave; rr < nrows + nck; rr += NWAVE) {
         const int R = rr < nrows ? r0 + rr : cb + (rr - nrows);
@@ -480,6 +573,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
             static_cast<T*>(const_cast<void*>(a.q))[R] = (T)dv;
           } else {
             const int i = R - n;
+            exs[rr] = dv;
             upd[rr][0] = (T)(a.plo[i] - dv);
             upd[rr][1] = (T)(a.phi[i] - dv);
             static_cast<T*>(const_cast<void*>(a.l))[i] = upd[rr][0];
@@ -493,7 +587,10 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
     __syncthreads();
 
     // row-owner state: cold (zero, start penalty), warm from the handle (first solve) or from
-    // the previous solve of this launch
+    // the previous solve of this launch. A warm start that continues a solve takes z = A x
+    // from the product the constraint-row owners carried along it (in registers within the
+    // launch, from the handle's copy across launches); only a caller-given x needs the product.
+    const bool carried = warm && (sv > 0 || a.warm_ax != 0);
     if (rs.own) {
       if (rs.xrow) {
         rs.sq = a.x0 ? upd[tid][0] : static_cast<const T*>(a.q)[rs.R];
@@ -503,10 +600,11 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         const int i = rs.R - n;
         sl = a.x0 ? upd[tid][0] : static_cast<const T*>(a.l)[i];
         su = a.x0 ? upd[tid][1] : static_cast<const T*>(a.u)[i];
-        rs.sz = (T)0;
-        rs.ax = 0.0;
         if (!warm) rs.sy = (T)0;
         else if (sv == 0) rs.sy = static_cast<const T*>(a.ys)[i];
+        if (!carried) rs.ax = 0.0;
+        else if (sv == 0) rs.ax = a.axs[i];
+        rs.sz = carried ? (T)rs.ax : (T)0;
       }
     }
     if (!warm) j = a.j0;
@@ -518,14 +616,14 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
     __syncthreads();  // fail_flag, LDS rows
     int nchk = 0;
 
-    // warm start: z = A x (Sec. II-B, warm starting)
-    if (warm) {
+    // warm start from a caller-given x: z = A x (Sec. II-B, warm starting)
+    if (warm && !carried) {
       if (rs.own) ll_store(a.xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, tag);
       Cols<T, NC> cv;
       const bool ok = gather<T, NC>(a.xc, L, tag, cv.v, a.err, tag);
       if (__syncthreads_or(!ok)) {
         if (tid == 0) err_raise(a.err, tag);
-        finish<T>(a, rs, sv, 0, ST_INTERNAL, j);
+        finish<T>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
         return;
       }
       double ax, unused;
@@ -589,7 +687,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
           __syncthreads();
           if (fail_flag) {
             if (tid == 0) err_raise(a.err, tag);
-            finish<T>(a, rs, sv, k, ST_INTERNAL, j);
+            finish<T>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
             return;
           }
 
@@ -618,17 +716,23 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         }
       }
 
+      // a fixed budget that is not a multiple of the check interval ends without a check
+      if (!a.final_check && k == max_iter && k % ci != 0) {
+        finish<T>(a, rs, sv, k, ST_MAX_ITER, j, tag, exs);
+        break;  // next solve of the sequence
+      }
+
       // check at iteration k (every check_interval iterations and at max_iter)
       __syncthreads();
       const CheckOut co = run_check<T, NC>(a, rt, rs, cb, nck, cq, k, nchk, j, tag, (long)sv * a.max_checks);
       ++nchk;
       if (!co.ok) {
         if (tid == 0) err_raise(a.err, tag);
-        finish<T>(a, rs, sv, k, ST_INTERNAL, j);
+        finish<T>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
         return;
       }
       if (co.status != ST_RUNNING) {
-        finish<T>(a, rs, sv, k, co.status, j);
+        finish<T>(a, rs, sv, k, co.status, j, tag, exs);
         break;  // next solve of the sequence
       }
       if (co.jn != j) {
@@ -641,6 +745,18 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
       if (rs.own) ll_store(a.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
     }
+  }
+
+  // closed loop: the state after the last control, written by workgroup 0
+  if (closed && g == 0) {
+    const uint32_t last = a.tag + (uint32_t)(a.count - 1) * span;
+    __syncthreads();
+    if (!plant_step<NWAVE>(a, a.count, last, ucur, &fail_flag)) {
+      if (tid == 0) err_raise(a.err, last);
+      return;
+    }
+    const double* xf = a.xpl + ((long)(a.count & 1) * G + g) * kMaxPlant;
+    for (int c = tid; c < a.nx; c += BS) a.traj_x[(long)a.count * a.nx + c] = xf[c];
   }
 }
 

@@ -76,6 +76,9 @@ struct relu_qp_handle {
   uint64_t* xw = nullptr;
   uint64_t* xc = nullptr;
   uint64_t* xn = nullptr;
+  uint64_t* xu = nullptr;  // closed loop: applied-control words, 2 parities x kMaxPlant x 2
+  double* xpl = nullptr;   // closed loop: per-workgroup plant state, 2 x kMaxGrid x kMaxPlant
+  double* axs = nullptr;   // A x of the last solve's x (m, FP64), for warm starts that continue it
   size_t xw_words = 0, xn_words = 0;
   unsigned* err = nullptr;
   int* abort_h = nullptr;  // host-mapped
@@ -123,7 +126,7 @@ namespace {
 void free_handle(relu_qp_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->W,    h->C,    h->q,    h->l,    h->u,     h->eq_d,   h->grid_d,  h->mid_d,
-                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,
+                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs,
                   h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
                   h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
                   h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
@@ -293,6 +296,9 @@ int alloc_exchange(relu_qp_handle* h) {
   HIP_OR_FAIL(dmalloc(h, &h->xw, h->xw_words * 8));
   HIP_OR_FAIL(dmalloc(h, &h->xc, h->xw_words * 8));
   HIP_OR_FAIL(dmalloc(h, &h->xn, h->xn_words * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->xu, (size_t)2 * rqp::kMaxPlant * 2 * 8));
+  HIP_OR_FAIL(hipMemset(h->xu, 0, (size_t)2 * rqp::kMaxPlant * 2 * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->xpl, (size_t)2 * rqp::kMaxGrid * rqp::kMaxPlant * 8));
   HIP_OR_FAIL(hipMemset(h->xw, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xc, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xn, 0, h->xn_words * 8));
@@ -663,13 +669,15 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
       dmalloc(h, &h->q, (size_t)n * h->esize) != hipSuccess || dmalloc(h, &h->l, (size_t)m * h->esize) != hipSuccess ||
       dmalloc(h, &h->u, (size_t)m * h->esize) != hipSuccess || dmalloc(h, &h->xs, (size_t)n * h->esize) != hipSuccess ||
       dmalloc(h, &h->zs, (size_t)m * h->esize) != hipSuccess || dmalloc(h, &h->ys, (size_t)m * h->esize) != hipSuccess ||
-      dmalloc(h, &h->js, sizeof(int)) != hipSuccess || dmalloc(h, &h->err, sizeof(unsigned)) != hipSuccess) {
+      dmalloc(h, &h->js, sizeof(int)) != hipSuccess || dmalloc(h, &h->err, sizeof(unsigned)) != hipSuccess ||
+      dmalloc(h, &h->axs, (size_t)m * 8) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(RQP_ENOMEM, "device allocation failed (n=%d, m=%d, %zu penalties)", n, m, nr));
   }
   if ((rc = upload(h, h->q, q, n)) || (rc = upload(h, h->l, l, m)) || (rc = upload(h, h->u, u, m))) return bail(rc);
   if (hipMemset(h->xs, 0, (size_t)n * h->esize) != hipSuccess || hipMemset(h->zs, 0, (size_t)m * h->esize) != hipSuccess ||
       hipMemset(h->ys, 0, (size_t)m * h->esize) != hipSuccess || hipMemset(h->js, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(h->axs, 0, (size_t)m * 8) != hipSuccess ||
       hipMemset(h->err, 0, sizeof(unsigned)) != hipSuccess)
     return bail(fail(RQP_EHIP, "initial copies failed"));
 
@@ -828,7 +836,17 @@ int relu_qp_set_warm(relu_qp_handle* h, int enabled) {
 namespace {
 // One persistent launch of `count` solves of the online loop; with x0 (count x nx), each solve
 // first forms its q, l, u from its own initial state.
-int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, relu_qp_result* out) {
+// A closed loop's plant and trajectory buffers (device, FP64).
+struct ClosedLoop {
+  const double* Ad;
+  const double* Bd;
+  int nu;
+  double* traj_x;
+  double* traj_u;
+};
+
+int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, relu_qp_result* out,
+               const ClosedLoop* cl = nullptr) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
     return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
@@ -850,6 +868,7 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
     HIP_OR_FAIL(hipMemsetAsync(h->xw, 0, h->xw_words * 8, st));
     HIP_OR_FAIL(hipMemsetAsync(h->xc, 0, h->xw_words * 8, st));
     HIP_OR_FAIL(hipMemsetAsync(h->xn, 0, h->xn_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xu, 0, (size_t)2 * rqp::kMaxPlant * 2 * 8, st));
     HIP_OR_FAIL(hipMemsetAsync(h->err, 0, sizeof(unsigned), st));
     h->tag = 1;
   }
@@ -883,6 +902,8 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
   a.zs = h->zs;
   a.ys = h->ys;
   a.js = h->js;
+  a.axs = h->axs;
+  a.warm_ax = (!h->warm_pending && h->warm_mode && h->have_prev) ? 1 : 0;
   a.xo = out->x;
   a.zo = out->z;
   a.yo = out->y;
@@ -907,6 +928,18 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
   a.plo = h->lo_d;
   a.phi = h->hi_d;
   a.nx = h->nx;
+  a.final_check = 1;
+  a.xu = h->xu;
+  a.xpl = h->xpl;
+  if (cl) {
+    a.Ad = cl->Ad;
+    a.Bd = cl->Bd;
+    a.nu = cl->nu;
+    a.traj_x = cl->traj_x;
+    a.traj_u = cl->traj_u;
+    a.chain = 1;
+    a.final_check = 0;
+  }
   hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->plan, h->grid_wg, st)
                                : rqp::launch_layer<float>(a, h->plan, h->grid_wg, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
@@ -932,6 +965,19 @@ int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_
 int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out) {
   if (!x0s) return fail(RQP_EINVAL, "x0s is NULL");
   return solve_impl(h, x0s, count, stream, out);
+}
+
+int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const double* Ad, const double* Bd, int nu,
+                        double* traj_x, double* traj_u, void* stream, relu_qp_result* out) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (h->batched) return fail(RQP_ESTATE, "closed loops run on the single-instance engine");
+  if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
+  if (!x0 || !Ad || !Bd || !traj_x || !traj_u) return fail(RQP_EINVAL, "x0, Ad, Bd, traj_x and traj_u are required");
+  if (nu < 1 || nu > h->m || nu > rqp::kMaxPlant)
+    return fail(RQP_EINVAL, "nu = %d outside [1, min(m, %d)]", nu, rqp::kMaxPlant);
+  if (h->nx > rqp::kMaxPlant) return fail(RQP_EINVAL, "nx = %d above %d", h->nx, rqp::kMaxPlant);
+  const ClosedLoop cl{Ad, Bd, nu, traj_x, traj_u};
+  return solve_impl(h, x0, steps, stream, out, &cl);
 }
 
 int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const double* q, const double* l,
@@ -1088,9 +1134,11 @@ int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* b
     const size_t ldw = (L + 3) / 4 * 4, w_stride = L * ldw;
     t += nr * w_stride * es + w_stride * es;  // layer and check matrices
     t += 2 * ((size_t)n + 2 * m) * es;        // q, l, u and x, z, y
-    t += 4 + 4;                               // penalty index, error word
+    t += 4 + 4 + (size_t)m * 8;               // penalty index, error word, carried A x
     const size_t words = es == 8 ? 2 : 1;
     t += 2 * (2 * L * words * 8) + 2 * L * 8 * 2 * 8;  // exchange buffers
+    t += (size_t)2 * rqp::kMaxPlant * 2 * 8;           // closed-loop control words
+    t += (size_t)2 * rqp::kMaxGrid * rqp::kMaxPlant * 8;  // closed-loop plant states
   }
   if (nx > 0) t += ((size_t)n + m) * nx * 8 + 2 * (size_t)m * 8;
   *bytes = t;

@@ -183,6 +183,28 @@ class Solver:
                                            byref(out["_result"])))
         return out
 
+    def closed_loop(self, x0: torch.Tensor, steps: int, Ad: torch.Tensor, Bd: torch.Tensor, nu: int, stream=None,
+                    out=None):
+        """``steps`` MPC steps in one launch: each runs ``max_iter`` warm-started iterations from
+        the plant state, applies the first stage's control and steps the plant x <- Ad x + Bd u
+        on the device. x0 (nx), Ad (nx, nx), Bd (nx, nu): float64 cuda. Returns the dict of
+        ``sequence_slots(steps)`` with ``traj_x`` (steps + 1, nx) and ``traj_u`` (steps, nu)."""
+        for t in (x0, Ad, Bd):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("x0, Ad and Bd must be contiguous float64 cuda tensors")
+        nx = x0.numel()
+        if Ad.shape != (nx, nx) or Bd.shape != (nx, nu):
+            raise ValueError("Ad must be (nx, nx) and Bd (nx, nu)")
+        if out is None:
+            out = self.sequence_slots(steps)
+            out["traj_x"] = torch.zeros(steps + 1, nx, dtype=torch.float64, device=self.device)
+            out["traj_u"] = torch.zeros(steps, nu, dtype=torch.float64, device=self.device)
+        check(lib().relu_qp_closed_loop(self._h, c_void_p(x0.data_ptr()), int(steps), c_void_p(Ad.data_ptr()),
+                                        c_void_p(Bd.data_ptr()), int(nu), c_void_p(out["traj_x"].data_ptr()),
+                                        c_void_p(out["traj_u"].data_ptr()), _stream_handle(stream),
+                                        byref(out["_result"])))
+        return out
+
     def sequence_slots(self, count: int) -> dict:
         """Device result tensors for ``count`` solves of one sequence launch."""
         dev = self.device

@@ -68,6 +68,7 @@ def test_serving_calls_reject_a_null_handle():
     assert lib.relu_qp_load_slots_x0(None, None, 0, None, None) == E
     assert lib.relu_qp_admit(None, None, 0, -1, 0, 0, None) == E
     assert lib.relu_qp_step(None, 1, None, None) == E
+    assert lib.relu_qp_closed_loop(None, None, 1, None, None, 1, None, None, None, None) == E
 
 
 def test_settings_rules_for_engines():

@@ -1,0 +1,111 @@
+"""GPU closed-loop MPC (``relu_qp_closed_loop``: every MPC step, its warm-started iterations,
+the applied control and the plant step in one launch) against the FP64 closed-loop oracle.
+
+Tolerances per trajectory (||a - b||_inf <= tol * max(||b||_inf, 1)): 1e-9 in FP64, 1e-4 in
+FP32, for the plant states, the applied controls and every step's x, z, y.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import admm
+from oracle.closed_loop import closed_loop
+from workloads import make_config, x0_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2311_18056_amd as rq
+
+    rq.lib()
+    return rq
+
+
+def _dev(a):
+    import torch
+
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _close(a, b, tol, what):
+    err = np.max(np.abs(a - b))
+    scale = max(np.max(np.abs(b)), 1.0)
+    assert err <= tol * scale, f"{what}: |diff|={err:.3e} > {tol:.1e} * {scale:.3e}"
+
+
+def _run(rq, prob, x0, steps, prec, **settings):
+    q, l, u = prob.instance(x0)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision=prec, engine="single", **settings)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    out = sol.closed_loop(_dev(x0), steps, _dev(prob.A_dyn), _dev(prob.B), prob.nu)
+    res = {k: v.cpu().numpy() for k, v in out.items() if k != "_result"}
+    sol.close()
+    return res
+
+
+def _oracle(prob, x0, steps, **settings):
+    s = admm.Settings()
+    for k, v in settings.items():
+        setattr(s, k, v)
+    return closed_loop(prob.P, prob.A, prob.F, prob.E, prob.lo, prob.hi, prob.A_dyn, prob.B, prob.nu, x0, steps, s)
+
+
+@pytest.mark.parametrize("budget,eps", [(1, 0.0), (2, 0.0), (15, 0.0), (30, 1e-3)])
+def test_closed_loop_fp64_matches_oracle(rq, budget, eps):
+    prob = make_config("c0")
+    x0 = 8.0 * x0_batch(prob.nx, 1, 41)[0]
+    steps = 40
+    kw = dict(n_rho=8, eps_abs=eps, eps_rel=eps, max_iter=budget)
+    g = _run(rq, prob, x0, steps, "fp64", **kw)
+    xs, us, res = _oracle(prob, x0, steps, **kw)
+    assert np.array_equal(g["traj_x"][0], x0)
+    _close(g["traj_x"], xs, 1e-9, "plant states")
+    _close(g["traj_u"], us, 1e-9, "controls")
+    for s in range(steps):
+        assert g["iterations"][s] == res[s].iterations and g["status"][s] == res[s].status, s
+        assert g["rho_index"][s] == res[s].rho_index, s
+        for name in ("x", "z", "y"):
+            _close(g[name][s], getattr(res[s], name), 1e-9, f"step {s} {name}")
+    assert np.max(np.abs(g["traj_u"])) <= 1.0 + 1e-12  # (hi - Ex) + Ex rounds to within an ulp
+    if budget < 25:
+        assert np.all(g["status"] == rq.RQP_MAX_ITER) and np.all(g["iterations"] == budget)
+
+
+def test_closed_loop_fp32_full_size(rq):
+    """The n = m = 1600 family, states large enough that the limits bind, two iterations per
+    step (the budget of the paper's humanoid experiment)."""
+    prob = make_config("c1")
+    x0 = 20.0 * x0_batch(prob.nx, 1, 42)[0]
+    steps = 20
+    kw = dict(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=2)
+    g = _run(rq, prob, x0, steps, "fp32", **kw)
+    xs, us, res = _oracle(prob, x0, steps, **kw)
+    _close(g["traj_x"], xs, 1e-4, "plant states")
+    _close(g["traj_u"], us, 1e-4, "controls")
+    for s in (0, steps // 2, steps - 1):
+        for name in ("x", "z"):
+            _close(g[name][s], getattr(res[s], name), 1e-4, f"step {s} {name}")
+    assert np.max(np.abs(us)) > 0.99  # the limits bind
+    assert np.max(np.abs(g["traj_u"])) <= 1.0 + 1e-6
+
+
+def test_closed_loop_then_plain_solves(rq):
+    """A closed loop leaves the handle usable: a later cold solve matches a fresh handle's."""
+    prob = make_config("c0")
+    x0 = 5.0 * x0_batch(prob.nx, 1, 43)[0]
+    q, l, u = prob.instance(x0)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp64", n_rho=8, max_iter=3, eps_abs=0.0, eps_rel=0.0)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    sol.closed_loop(_dev(x0), 7, _dev(prob.A_dyn), _dev(prob.B), prob.nu)
+    sol.update(q, l, u)
+    sol.solve()
+    a = sol.result()
+    sol.close()
+    fresh = rq.Solver(prob.P, q, prob.A, l, u, precision="fp64", n_rho=8, max_iter=3, eps_abs=0.0, eps_rel=0.0)
+    fresh.solve()
+    b = fresh.result()
+    fresh.close()
+    for name in ("x", "y", "z"):
+        assert np.array_equal(a[name], b[name]), name
