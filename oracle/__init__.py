@@ -11,6 +11,7 @@ Modules:
   * ``lqr``        -- finite-horizon Riccati recursion (exact unconstrained MPC solution)
   * ``mpc_update`` -- the per-solve QP vectors of a condensed MPC problem from x0
   * ``closed_loop`` -- receding-horizon MPC with a fixed ADMM budget per step and a plant
+  * ``scaling``    -- modified Ruiz equilibration with cost scaling, unscaled termination
 
 Parity pins: every function is pinned by a ``-m "not gpu"`` test against something other than
 itself (closed forms, brute force, the paper's own matrix W, Riccati). The iteration counts and

@@ -280,7 +280,7 @@ def _validate(P, q, A, l, u, s):
 
 
 def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=None, record=False,
-          cache: dict | None = None, final_check: bool = True) -> Result:
+          cache: dict | None = None, final_check: bool = True, original=None) -> Result:
     """ReLU-QP solve (Algorithm 1, online part), in FP64.
 
     ``warm``: None for a cold start (x = z = y = 0), or (x, y, rho_index): the previous primal,
@@ -292,6 +292,9 @@ def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=
     on the same P, A, settings and equality pattern (Algorithm 1 computes them once).
     ``final_check=False``: a max_iter that is not a multiple of check_interval ends the solve
     with MAX_ITER and no check (a fixed iteration budget per MPC step, Sec. V-B).
+    ``original``: for a scaled problem (``scaling.scale_problem``), the tuple
+    (P0, q0, A0, D, E, c) of the original data and the scaling: the check then evaluates the
+    residuals and norms of the original problem at the unscaled iterates.
     """
     P = np.asarray(P, np.float64)
     q = np.asarray(q, np.float64)
@@ -344,7 +347,11 @@ def solve(P, q, A, l, u, s: Settings, *, form: str = "R", warm=None, rho_replay=
             res.status = MAX_ITER
             res.iterations = k
             break
-        nm = residual_norms(P, q, A, x, z, y)
+        if original is None:
+            nm = residual_norms(P, q, A, x, z, y)
+        else:
+            P0, q0, A0, D, E, c = original
+            nm = residual_norms(P0, q0, A0, D * x, z / E, E * y / c)
         res.prim_res.append(nm["r_p"])
         res.dual_res.append(nm["r_d"])
         status = RUNNING
