@@ -84,6 +84,10 @@ typedef struct {
   int precision;       /* RQP_FP64, RQP_FP32 or RQP_BF16X3 */
   int batch;           /* instances sharing P and A (>= 1) */
   int engine;          /* RQP_ENGINE_* (default AUTO) */
+  int scaling;         /* passes of the modified Ruiz equilibration with cost scaling (Algorithm 1
+                        * "scale problem", Sec. III-D; OSQP's form): 0 (default) = none, at most
+                        * 100. The solve iterates on the scaled problem; termination, residuals
+                        * and outputs are in the original units. Single-instance engine only. */
 } relu_qp_settings;
 
 typedef struct relu_qp_handle relu_qp_handle; /* opaque, library-owned */
@@ -174,8 +178,8 @@ int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void
  * Ad: nx*nx, Bd: nx*nu row-major (DEVICE FP64); traj_x: (steps+1)*nx, traj_u: steps*nu
  * (DEVICE FP64, caller-owned, written asynchronously on stream); out: results of each step at
  * index s as in relu_qp_solve_sequence. Needs parametric data (RQP_ESTATE); RQP_EINVAL for
- * NULL pointers, steps < 1, nu outside [1, min(m, 256)], nx > 256, or on the batched engine
- * (RQP_ESTATE). */
+ * NULL pointers, steps < 1, nu outside [1, min(m, 256)], nx > 256, or a handle with Ruiz
+ * scaling; RQP_ESTATE on the batched engine. */
 int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const double* Ad, const double* Bd, int nu,
                         double* traj_x, double* traj_u, void* stream, relu_qp_result* out);
 

@@ -74,6 +74,7 @@ class Settings(Structure):
         ("precision", c_int),
         ("batch", c_int),
         ("engine", c_int),
+        ("scaling", c_int),
     ]
 
 

@@ -68,6 +68,14 @@ struct LayerArgs {
   double* traj_x;
   double* traj_u;
   int final_check;      // 0: a max_iter that is not a multiple of check_interval ends unchecked
+  // Ruiz scaling (null: none). The kernel iterates on the scaled problem; the check weights
+  // each row's terms so that residuals and norms are the original problem's, and the outputs
+  // are written unscaled. sc_dual = 1 / (c D) (n), sc_prim = 1 / E (m), un_x = D (n),
+  // un_y = E / c (m).
+  const double* sc_dual;
+  const double* sc_prim;
+  const double* un_x;
+  const double* un_y;
 };
 
 // nx and nu of a closed loop are at most kMaxPlant; grids are at most kMaxGrid workgroups.

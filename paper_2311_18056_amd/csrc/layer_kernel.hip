@@ -309,16 +309,18 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
   uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
   if (tid < nck) {
     const double qv = (double)cq[tid];
-    nb[N_RD] = abs_bits(pr + qv + ar);
-    nb[N_PX] = abs_bits(pr);
-    nb[N_ATY] = abs_bits(ar);
-    nb[N_Q] = abs_bits(qv);
+    const double f = a.sc_dual ? a.sc_dual[cb + tid] : 1.0;  // original units
+    nb[N_RD] = abs_bits(f * (pr + qv + ar));
+    nb[N_PX] = abs_bits(f * pr);
+    nb[N_ATY] = abs_bits(f * ar);
+    nb[N_Q] = abs_bits(f * qv);
   }
   // primal side: A x is carried by the constraint-row owners (no product needed)
   if (rs.own && !rs.xrow) {
-    nb[N_RP] = abs_bits(rs.ax - (double)rs.sz);
-    nb[N_AX] = abs_bits(rs.ax);
-    nb[N_Z] = abs_bits((double)rs.sz);
+    const double e = a.sc_prim ? a.sc_prim[rs.R - a.n] : 1.0;
+    nb[N_RP] = abs_bits(e * (rs.ax - (double)rs.sz));
+    nb[N_AX] = abs_bits(e * rs.ax);
+    nb[N_Z] = abs_bits(e * (double)rs.sz);
   }
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
@@ -410,19 +412,20 @@ template <typename T>
 __device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int sv, int k, int st, int j,
                                        uint32_t tag, const double* exs) {
   if (rs.own) {
+    // the handle keeps the (scaled) iterates; the outputs are in original units
     if (rs.xrow) {
       static_cast<T*>(a.xs)[rs.R] = rs.sx;
-      static_cast<T*>(a.xo)[(long)sv * a.n + rs.R] = rs.sx;
+      static_cast<T*>(a.xo)[(long)sv * a.n + rs.R] = a.un_x ? (T)(a.un_x[rs.R] * (double)rs.sx) : rs.sx;
     } else {
       const int i = rs.R - a.n;
       static_cast<T*>(a.zs)[i] = rs.sz;
       static_cast<T*>(a.ys)[i] = rs.sy;
       a.axs[i] = rs.ax;
-      static_cast<T*>(a.zo)[(long)sv * a.m + i] = rs.sz;
-      static_cast<T*>(a.yo)[(long)sv * a.m + i] = rs.sy;
+      static_cast<T*>(a.zo)[(long)sv * a.m + i] = a.sc_prim ? (T)(a.sc_prim[i] * (double)rs.sz) : rs.sz;
+      static_cast<T*>(a.yo)[(long)sv * a.m + i] = a.un_y ? (T)(a.un_y[i] * (double)rs.sy) : rs.sy;
       if (a.Ad && i < a.nu) {
         // the first stage's applied control (the clamped constraint row plus its E x_s part)
-        const double uv = (double)rs.sz + exs[threadIdx.x];
+        const double uv = ((double)rs.sz + exs[threadIdx.x]) * (a.sc_prim ? a.sc_prim[i] : 1.0);
         a.traj_u[(long)sv * a.nu + i] = uv;
         ll_store(a.xu + ((long)(sv & 1) * a.nu + i) * 2, uv, tag);
       }

@@ -79,6 +79,11 @@ struct relu_qp_handle {
   uint64_t* xu = nullptr;  // closed loop: applied-control words, 2 parities x kMaxPlant x 2
   double* xpl = nullptr;   // closed loop: per-workgroup plant state, 2 x kMaxGrid x kMaxPlant
   double* axs = nullptr;   // A x of the last solve's x (m, FP64), for warm starts that continue it
+  // Ruiz scaling (settings.scaling > 0): x = D xb, z = zb / E, y = E yb / c. Device copy scl:
+  // c D (n), E (m), 1 / (c D) (n), 1 / E (m), D (n), E / c (m).
+  std::vector<double> sD, sE;
+  double sc = 1.0;
+  double* scl = nullptr;
   size_t xw_words = 0, xn_words = 0;
   unsigned* err = nullptr;
   int* abort_h = nullptr;  // host-mapped
@@ -126,7 +131,7 @@ namespace {
 void free_handle(relu_qp_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->W,    h->C,    h->q,    h->l,    h->u,     h->eq_d,   h->grid_d,  h->mid_d,
-                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs,
+                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs, h->scl,
                   h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
                   h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
                   h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
@@ -165,12 +170,74 @@ int validate_settings(const relu_qp_settings* s) {
     return fail(RQP_EINVAL, "unknown precision");
   if (s->batch < 1 || s->batch > (1 << 20)) return fail(RQP_EINVAL, "batch must be in [1, 2^20]");
   if (s->engine < RQP_ENGINE_AUTO || s->engine > RQP_ENGINE_BATCH) return fail(RQP_EINVAL, "unknown engine");
+  if (s->scaling < 0 || s->scaling > 100) return fail(RQP_EINVAL, "scaling must be in [0, 100] passes");
   const bool batched = s->engine == RQP_ENGINE_BATCH ||
                        (s->engine == RQP_ENGINE_AUTO && (s->batch > 1 || s->precision == RQP_BF16X3));
   if (batched && s->precision == RQP_FP64) return fail(RQP_EINVAL, "the batched engine runs FP32 or BF16X3");
   if (!batched && s->precision == RQP_BF16X3) return fail(RQP_EINVAL, "BF16X3 needs the batched engine");
   if (!batched && s->batch != 1) return fail(RQP_EINVAL, "the single-instance engine needs batch == 1");
+  if (batched && s->scaling > 0) return fail(RQP_EINVAL, "Ruiz scaling runs on the single-instance engine");
   return RQP_OK;
+}
+
+// Modified Ruiz equilibration (Algorithm 1 "scale problem"; Sec. III-D scales the KKT matrix
+// and the cost as OSQP does), FP64 on the host at setup. Each pass: delta = 1 / sqrt of the
+// inf-norm of every column of [[P, A'], [A, 0]] (1 for a zero column, clipped to
+// [1e-4, 1e4]); P <- Dd P Dd, q <- Dd q, A <- De A Dd; then the cost scale
+// gamma = 1 / max(mean column inf-norm of P, ||q||_inf) (clipped likewise), P, q <- gamma P, q.
+// Returns the accumulated D (n), E (m) and c.
+double clip_scale(double v) {
+  const double d = v > 0.0 ? 1.0 / std::sqrt(v) : 1.0;
+  return d < 1e-4 ? 1e-4 : (d > 1e4 ? 1e4 : d);
+}
+
+void ruiz(int n, int m, const double* P0, const double* q0, const double* A0, int passes, std::vector<double>& D,
+          std::vector<double>& E, double& c) {
+  std::vector<double> P(P0, P0 + (size_t)n * n), A(A0, A0 + (size_t)m * n), q(q0, q0 + n);
+  D.assign(n, 1.0);
+  E.assign(m, 1.0);
+  c = 1.0;
+  std::vector<double> colx(n), colz(m), dd(n), de(m);
+  for (int it = 0; it < passes; ++it) {
+    std::fill(colx.begin(), colx.end(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) colx[j] = std::max(colx[j], std::fabs(P[(size_t)i * n + j]));
+    for (int i = 0; i < m; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double v = std::fabs(A[(size_t)i * n + j]);
+        colx[j] = std::max(colx[j], v);
+        r = std::max(r, v);
+      }
+      colz[i] = r;
+    }
+    for (int j = 0; j < n; ++j) dd[j] = clip_scale(colx[j]);
+    for (int i = 0; i < m; ++i) de[i] = clip_scale(colz[i]);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) P[(size_t)i * n + j] = dd[i] * P[(size_t)i * n + j] * dd[j];
+    for (int i = 0; i < n; ++i) q[i] = dd[i] * q[i];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = de[i] * A[(size_t)i * n + j] * dd[j];
+    for (int j = 0; j < n; ++j) D[j] *= dd[j];
+    for (int i = 0; i < m; ++i) E[i] *= de[i];
+    // cost scaling
+    std::fill(colx.begin(), colx.end(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) colx[j] = std::max(colx[j], std::fabs(P[(size_t)i * n + j]));
+    double mean = 0.0, qn = 0.0;
+    for (int j = 0; j < n; ++j) mean += colx[j];
+    mean /= n;
+    for (int i = 0; i < n; ++i) qn = std::max(qn, std::fabs(q[i]));
+    const double sc = std::max(mean, qn);
+    double g = 1.0;
+    if (sc > 0.0) {
+      g = 1.0 / sc;
+      g = g < 1e-4 ? 1e-4 : (g > 1e4 ? 1e4 : g);
+    }
+    for (auto& v : P) v *= g;
+    for (auto& v : q) v *= g;
+    c *= g;
+  }
 }
 
 // Penalty grid (Sec. III-C): {rho0}, or n_rho log-spaced values; start at the value nearest
@@ -219,9 +286,10 @@ int upload(relu_qp_handle* h, void* dst, const double* src, size_t count) {
   return h->esize == 8 ? upload_vec<double>(dst, src, count) : upload_vec<float>(dst, src, count);
 }
 
-hipError_t cast_dev(relu_qp_handle* h, long count, const double* x, void* y, hipStream_t st) {
-  return h->esize == 8 ? rqp::cast_from_f64<double>(count, x, static_cast<double*>(y), st)
-                       : rqp::cast_from_f64<float>(count, x, static_cast<float*>(y), st);
+hipError_t cast_dev(relu_qp_handle* h, long count, const double* x, void* y, hipStream_t st,
+                    const double* f = nullptr, long period = 1) {
+  return h->esize == 8 ? rqp::cast_from_f64<double>(count, x, static_cast<double*>(y), st, f, period)
+                       : rqp::cast_from_f64<float>(count, x, static_cast<float*>(y), st, f, period);
 }
 
 // Forms the compact layer matrices [D_j, D_j A'; A D_j, A D_j A'] for every grid value and the
@@ -588,6 +656,7 @@ void relu_qp_default_settings(relu_qp_settings* s) {
   s->precision = RQP_FP32;
   s->batch = 1;
   s->engine = RQP_ENGINE_AUTO;
+  s->scaling = 0;
 }
 
 const char* relu_qp_last_error(void) { return g_last_error.c_str(); }
@@ -664,6 +733,50 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
     return RQP_OK;
   }
 
+  // Ruiz scaling: the device holds the scaled problem from here on
+  std::vector<double> Ps, As, qs, ls, us;
+  if (s->scaling > 0) {
+    ruiz(n, m, P, q, A, s->scaling, h->sD, h->sE, h->sc);
+    const std::vector<double>& D = h->sD;
+    const std::vector<double>& E = h->sE;
+    const double c = h->sc;
+    Ps.resize((size_t)n * n);
+    As.resize((size_t)m * n);
+    qs.resize(n);
+    ls.resize(m);
+    us.resize(m);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) Ps[(size_t)i * n + j] = c * (D[i] * P[(size_t)i * n + j] * D[j]);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) As[(size_t)i * n + j] = E[i] * A[(size_t)i * n + j] * D[j];
+    for (int i = 0; i < n; ++i) qs[i] = c * D[i] * q[i];
+    for (int i = 0; i < m; ++i) {
+      ls[i] = E[i] * l[i];
+      us[i] = E[i] * u[i];
+    }
+    P = Ps.data();
+    A = As.data();
+    q = qs.data();
+    l = ls.data();
+    u = us.data();
+    std::vector<double> v(3 * ((size_t)n + m));
+    for (int i = 0; i < n; ++i) {
+      v[i] = c * D[i];
+      v[(size_t)n + m + i] = 1.0 / (c * D[i]);
+      v[2 * ((size_t)n + m) + i] = D[i];
+    }
+    for (int i = 0; i < m; ++i) {
+      v[(size_t)n + i] = E[i];
+      v[2 * (size_t)n + m + i] = 1.0 / E[i];
+      v[3 * (size_t)n + 2 * m + i] = E[i] / c;
+    }
+    if (dmalloc(h, &h->scl, v.size() * 8) != hipSuccess ||
+        hipMemcpy(h->scl, v.data(), v.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(RQP_ENOMEM, "scaling vectors: device allocation failed"));
+    }
+  }
+
   if (dmalloc(h, &h->W, nr * h->w_stride * h->esize) != hipSuccess ||
       dmalloc(h, &h->C, (size_t)h->w_stride * h->esize) != hipSuccess ||
       dmalloc(h, &h->q, (size_t)n * h->esize) != hipSuccess || dmalloc(h, &h->l, (size_t)m * h->esize) != hipSuccess ||
@@ -721,6 +834,8 @@ int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const do
       std::vector<double>& dst = side == 0 ? lv : uv;
       if (src) {
         std::memcpy(dst.data(), src, h->m * 8);
+        if (h->scl)
+          for (int i = 0; i < h->m; ++i) dst[i] *= h->sE[i];  // scaled rows (E > 0 keeps l <= u)
       } else {
         void* dev = side == 0 ? h->l : h->u;
         if (es == 8) {
@@ -740,6 +855,12 @@ int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const do
   }
   int rc;
   // a non-finite q is accepted: the solve reports RQP_NONFINITE
+  std::vector<double> qv;
+  if (q && h->scl) {
+    qv.resize(h->n);
+    for (int i = 0; i < h->n; ++i) qv[i] = h->sc * h->sD[i] * q[i];
+    q = qv.data();
+  }
   if (q && (rc = upload(h, h->q, q, h->n))) return rc;
   if (l && (rc = upload(h, h->l, lv.data(), h->m))) return rc;
   if (u && (rc = upload(h, h->u, uv.data(), h->m))) return rc;
@@ -750,9 +871,12 @@ int relu_qp_update_device(relu_qp_handle* h, const double* q, const double* l, c
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long B = h->batch;
-  if (q) HIP_OR_FAIL(cast_dev(h, B * h->n, q, h->q, st));
-  if (l) HIP_OR_FAIL(cast_dev(h, B * h->m, l, h->l, st));
-  if (u) HIP_OR_FAIL(cast_dev(h, B * h->m, u, h->u, st));
+  // with Ruiz scaling: q <- c D q, l <- E l, u <- E u on the way
+  const double* fq = h->scl;
+  const double* fe = h->scl ? h->scl + h->n : nullptr;
+  if (q) HIP_OR_FAIL(cast_dev(h, B * h->n, q, h->q, st, fq, h->n));
+  if (l) HIP_OR_FAIL(cast_dev(h, B * h->m, l, h->l, st, fe, h->m));
+  if (u) HIP_OR_FAIL(cast_dev(h, B * h->m, u, h->u, st, fe, h->m));
   return RQP_OK;
 }
 
@@ -779,6 +903,24 @@ int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const dou
   HIP_OR_FAIL(dmalloc(h, &h->E_d, (size_t)h->m * nx * 8));
   HIP_OR_FAIL(dmalloc(h, &h->lo_d, (size_t)h->m * 8));
   HIP_OR_FAIL(dmalloc(h, &h->hi_d, (size_t)h->m * 8));
+  std::vector<double> Fs, Es, los, his;
+  if (h->scl) {  // scaled rows: q = (c D F) x0, l = E lo - (E E_x) x0, u likewise
+    Fs.assign(F, F + (size_t)h->n * nx);
+    Es.assign(E, E + (size_t)h->m * nx);
+    los.assign(lo, lo + h->m);
+    his.assign(hi, hi + h->m);
+    for (int i = 0; i < h->n; ++i)
+      for (int k = 0; k < nx; ++k) Fs[(size_t)i * nx + k] *= h->sc * h->sD[i];
+    for (int i = 0; i < h->m; ++i) {
+      for (int k = 0; k < nx; ++k) Es[(size_t)i * nx + k] *= h->sE[i];
+      los[i] *= h->sE[i];
+      his[i] *= h->sE[i];
+    }
+    F = Fs.data();
+    E = Es.data();
+    lo = los.data();
+    hi = his.data();
+  }
   HIP_OR_FAIL(hipMemcpy(h->F_d, F, (size_t)h->n * nx * 8, hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(h->E_d, E, (size_t)h->m * nx * 8, hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(h->lo_d, lo, (size_t)h->m * 8, hipMemcpyHostToDevice));
@@ -818,6 +960,15 @@ int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int 
     HIP_OR_FAIL(hipMemcpy(h->bjb, jv.data(), (size_t)B * 4, hipMemcpyHostToDevice));
     h->warm_pending = true;
     return RQP_OK;
+  }
+  std::vector<double> xv, yv;
+  if (h->scl) {  // to scaled units: xb = x / D, yb = c y / E
+    xv.resize(h->n);
+    yv.resize(h->m);
+    for (int i = 0; i < h->n; ++i) xv[i] = x[i] / h->sD[i];
+    for (int i = 0; i < h->m; ++i) yv[i] = h->sc * y[i] / h->sE[i];
+    x = xv.data();
+    y = yv.data();
   }
   if ((rc = upload(h, h->xs, x, h->n)) || (rc = upload(h, h->ys, y, h->m))) return rc;
   HIP_OR_FAIL(hipMemcpy(h->js, &rho_index, sizeof(int), hipMemcpyHostToDevice));
@@ -929,6 +1080,13 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
   a.phi = h->hi_d;
   a.nx = h->nx;
   a.final_check = 1;
+  if (h->scl) {
+    const size_t n = h->n, m = h->m;
+    a.sc_dual = h->scl + n + m;
+    a.sc_prim = h->scl + 2 * n + m;
+    a.un_x = h->scl + 2 * (n + m);
+    a.un_y = h->scl + 3 * n + 2 * m;
+  }
   a.xu = h->xu;
   a.xpl = h->xpl;
   if (cl) {
@@ -976,6 +1134,7 @@ int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const do
   if (nu < 1 || nu > h->m || nu > rqp::kMaxPlant)
     return fail(RQP_EINVAL, "nu = %d outside [1, min(m, %d)]", nu, rqp::kMaxPlant);
   if (h->nx > rqp::kMaxPlant) return fail(RQP_EINVAL, "nx = %d above %d", h->nx, rqp::kMaxPlant);
+  if (h->scl) return fail(RQP_EINVAL, "closed loops run without Ruiz scaling");
   const ClosedLoop cl{Ad, Bd, nu, traj_x, traj_u};
   return solve_impl(h, x0, steps, stream, out, &cl);
 }
@@ -1139,6 +1298,7 @@ int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* b
     t += 2 * (2 * L * words * 8) + 2 * L * 8 * 2 * 8;  // exchange buffers
     t += (size_t)2 * rqp::kMaxPlant * 2 * 8;           // closed-loop control words
     t += (size_t)2 * rqp::kMaxGrid * rqp::kMaxPlant * 8;  // closed-loop plant states
+    if (s->scaling > 0) t += 3 * L * 8;                    // Ruiz scaling vectors
   }
   if (nx > 0) t += ((size_t)n + m) * nx * 8 + 2 * (size_t)m * 8;
   *bytes = t;

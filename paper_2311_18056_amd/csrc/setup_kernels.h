@@ -42,8 +42,9 @@ template <typename T>
 hipError_t mpc_vectors_tiled(int B, int n, int m, int nx, const double* F, const double* E, const double* lo,
                              const double* hi, const double* x0, T* q, T* l, T* u, hipStream_t st);
 
-// y = x cast to T (count elements).
+// y = x cast to T (count elements); with f: y[i] = x[i] * f[i % period] cast to T.
 template <typename T>
-hipError_t cast_from_f64(long count, const double* x, T* y, hipStream_t st);
+hipError_t cast_from_f64(long count, const double* x, T* y, hipStream_t st, const double* f = nullptr,
+                         long period = 1);
 
 }  // namespace rqp

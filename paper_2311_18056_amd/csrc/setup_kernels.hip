@@ -269,9 +269,10 @@ __global__ void assemble_check_kernel(int n, int m, const double* __restrict__ P
 }
 
 template <typename T>
-__global__ void cast_kernel(long count, const double* __restrict__ x, T* __restrict__ y) {
+__global__ void cast_kernel(long count, const double* __restrict__ x, const double* __restrict__ f, long period,
+                            T* __restrict__ y) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < count) y[idx] = (T)x[idx];
+  if (idx < count) y[idx] = f ? (T)(x[idx] * f[idx % period]) : (T)x[idx];
 }
 
 // One wave per output row: q rows first, then the m constraint rows. Writes the vectors
@@ -420,9 +421,10 @@ hipError_t mpc_vectors_tiled(int B, int n, int m, int nx, const double* F, const
 }
 
 template <typename T>
-hipError_t cast_from_f64(long count, const double* x, T* y, hipStream_t st) {
+hipError_t cast_from_f64(long count, const double* x, T* y, hipStream_t st, const double* f, long period) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cast_kernel<T>, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, x, y);
+  hipLaunchKernelGGL(cast_kernel<T>, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, x, f,
+                     period > 0 ? period : 1, y);
   return hipGetLastError();
 }
 
@@ -438,7 +440,7 @@ template hipError_t mpc_vectors<double>(int, int, int, int, const double*, const
                                         const double*, const double*, double*, double*, double*, hipStream_t);
 template hipError_t mpc_vectors_tiled<float>(int, int, int, int, const double*, const double*, const double*,
                                              const double*, const double*, float*, float*, float*, hipStream_t);
-template hipError_t cast_from_f64<float>(long, const double*, float*, hipStream_t);
-template hipError_t cast_from_f64<double>(long, const double*, double*, hipStream_t);
+template hipError_t cast_from_f64<float>(long, const double*, float*, hipStream_t, const double*, long);
+template hipError_t cast_from_f64<double>(long, const double*, double*, hipStream_t, const double*, long);
 
 }  // namespace rqp

@@ -36,7 +36,7 @@ def test_default_settings():
     assert (s.sigma, s.alpha, s.rho0, s.n_rho) == (1e-6, 1.6, 0.1, 1)
     assert (s.rho_min, s.rho_max, s.rho_eq_scale) == (1e-3, 1e3, 1e3)
     assert (s.eps_abs, s.eps_rel, s.max_iter, s.check_interval) == (1e-3, 1e-3, 4000, 25)
-    assert s.batch == 1
+    assert s.batch == 1 and s.scaling == 0
     with pytest.raises(AttributeError):
         rq.default_settings(no_such_field=1)
 
@@ -142,7 +142,9 @@ def test_setup_rejects_bad_settings():
                      (dict(n_rho=65), "n_rho"), (dict(n_rho=8, rho_min=1.0, rho_max=0.5), "rho_min"),
                      (dict(eps_abs=-1.0), "eps_abs"), (dict(max_iter=0), "max_iter"),
                      (dict(check_interval=0), "check_interval"), (dict(precision=7), "precision"),
-                     (dict(engine=9), "engine"), (dict(batch=0), "batch"), (dict(rho_eq_scale=0.0), "rho_eq_scale")):
+                     (dict(engine=9), "engine"), (dict(batch=0), "batch"), (dict(rho_eq_scale=0.0), "rho_eq_scale"),
+                     (dict(scaling=-1), "scaling"), (dict(scaling=101), "scaling"),
+                     (dict(scaling=10, engine=rq._lib.RQP_ENGINE_BATCH), "single-instance")):
         rc, msg = _setup_rc(2, 2, P, q, A, l, u, **kw)
         assert rc == E and word in msg, (kw, rc, msg)
 

@@ -185,6 +185,7 @@ def test_server_two_families(rq, light):
 
 
 @pytest.mark.parametrize("kw", [dict(precision="fp64", engine="single"), dict(precision="fp32", engine="single"),
+                                dict(precision="fp64", engine="single", scaling=10),
                                 dict(precision="fp32", engine="batch", batch=5),
                                 dict(precision="bf16x3", engine="batch", batch=130)])
 def test_footprint_matches_the_bytes_a_handle_holds(rq, kw):
