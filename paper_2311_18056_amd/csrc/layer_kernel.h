@@ -95,8 +95,9 @@ struct LaunchPlan {
   size_t dyn_bytes;
   int max_grid;  // largest cooperative grid with these resources
 };
+// xt: the instantiation that also runs closed loops and Ruiz-scaled problems.
 template <typename T>
-LaunchPlan plan_layer(int L, int grid);
+LaunchPlan plan_layer(int L, int grid, bool xt);
 
 // Launch the persistent solve as a cooperative grid of `grid` workgroups of kLayerBlock threads.
 template <typename T>

@@ -280,7 +280,7 @@ struct CheckOut {
 // Residual check (eqs. primal, dual), stopping test and penalty rule (eq. rho_update; nearest
 // grid value, Sec. III-C) at iteration k, check number nchk. Every workgroup returns the same
 // result.
-template <typename T, int NC>
+template <typename T, int NC, bool XT>
 __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable& rt, RowState<T> rs, int cb,
                                               int nck, const T* cq, int k, int nchk, int j, uint32_t tag,
                                               long hoff) {
@@ -309,7 +309,7 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
   uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
   if (tid < nck) {
     const double qv = (double)cq[tid];
-    const double f = a.sc_dual ? a.sc_dual[cb + tid] : 1.0;  // original units
+    const double f = XT && a.sc_dual ? a.sc_dual[cb + tid] : 1.0;  // original units
     nb[N_RD] = abs_bits(f * (pr + qv + ar));
     nb[N_PX] = abs_bits(f * pr);
     nb[N_ATY] = abs_bits(f * ar);
@@ -317,7 +317,7 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
   }
   // primal side: A x is carried by the constraint-row owners (no product needed)
   if (rs.own && !rs.xrow) {
-    const double e = a.sc_prim ? a.sc_prim[rs.R - a.n] : 1.0;
+    const double e = XT && a.sc_prim ? a.sc_prim[rs.R - a.n] : 1.0;
     nb[N_RP] = abs_bits(e * (rs.ax - (double)rs.sz));
     nb[N_AX] = abs_bits(e * rs.ax);
     nb[N_Z] = abs_bits(e * (double)rs.sz);
@@ -408,22 +408,22 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
   return out;
 }
 
-template <typename T>
+template <typename T, bool XT>
 __device__ __forceinline__ void finish(const LayerArgs& a, RowState<T> rs, int sv, int k, int st, int j,
                                        uint32_t tag, const double* exs) {
   if (rs.own) {
     // the handle keeps the (scaled) iterates; the outputs are in original units
     if (rs.xrow) {
       static_cast<T*>(a.xs)[rs.R] = rs.sx;
-      static_cast<T*>(a.xo)[(long)sv * a.n + rs.R] = a.un_x ? (T)(a.un_x[rs.R] * (double)rs.sx) : rs.sx;
+      static_cast<T*>(a.xo)[(long)sv * a.n + rs.R] = XT && a.un_x ? (T)(a.un_x[rs.R] * (double)rs.sx) : rs.sx;
     } else {
       const int i = rs.R - a.n;
       static_cast<T*>(a.zs)[i] = rs.sz;
       static_cast<T*>(a.ys)[i] = rs.sy;
       a.axs[i] = rs.ax;
-      static_cast<T*>(a.zo)[(long)sv * a.m + i] = a.sc_prim ? (T)(a.sc_prim[i] * (double)rs.sz) : rs.sz;
-      static_cast<T*>(a.yo)[(long)sv * a.m + i] = a.un_y ? (T)(a.un_y[i] * (double)rs.sy) : rs.sy;
-      if (a.Ad && i < a.nu) {
+      static_cast<T*>(a.zo)[(long)sv * a.m + i] = XT && a.sc_prim ? (T)(a.sc_prim[i] * (double)rs.sz) : rs.sz;
+      static_cast<T*>(a.yo)[(long)sv * a.m + i] = XT && a.un_y ? (T)(a.un_y[i] * (double)rs.sy) : rs.sy;
+      if (XT && a.Ad && i < a.nu) {
         // the first stage's applied control (the clamped constraint row plus its E x_s part)
         const double uv = ((double)rs.sz + exs[threadIdx.x]) * (a.sc_prim ? a.sc_prim[i] : 1.0);
         a.traj_u[(long)sv * a.nu + i] = uv;
@@ -486,7 +486,7 @@ __device__ __forceinline__ void load_lds_rows(const LayerArgs& a, int j, int r0,
 // NRS rows of each block in registers, NLM in LDS, the rest streamed. The loop between two
 // checks is kept free of everything the check needs, and the register rows are reloaded after
 // every check, so the check code does not compete with them for registers.
-template <typename T, int NC, int NRS, int NLM>
+template <typename T, int NC, int NRS, int NLM, bool XT>
 __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   constexpr int NW = LLWords<T>::kWords;
   __shared__ T red[NWAVE][kMaxRows];
@@ -535,7 +535,9 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   // closed loop: (E x_s)_i of the owned constraint rows; the applied control
   __shared__ double exs[kMaxRows];
   __shared__ double ucur[kMaxPlant];
-  const bool closed = a.Ad != nullptr;
+  // XT instantiations also run closed loops and scaled problems; the others carry none of
+  // that code (its registers would cost the plain solves)
+  const bool closed = XT && a.Ad != nullptr;
 
   for (int sv = 0; sv < a.count; ++sv) {
     const uint32_t tag = a.tag + (uint32_t)sv * span;
@@ -552,7 +554,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         __syncthreads();
       } else if (!plant_step<NWAVE>(a, sv, tag - span, ucur, &fail_flag)) {
         if (tid == 0) err_raise(a.err, tag);
-        finish<T>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
+        finish<T, XT>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
         return;
       }
       if (g == 0)
@@ -576,7 +578,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
             static_cast<T*>(const_cast<void*>(a.q))[R] = (T)dv;
           } else {
             const int i = R - n;
-            exs[rr] = dv;
+            if constexpr (XT) exs[rr] = dv;
             upd[rr][0] = (T)(a.plo[i] - dv);
             upd[rr][1] = (T)(a.phi[i] - dv);
             static_cast<T*>(const_cast<void*>(a.l))[i] = upd[rr][0];
@@ -590,10 +592,12 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
     __syncthreads();
 
     // row-owner state: cold (zero, start penalty), warm from the handle (first solve) or from
-    // the previous solve of this launch. A warm start that continues a solve takes z = A x
-    // from the product the constraint-row owners carried along it (in registers within the
-    // launch, from the handle's copy across launches); only a caller-given x needs the product.
-    const bool carried = warm && (sv > 0 || a.warm_ax != 0);
+    // the previous solve of this launch. In the XT instantiation (closed loops, scaled
+    // problems) a warm start that continues a solve takes z = A x from the product the
+    // constraint-row owners carried along it (in registers within the launch, from the
+    // handle's copy across launches); otherwise, and for a caller-given x, z = A x is formed
+    // through the check product (keeping the carried value live costs the plain loop).
+    const bool carried = XT && warm && (sv > 0 || a.warm_ax != 0);
     if (rs.own) {
       if (rs.xrow) {
         rs.sq = a.x0 ? upd[tid][0] : static_cast<const T*>(a.q)[rs.R];
@@ -626,7 +630,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       const bool ok = gather<T, NC>(a.xc, L, tag, cv.v, a.err, tag);
       if (__syncthreads_or(!ok)) {
         if (tid == 0) err_raise(a.err, tag);
-        finish<T>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
+        finish<T, XT>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
         return;
       }
       double ax, unused;
@@ -690,7 +694,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
           __syncthreads();
           if (fail_flag) {
             if (tid == 0) err_raise(a.err, tag);
-            finish<T>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
+            finish<T, XT>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
             return;
           }
 
@@ -720,22 +724,25 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       }
 
       // a fixed budget that is not a multiple of the check interval ends without a check
-      if (!a.final_check && k == max_iter && k % ci != 0) {
-        finish<T>(a, rs, sv, k, ST_MAX_ITER, j, tag, exs);
-        break;  // next solve of the sequence
+      // (closed loops; they run the XT instantiation)
+      if constexpr (XT) {
+        if (!a.final_check && k == max_iter && k % ci != 0) {
+          finish<T, XT>(a, rs, sv, k, ST_MAX_ITER, j, tag, exs);
+          break;  // next solve of the sequence
+        }
       }
 
       // check at iteration k (every check_interval iterations and at max_iter)
       __syncthreads();
-      const CheckOut co = run_check<T, NC>(a, rt, rs, cb, nck, cq, k, nchk, j, tag, (long)sv * a.max_checks);
+      const CheckOut co = run_check<T, NC, XT>(a, rt, rs, cb, nck, cq, k, nchk, j, tag, (long)sv * a.max_checks);
       ++nchk;
       if (!co.ok) {
         if (tid == 0) err_raise(a.err, tag);
-        finish<T>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
+        finish<T, XT>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
         return;
       }
       if (co.status != ST_RUNNING) {
-        finish<T>(a, rs, sv, k, co.status, j, tag, exs);
+        finish<T, XT>(a, rs, sv, k, co.status, j, tag, exs);
         break;  // next solve of the sequence
       }
       if (co.jn != j) {
@@ -785,27 +792,29 @@ struct KernelChoice {
 };
 
 template <typename T, int NC>
-KernelChoice pick_kernel() {
+KernelChoice pick_kernel(bool xt) {
   constexpr int nrs = reg_rows<T, NC>();
   constexpr int nlm = lds_rows_max<T, NC>();
-  return KernelChoice{reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs, nlm>), NC, nrs, nlm};
+  const void* fn = xt ? reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs, nlm, true>)
+                      : reinterpret_cast<const void*>(&layer_kernel<T, NC, nrs, nlm, false>);
+  return KernelChoice{fn, NC, nrs, nlm};
 }
 
 template <typename T>
-KernelChoice kernel_for(int L) {
-  if (L <= BS) return pick_kernel<T, 1>();
-  if (L <= 2 * BS) return pick_kernel<T, 2>();
-  if (L <= 4 * BS) return pick_kernel<T, 4>();
-  if (L <= 8 * BS) return pick_kernel<T, 8>();
+KernelChoice kernel_for(int L, bool xt) {
+  if (L <= BS) return pick_kernel<T, 1>(xt);
+  if (L <= 2 * BS) return pick_kernel<T, 2>(xt);
+  if (L <= 4 * BS) return pick_kernel<T, 4>(xt);
+  if (L <= 8 * BS) return pick_kernel<T, 8>(xt);
   return KernelChoice{nullptr, 0, 0, 0};
 }
 
 }  // namespace
 
 template <typename T>
-LaunchPlan plan_layer(int L, int grid) {
+LaunchPlan plan_layer(int L, int grid, bool xt) {
   LaunchPlan p{};
-  const KernelChoice kc = kernel_for<T>(L);
+  const KernelChoice kc = kernel_for<T>(L, xt);
   if (!kc.fn || grid < 1) return p;
   int dev = 0, smem_max = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return p;
@@ -843,8 +852,8 @@ hipError_t launch_layer(const LayerArgs& a, const LaunchPlan& p, int grid, hipSt
   return hipLaunchCooperativeKernel(p.fn, dim3(grid), dim3(BS), args, p.dyn_bytes, st);
 }
 
-template LaunchPlan plan_layer<float>(int, int);
-template LaunchPlan plan_layer<double>(int, int);
+template LaunchPlan plan_layer<float>(int, int, bool);
+template LaunchPlan plan_layer<double>(int, int, bool);
 template hipError_t launch_layer<float>(const LayerArgs&, const LaunchPlan&, int, hipStream_t);
 template hipError_t launch_layer<double>(const LayerArgs&, const LaunchPlan&, int, hipStream_t);
 

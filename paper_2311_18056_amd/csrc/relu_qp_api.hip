@@ -58,7 +58,8 @@ struct relu_qp_handle {
   std::vector<unsigned char> eq;
   int j0 = 0;
   int grid_wg = 0;   // workgroups of the persistent launch
-  rqp::LaunchPlan plan{};
+  rqp::LaunchPlan plan{};    // plain solves
+  rqp::LaunchPlan plan_xt{}; // closed loops and Ruiz-scaled problems
   // device
   void* W = nullptr;
   long w_stride = 0;
@@ -328,8 +329,8 @@ int build_weights(relu_qp_handle* h, const double* P, const double* A, hipStream
   return RQP_OK;
 }
 
-rqp::LaunchPlan make_plan(const relu_qp_handle* h, int grid) {
-  return h->esize == 8 ? rqp::plan_layer<double>(h->L, grid) : rqp::plan_layer<float>(h->L, grid);
+rqp::LaunchPlan make_plan(const relu_qp_handle* h, int grid, bool xt) {
+  return h->esize == 8 ? rqp::plan_layer<double>(h->L, grid, xt) : rqp::plan_layer<float>(h->L, grid, xt);
 }
 
 // Launch shape: one workgroup per compute unit (at most one per row), at most kMaxRows rows
@@ -338,10 +339,12 @@ int set_grid(relu_qp_handle* h, int grid) {
   const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
   const int top = h->L < 256 ? h->L : 256;  // the check gathers at most 8 * 256 norm partials
   if (grid < need || grid > top) return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, top);
-  rqp::LaunchPlan p = make_plan(h, grid);
-  if (!p.fn) return fail(RQP_EHIP, "no kernel resources for n + m = %d", h->L);
-  if (grid > p.max_grid) return fail(RQP_EINVAL, "grid %d exceeds the cooperative limit %d", grid, p.max_grid);
+  rqp::LaunchPlan p = make_plan(h, grid, false), px = make_plan(h, grid, true);
+  if (!p.fn || !px.fn) return fail(RQP_EHIP, "no kernel resources for n + m = %d", h->L);
+  const int lim = p.max_grid < px.max_grid ? p.max_grid : px.max_grid;
+  if (grid > lim) return fail(RQP_EINVAL, "grid %d exceeds the cooperative limit %d", grid, lim);
   h->plan = p;
+  h->plan_xt = px;
   h->grid_wg = grid;
   return RQP_OK;
 }
@@ -1098,8 +1101,9 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
     a.chain = 1;
     a.final_check = 0;
   }
-  hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, h->plan, h->grid_wg, st)
-                               : rqp::launch_layer<float>(a, h->plan, h->grid_wg, st);
+  const rqp::LaunchPlan& plan = (cl || h->scl) ? h->plan_xt : h->plan;
+  hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, h->grid_wg, st)
+                               : rqp::launch_layer<float>(a, plan, h->grid_wg, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
   h->tag += span * (uint32_t)count;
   h->warm_pending = false;
