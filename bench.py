@@ -285,7 +285,7 @@ def main():
             # measured HBM bytes per launch (rocprofv3 counters) over the same launch duration
             "traffic": None if traffic_bytes is None else traffic_bytes / avg_launch_s / 1e9,
             "traffic_bytes_per_launch": traffic_bytes,
-            "kernel": "layer_kernel<float,4,8,8>",
+            "kernel": "layer_kernel<float, 4, 8, 8, false>",
             "alg_bytes_per_unit": bytes_per_unit,
             "avg_launch_us": float(np.mean(kern_ms) * 1e3),
         },
