@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
     ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
     ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
+    ap.add_argument("--form-iters", type=int, default=2000, help="forms: layers per timed run")
     ap.add_argument("--closed-nu", default="10,40,50", help="closed: control dimensions")
     ap.add_argument("--budgets", default="1,2,15", help="closed: ADMM iterations per MPC step")
     ap.add_argument("--closed-steps", type=int, default=1000, help="closed: MPC steps per launch")
@@ -57,11 +58,12 @@ def parse():
     ap.add_argument("--dense-problems", type=int, default=10, help="dense: problems per size")
     ap.add_argument("--dense-reps", type=int, default=3, help="dense: timed solves per problem")
     ap.add_argument("--dense-precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "dense", "closed"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "dense", "closed", "forms"], default="c1",
                     help="c1: one instance per solve (the headline, n = m = 1600); c2: one instance per solve "
                          "of the n = 600, m = 1800 family; batch: 4096 instances of the c1 family per solve on "
                          "the matrix cores; serve: continuous batching of MPC requests; dense: random dense QPs "
-                         "with equality rows to eps 1e-6; closed: closed-loop MPC, fixed iterations per step")
+                         "with equality rows to eps 1e-6; closed: closed-loop MPC, fixed iterations per step; forms: compact vs the "
+                         "paper's literal layer")
     ap.add_argument("--precision", choices=["bf16x3", "fp32"], default="bf16x3", help="batched engine precision")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--rates", default="100,300,1000,3000,10000,20000", help="serve: request rates per second")
@@ -143,6 +145,8 @@ def main():
         return bench_dense(args)
     if args.workload == "closed":
         return bench_closed(args)
+    if args.workload == "forms":
+        return bench_forms(args)
 
     import torch
 
@@ -517,6 +521,49 @@ def dense_cpu_baseline(settings, budget_s):
         done += 1
     return {"value": done / dt, "unit": "solves/s at n=2000", "cores": int(cores), "kind": "oracle",
             "sample": f"{done} of the n = 2000 problems, each solved once to 1e-6 after an untimed setup"}
+
+
+def bench_forms(args):
+    """Layer forms at alpha = 1 and a fixed penalty (0.1), FP32: the compact form the solver runs
+    ([x; z] rows, (n+m)^2 weights held on chip) against the paper's literal layer ([x; z; lambda]
+    rows, (n+2m)^2 weights streamed every layer), both one exchange per layer. Fixed iteration
+    counts; the compact run checks once at the end."""
+    import torch
+
+    import paper_2311_18056_amd as rq
+    from workloads import make_config, x0_batch
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    K = args.form_iters
+    rows = []
+    for name, scale in (("c1", 20.0), ("c2", 3.0)):
+        prob = make_config(name)
+        q, l, u = prob.instance(scale * x0_batch(prob.nx, 1, 1001)[0])
+        n, m = prob.n, prob.m
+        sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp32", alpha=1.0, n_rho=1, rho0=0.1, eps_abs=0.0,
+                        eps_rel=0.0, max_iter=K, check_interval=K)
+        res = {}
+        for form, run in (("compact", lambda: sol.solve(stream)), ("paper", lambda: sol.solve_paper_form(K, stream))):
+            run()  # warm-up (and the paper form's one-time weight build)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                run()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            res[form] = float(np.min(ms)) * 1e3 / K
+        rows.append({"workload": name, "n": n, "m": m, "iterations": K,
+                     "compact_us_per_iter": res["compact"], "paper_us_per_iter": res["paper"],
+                     "compact_weight_MB": (n + m) ** 2 * 4 / 1e6, "paper_weight_MB": (n + 2 * m) ** 2 * 4 / 1e6,
+                     "paper_streamed_TBs": (n + 2 * m) ** 2 * 4 / (res["paper"] * 1e-6) / 1e12})
+        print(json.dumps(rows[-1]), flush=True)
+        sol.close()
+    print(json.dumps({"metric": "us per layer, compact vs the paper's literal layer (alpha 1, fixed penalty)",
+                      "unit": "us", "n_gpus": 1, "dtype": "f32", "data": "synthetic", "runs": rows}), flush=True)
 
 
 # MPC step times the paper reports for one ADMM iteration per step (Fig. 1, RTX 3080; context)

@@ -166,6 +166,19 @@ int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_
  * data; RQP_EINVAL if count < 1, on the batched engine, or count*(max_iter+2) >= 2^31. */
 int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out);
 
+/* The paper's literal layer (eq. gpu_update), for comparison with the compact form the solver
+ * runs: v <- clamp(W v + b, c~, d~) with v = [x; z; lambda] (n + 2m), W the full
+ * (n+2m) x (n+2m) weight matrix built from the handle's matrices at first use (FP64 products,
+ * stored in the iteration precision, streamed from memory every layer), b = [-D q; -A D q; 0]
+ * from the handle's q, only the z block clamped to [l, u]. Runs `iters` layers from v = 0 in
+ * one launch, asynchronously on stream, and writes x, z and the lagged dual lambda (the
+ * textbook dual of the previous layer) to out->x, out->z, out->y; iterations = iters, status
+ * RQP_MAX_ITER. Exactly the textbook iteration at alpha = 1 with a fixed penalty, so it needs
+ * alpha == 1 and n_rho == 1 (RQP_EINVAL otherwise, or with Ruiz scaling, iters outside
+ * [1, 2^24], or n + 2m > 16384); RQP_ESTATE on the batched engine. The weights (and their
+ * exchange words) stay allocated with the handle after the first call. */
+int relu_qp_solve_paper_form(relu_qp_handle* h, int iters, void* stream, relu_qp_result* out);
+
 /* Closed-loop MPC (the receding-horizon use of Sec. V-B) in ONE launch of the single-instance
  * engine: `steps` MPC steps, step s from the plant state x_s (x_0 = x0, DEVICE FP64, nx):
  * q, l, u from x_s as in relu_qp_solve_x0, then settings.max_iter iterations (the per-step

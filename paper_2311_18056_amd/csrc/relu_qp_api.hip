@@ -15,6 +15,7 @@
 #include "relu_qp.h"
 #include "batch_kernel.h"
 #include "layer_kernel.h"
+#include "paper_layer.h"
 #include "setup_kernels.h"
 
 namespace {
@@ -85,6 +86,10 @@ struct relu_qp_handle {
   std::vector<double> sD, sE;
   double sc = 1.0;
   double* scl = nullptr;
+  // the paper's literal layer (built at first use): W (n+2m) x ldp and its exchange words
+  void* Wp = nullptr;
+  long ldp = 0;
+  uint64_t* xwp = nullptr;
   size_t xw_words = 0, xn_words = 0;
   unsigned* err = nullptr;
   int* abort_h = nullptr;  // host-mapped
@@ -132,7 +137,7 @@ namespace {
 void free_handle(relu_qp_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->W,    h->C,    h->q,    h->l,    h->u,     h->eq_d,   h->grid_d,  h->mid_d,
-                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs, h->scl,
+                  h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs, h->scl, h->Wp, h->xwp,
                   h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
                   h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
                   h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
@@ -1127,6 +1132,86 @@ int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_
 int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out) {
   if (!x0s) return fail(RQP_EINVAL, "x0s is NULL");
   return solve_impl(h, x0s, count, stream, out);
+}
+
+int relu_qp_solve_paper_form(relu_qp_handle* h, int iters, void* stream, relu_qp_result* out) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (h->batched) return fail(RQP_ESTATE, "the paper's layer form runs on the single-instance engine");
+  if (h->grid.size() != 1 || h->s.alpha != 1.0)
+    return fail(RQP_EINVAL, "the paper's layer form needs alpha = 1 and a fixed penalty (n_rho = 1)");
+  if (h->scl) return fail(RQP_EINVAL, "the paper's layer form runs without Ruiz scaling");
+  if (iters < 1 || iters > (1 << 24)) return fail(RQP_EINVAL, "iters must be in [1, 2^24]");
+  if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status)
+    return fail(RQP_EINVAL, "result buffers x, y, z, iterations and status are required");
+  const int n = h->n, m = h->m;
+  const long Lp = (long)n + 2L * m;
+  if (Lp > rqp::kPaperMaxL) return fail(RQP_EINVAL, "n + 2m = %ld above %d", Lp, rqp::kPaperMaxL);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t words = h->esize == 8 ? 2 : 1;
+  if (!h->Wp) {
+    const long ldp = (Lp + 3) / 4 * 4;
+    if (dmalloc(h, &h->Wp, (size_t)Lp * ldp * h->esize) != hipSuccess ||
+        dmalloc(h, &h->xwp, 2 * (size_t)Lp * words * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RQP_ENOMEM, "paper-form weights: device allocation failed");
+    }
+    HIP_OR_FAIL(hipMemset(h->xwp, 0, 2 * (size_t)Lp * words * 8));
+    std::vector<double> rv(m);
+    for (int i = 0; i < m; ++i) rv[i] = h->grid[0] * (h->eq[i] ? h->s.rho_eq_scale : 1.0);
+    DevBuf rho;
+    if (rho.alloc((size_t)m * 8)) return fail(RQP_ENOMEM, "paper-form setup: device allocation failed");
+    HIP_OR_FAIL(hipMemcpy(rho.p, rv.data(), (size_t)m * 8, hipMemcpyHostToDevice));
+    hipError_t e = h->esize == 8
+                       ? rqp::assemble_paper_w<double>(n, m, static_cast<const double*>(h->W), h->ldw,
+                                                       static_cast<const double*>(h->C), rho.d(), h->s.sigma,
+                                                       static_cast<double*>(h->Wp), ldp, st)
+                       : rqp::assemble_paper_w<float>(n, m, static_cast<const float*>(h->W), h->ldw,
+                                                      static_cast<const float*>(h->C), rho.d(), h->s.sigma,
+                                                      static_cast<float*>(h->Wp), ldp, st);
+    if (e != hipSuccess) return fail(RQP_EHIP, "paper-form setup failed: %s", hipGetErrorString(e));
+    h->ldp = ldp;
+  }
+  const uint32_t span = (uint32_t)iters + 2u;
+  if ((uint64_t)h->tag + span >= 0xffffffffull) {
+    // restart the tag sequence: clear every exchange word so no stale tag can match
+    HIP_OR_FAIL(hipMemsetAsync(h->xw, 0, h->xw_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xc, 0, h->xw_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xn, 0, h->xn_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xu, 0, (size_t)2 * rqp::kMaxPlant * 2 * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xwp, 0, 2 * (size_t)Lp * words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->err, 0, sizeof(unsigned), st));
+    h->tag = 1;
+  }
+  int cus = 0, dev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev));
+  HIP_OR_FAIL(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int grid = cus < 256 ? cus : 256;
+  if (grid > Lp) grid = (int)Lp;
+  if ((Lp + grid - 1) / grid > rqp::kPaperMaxRows) return fail(RQP_EINVAL, "too many rows per workgroup");
+  rqp::PaperArgs a{};
+  a.n = n;
+  a.m = m;
+  a.Lp = (int)Lp;
+  a.ldp = h->ldp;
+  a.W = h->Wp;
+  a.Wc = h->W;
+  a.ldw = h->ldw;
+  a.q = h->q;
+  a.l = h->l;
+  a.u = h->u;
+  a.iters = iters;
+  a.xw = h->xwp;
+  a.tag = h->tag;
+  a.err = h->err;
+  a.xo = out->x;
+  a.zo = out->z;
+  a.yo = out->y;
+  a.iterations = out->iterations;
+  a.status = out->status;
+  hipError_t e = h->esize == 8 ? rqp::launch_paper_layer<double>(a, grid, st) : rqp::launch_paper_layer<float>(a, grid, st);
+  if (e != hipSuccess) return fail(RQP_EHIP, "paper-form launch failed: %s", hipGetErrorString(e));
+  h->tag += span;
+  return RQP_OK;
 }
 
 int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const double* Ad, const double* Bd, int nu,

@@ -183,6 +183,12 @@ class Solver:
                                            byref(out["_result"])))
         return out
 
+    def solve_paper_form(self, iters: int, stream=None, out: Result | None = None):
+        """``iters`` layers of the paper's literal form v <- clamp(W v + b) from v = 0 (alpha = 1,
+        fixed penalty); x, z and the lagged dual go to the result tensors."""
+        check(lib().relu_qp_solve_paper_form(self._h, int(iters), _stream_handle(stream),
+                                             byref(out if out is not None else self._res)))
+
     def closed_loop(self, x0: torch.Tensor, steps: int, Ad: torch.Tensor, Bd: torch.Tensor, nu: int, stream=None,
                     out=None):
         """``steps`` MPC steps in one launch: each runs ``max_iter`` warm-started iterations from
