@@ -247,3 +247,41 @@ def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
                 assert _rel(res[name][b], getattr(ref, name)) <= tol, (prec, shape, b, name)
     sol.close()
     print(f"\n{prec}: autotuner us/iteration {us}, chose {tn}")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("bf16x3", 5e-3)])
+def test_batch_full_size_configuration_3(rq, prec, tol):
+    """4096 instances of the n = m = 1600 family in the benchmark's launch configuration (the
+    autotuned tile, 8 penalties), x0 scaled 20x so that limits bind and penalties switch:
+    100 fixed iterations compared per iterate on sampled instances (schedules replayed), then a
+    solve to eps 1e-3 whose sampled solutions pass the FP64 residual test."""
+    prob = make_config("c1")
+    B = 4096
+    _, q, l, u = _batch_inputs(prob, B, 3_000_000, 20.0)
+    kw = dict(precision=prec, engine="batch", n_rho=8)
+    sol = rq.Solver(prob.P, q, prob.A, l, u, eps_abs=0.0, eps_rel=0.0, max_iter=100, **kw)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    cache = {}
+    worst = 0.0
+    for b in (0, 2047, B - 1):
+        ref = oracle.solve(prob.P, q[b], prob.A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=100),
+                           rho_replay=res["rho_hist"][b][:4].tolist(), cache=cache)
+        assert res["iterations"][b] == 100
+        for name in ("x", "z", "y"):
+            e = _rel(res[name][b], getattr(ref, name))
+            worst = max(worst, e)
+            assert e <= tol, f"{prec} instance {b} {name}: {e:.3e}"
+    sol = rq.Solver(prob.P, q, prob.A, l, u, **kw)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    assert np.all(res["status"] == rq.RQP_SOLVED)
+    for b in (5, 3000):
+        x, z, y = (res[k][b].astype(np.float64) for k in ("x", "z", "y"))
+        nm = admm.residual_norms(prob.P, q[b], prob.A, x, z, y)
+        assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
+        assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+    print(f"\n{prec} B={B}: worst sampled per-vector error after 100 iterations {worst:.3e}; "
+          f"mean iterations to 1e-3 {np.mean(res['iterations']):.1f}")

@@ -238,3 +238,47 @@ def test_server_admits_families_by_memory(rq):
     for f in fams:
         if f.resident:
             f.unload()
+
+
+def test_full_size_family_alone_equals_in_the_mix(rq):
+    """The largest served family (n = m = 3200, BF16x3 slots): requests admitted at different
+    steps next to each other give the bit-identical result of the same request alone (a batch of
+    one), and lie near the FP64 oracle with their schedule replayed (error stated)."""
+    prob = make_config("f3200")
+    kw = dict(precision="bf16x3", n_rho=8)
+    B = 4
+    sol = rq.Solver(prob.P, np.zeros((B, prob.n)), prob.A, np.repeat(prob.lo[None], B, 0),
+                    np.repeat(prob.hi[None], B, 0), engine="batch", **kw)
+    sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    x0 = 20.0 * x0_batch(prob.nx, 3, 3200)
+    done, admitted = {}, {0: 0, 2: 1}
+    sol.load_slots_x0([0, 2], _dev(x0[:2]))
+    sol.admit([0, 2])
+    for step in range(400):
+        sol.step(1)
+        r = sol.result()
+        for s, req in list(admitted.items()):
+            if r["status"][s] != rq.RQP_RUNNING:
+                done[req] = _snapshot(sol, s)
+                del admitted[s]
+        if step == 0:
+            sol.load_slots_x0([3], _dev(x0[2:3]))
+            sol.admit([3])
+            admitted[3] = 2
+        if not admitted:
+            break
+    sol.close()
+    assert sorted(done) == [0, 1, 2]
+    cache = {}
+    for req, d in done.items():
+        solo = _solo(rq, prob, x0[req], **kw)
+        assert d["status"] == solo["status"] == rq.RQP_SOLVED, req
+        assert d["iterations"] == solo["iterations"] and d["rho_hist"] == solo["rho_hist"], req
+        for name in ("x", "y", "z"):
+            assert np.array_equal(d[name], solo[name]), (req, name)
+        q, l, u = qp_vectors(prob.F, prob.E, prob.lo, prob.hi, x0[req])
+        ref = oracle.solve(prob.P, q, prob.A, l, u, _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=d["iterations"]),
+                           rho_replay=d["rho_hist"], cache=cache)
+        err = max(_rel(d[name], getattr(ref, name)) for name in ("x", "z"))
+        print(f"\nf3200 request {req}: {d['iterations']} iterations, BF16x3 error vs FP64 oracle {err:.2e}")
+        assert err < 5e-3
