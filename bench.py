@@ -689,8 +689,7 @@ def bench_serve(args):
         "rates": rows,
     }
     for f in fams:
-        if f.resident:
-            f.unload()
+        f.close()
     for s in singles:
         s.close()
     print(json.dumps(out), flush=True)

@@ -249,6 +249,17 @@ int relu_qp_set_tile(relu_qp_handle* h, int tile_rows);
  * device call; *setup_extra (may be NULL) receives the FP64 workspace setup holds on top of
  * that while it factors. RQP_EINVAL for bad sizes or settings (as relu_qp_setup). */
 int relu_qp_device_bytes(const relu_qp_handle* h, size_t* bytes);
+
+/* Spill and restore, so that a server can take a family out of HBM without losing its setup:
+ * relu_qp_offload waits for the device, copies every resident allocation of the handle
+ * (weights, state, slots, exchange words) to pinned host memory (allocated at the first
+ * offload and kept with the handle) and frees the device memory: relu_qp_device_bytes then
+ * reports 0, and every call that needs the device returns RQP_ESTATE. relu_qp_restore
+ * allocates the device memory again and copies everything back, so the handle continues
+ * exactly where it stopped. Both are synchronous; a second offload (restore) is a no-op.
+ * RQP_ENOMEM if the host (device) memory cannot be had; the handle is then left as it was. */
+int relu_qp_offload(relu_qp_handle* h);
+int relu_qp_restore(relu_qp_handle* h);
 int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* bytes, size_t* setup_extra);
 
 /* Ask a running solve to stop with status RQP_ABORTED (any thread). The flag lives in host

@@ -48,6 +48,8 @@ EXPORTS = [
     "relu_qp_device_bytes",
     "relu_qp_closed_loop",
     "relu_qp_solve_paper_form",
+    "relu_qp_offload",
+    "relu_qp_restore",
     "relu_qp_footprint",
     "relu_qp_abort",
     "relu_qp_max_checks",
@@ -133,6 +135,8 @@ def lib():
     L.relu_qp_set_tile.argtypes = [h, c_int]
     L.relu_qp_device_bytes.argtypes = [h, POINTER(c_size_t)]
     L.relu_qp_solve_paper_form.argtypes = [h, c_int, c_void_p, POINTER(Result)]
+    L.relu_qp_offload.argtypes = [h]
+    L.relu_qp_restore.argtypes = [h]
     L.relu_qp_closed_loop.argtypes = [h, c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
                                       POINTER(Result)]
     L.relu_qp_footprint.argtypes = [c_int, c_int, POINTER(Settings), c_int, POINTER(c_size_t), POINTER(c_size_t)]

@@ -38,6 +38,12 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(RQP_EHIP, "%s: %s", #expr, hipGetErrorString(e_));        \
   } while (0)
 
+// Entry points that touch the handle's device memory refuse an offloaded handle.
+#define DEVICE_OR_FAIL(h)                                                                       \
+  do {                                                                                         \
+    if ((h)->offloaded) return fail(RQP_ESTATE, "the handle is offloaded (relu_qp_restore first)"); \
+  } while (0)
+
 // RAII device buffer used during setup
 struct DevBuf {
   void* p = nullptr;
@@ -130,6 +136,15 @@ struct relu_qp_handle {
   rqp::BatchPlan bplans[2]{};        // tile rows 128 and 64
   double tile_us[2] = {0.0, 0.0};    // autotuner: microseconds per iteration of each shape
   size_t dev_bytes = 0;              // requested bytes of the resident device allocations
+  // every resident device allocation (the handle field that holds it, its size, and its pinned
+  // host copy once the handle has been offloaded)
+  struct DevAlloc {
+    void** slot;
+    size_t bytes;
+    void* host;
+  };
+  std::vector<DevAlloc> allocs;
+  bool offloaded = false;
 };
 
 namespace {
@@ -143,6 +158,8 @@ void free_handle(relu_qp_handle* h) {
                   h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (auto& e : h->allocs)
+    if (e.host) (void)hipHostFree(e.host);
   if (h->abort_h) (void)hipHostFree(h->abort_h);
   delete h;
 }
@@ -151,8 +168,24 @@ void free_handle(relu_qp_handle* h) {
 hipError_t dmalloc(relu_qp_handle* h, void** p, size_t bytes) {
   const size_t b = bytes ? bytes : 8;
   hipError_t e = hipMalloc(p, b);
-  if (e == hipSuccess) h->dev_bytes += b;
+  if (e == hipSuccess) {
+    h->dev_bytes += b;
+    h->allocs.push_back({p, b, nullptr});
+  }
   return e;
+}
+
+// Frees one resident allocation (and its host copy) and forgets it.
+void dfree(relu_qp_handle* h, void** p) {
+  for (size_t i = 0; i < h->allocs.size(); ++i)
+    if (h->allocs[i].slot == p) {
+      if (*p) (void)hipFree(*p);
+      if (h->allocs[i].host) (void)hipHostFree(h->allocs[i].host);
+      h->dev_bytes -= h->allocs[i].bytes;
+      h->allocs.erase(h->allocs.begin() + (long)i);
+      break;
+    }
+  *p = nullptr;
 }
 template <typename T>
 hipError_t dmalloc(relu_qp_handle* h, T** p, size_t bytes) {
@@ -811,6 +844,7 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
 
 int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const double* u) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (h->batched) {
     const int B = h->batch, n = h->n, m = h->m;
     if ((l == nullptr) != (u == nullptr)) return fail(RQP_EINVAL, "the batched engine updates l and u together");
@@ -877,6 +911,7 @@ int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const do
 
 int relu_qp_update_device(relu_qp_handle* h, const double* q, const double* l, const double* u, void* stream) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const long B = h->batch;
   // with Ruiz scaling: q <- c D q, l <- E l, u <- E u on the way
@@ -891,21 +926,14 @@ int relu_qp_update_device(relu_qp_handle* h, const double* q, const double* l, c
 int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const double* E, const double* lo,
                            const double* hi) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (nx < 1 || !F || !E || !lo || !hi) return fail(RQP_EINVAL, "bad parametric data");
   int rc = validate_bounds(h->m, lo, hi);
   if (rc) return rc;
   for (int i = 0; i < h->m; ++i)
     if ((lo[i] == hi[i]) != (h->eq[i] != 0)) return fail(RQP_EINVAL, "equality pattern of lo/hi differs at %d", i);
-  const size_t sizes[4] = {(size_t)h->n * h->nx * 8, (size_t)h->m * h->nx * 8, (size_t)h->m * 8, (size_t)h->m * 8};
-  int k = 0;
-  for (void** p : {(void**)&h->F_d, (void**)&h->E_d, (void**)&h->lo_d, (void**)&h->hi_d}) {
-    if (*p) {
-      (void)hipFree(*p);
-      *p = nullptr;
-      h->dev_bytes -= sizes[k] ? sizes[k] : 8;
-    }
-    ++k;
-  }
+  for (void** p : {(void**)&h->F_d, (void**)&h->E_d, (void**)&h->lo_d, (void**)&h->hi_d})
+    if (*p) dfree(h, p);
   h->nx = nx;
   HIP_OR_FAIL(dmalloc(h, &h->F_d, (size_t)h->n * nx * 8));
   HIP_OR_FAIL(dmalloc(h, &h->E_d, (size_t)h->m * nx * 8));
@@ -938,6 +966,7 @@ int relu_qp_set_parametric(relu_qp_handle* h, int nx, const double* F, const dou
 
 int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
   if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -958,6 +987,7 @@ int relu_qp_update_x0_device(relu_qp_handle* h, const double* x0, void* stream) 
 
 int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int rho_index) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (!x || !y) return fail(RQP_EINVAL, "x or y is NULL");
   if (rho_index < 0 || rho_index >= (int)h->grid.size()) return fail(RQP_EINVAL, "rho_index out of range");
   int rc;
@@ -1007,6 +1037,7 @@ struct ClosedLoop {
 int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, relu_qp_result* out,
                const ClosedLoop* cl = nullptr) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
     return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1136,6 +1167,7 @@ int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void
 
 int relu_qp_solve_paper_form(relu_qp_handle* h, int iters, void* stream, relu_qp_result* out) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (h->batched) return fail(RQP_ESTATE, "the paper's layer form runs on the single-instance engine");
   if (h->grid.size() != 1 || h->s.alpha != 1.0)
     return fail(RQP_EINVAL, "the paper's layer form needs alpha = 1 and a fixed penalty (n_rho = 1)");
@@ -1231,6 +1263,7 @@ int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const do
 int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const double* q, const double* l,
                        const double* u, void* stream) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   hipStream_t st = static_cast<hipStream_t>(stream);
   return for_slot_chunks(h, slots, n_slots, [&](const rqp::SlotList& sl, int i0) -> int {
     const size_t n = h->n, m = h->m;
@@ -1243,6 +1276,7 @@ int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const d
 
 int relu_qp_load_slots_x0(relu_qp_handle* h, const int* slots, int n_slots, const double* x0, void* stream) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (!h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
   if (!x0 && n_slots > 0) return fail(RQP_EINVAL, "x0 is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1257,6 +1291,7 @@ int relu_qp_load_slots_x0(relu_qp_handle* h, const int* slots, int n_slots, cons
 int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot, int shift_x, int shift_y,
                   void* stream) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (h->batched && (src_slot < -1 || src_slot >= h->batch))
     return fail(RQP_EINVAL, "src_slot %d out of range [-1, %d)", src_slot, h->batch);
   if (shift_x < 0 || shift_x > h->n || shift_y < 0 || shift_y > h->m) return fail(RQP_EINVAL, "bad shift");
@@ -1278,6 +1313,7 @@ int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot
 
 int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* out) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
   if (!h->batched) return fail(RQP_ESTATE, "relu_qp_step needs the batched engine");
   if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
     return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
@@ -1324,6 +1360,50 @@ int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid, int* n_rho) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (n_rho) *n_rho = (int)h->grid.size();
   if (grid) std::memcpy(grid, h->grid.data(), h->grid.size() * 8);
+  return RQP_OK;
+}
+
+int relu_qp_offload(relu_qp_handle* h) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (h->offloaded) return RQP_OK;
+  HIP_OR_FAIL(hipDeviceSynchronize());  // no launch may still use the buffers
+  // host copies first (kept for later offloads), so that a failure leaves the device intact
+  for (auto& e : h->allocs)
+    if (!e.host && hipHostMalloc(&e.host, e.bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      e.host = nullptr;
+      return fail(RQP_ENOMEM, "pinned host memory for the offload failed (%zu bytes)", e.bytes);
+    }
+  for (auto& e : h->allocs) HIP_OR_FAIL(hipMemcpy(e.host, *e.slot, e.bytes, hipMemcpyDeviceToHost));
+  for (auto& e : h->allocs) {
+    (void)hipFree(*e.slot);
+    *e.slot = nullptr;
+  }
+  h->offloaded = true;
+  h->dev_bytes = 0;
+  return RQP_OK;
+}
+
+int relu_qp_restore(relu_qp_handle* h) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  if (!h->offloaded) return RQP_OK;
+  size_t total = 0;
+  for (size_t i = 0; i < h->allocs.size(); ++i) {
+    auto& e = h->allocs[i];
+    if (hipMalloc(e.slot, e.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      for (size_t k = 0; k < i; ++k) {
+        (void)hipFree(*h->allocs[k].slot);
+        *h->allocs[k].slot = nullptr;
+      }
+      *e.slot = nullptr;
+      return fail(RQP_ENOMEM, "device memory for the restore failed (%zu bytes)", e.bytes);
+    }
+    total += e.bytes;
+  }
+  for (auto& e : h->allocs) HIP_OR_FAIL(hipMemcpy(*e.slot, e.host, e.bytes, hipMemcpyHostToDevice));
+  h->offloaded = false;
+  h->dev_bytes = total;
   return RQP_OK;
 }
 

@@ -19,6 +19,9 @@ slot state, result buffers; ``footprint`` gives their bytes before any is create
 only while they fit. A family with queued requests is loaded when its bytes fit beside the
 resident ones, after unloading idle families (no busy slot) least recently used first; if it
 cannot fit yet, families whose queued work is newer stop admitting, drain, and become idle.
+Unloading spills a family to pinned host memory (``relu_qp_offload``) by default, so that
+loading it again is a copy back (``relu_qp_restore``) rather than a new setup (factorisations);
+its result tensors stay on the device and stay counted.
 
 Latency is measured from a request's arrival time to the moment its result is on the host.
 """
@@ -61,9 +64,12 @@ class Family:
     pin: int | None = None      # slot holding the family's most recent solution
     single: Solver | None = None  # optional single-instance handle for light load
     bytes: int = 0              # device bytes of the family's handles while resident
+    residual: int = 0           # of which the result tensors (they stay when the family spills)
     last_used: float = 0.0
     keep_x: bool = False
     spec: dict = field(default_factory=dict)  # what load() builds
+    spill: bool = True          # unload() offloads to pinned host memory instead of freeing
+    spilled: bool = False
 
     @classmethod
     def from_mpc(cls, prob, slots: int, precision: str = "fp32", keep_x: bool = False, lazy: bool = False,
@@ -71,21 +77,22 @@ class Family:
         """lazy: only size the family (``footprint``); its handles are built by load()."""
         fam = cls(solver=None, stage=prob.nu, nx=prob.nx, keep_x=keep_x)
         fam.spec = dict(prob=prob, slots=slots, precision=precision, settings=settings, single=None)
-        fam.bytes = footprint(prob.n, prob.m, prob.nx, batch=slots, precision=precision, engine="batch",
-                              **settings)["resident"]
+        fp = footprint(prob.n, prob.m, prob.nx, batch=slots, precision=precision, engine="batch", **settings)
+        fam.bytes, fam.residual = fp["resident"], fp["results"]
         if not lazy:
             fam.load()
         return fam
 
     @property
     def resident(self) -> bool:
-        return self.solver is not None
+        return self.solver is not None and not self.spilled
 
     def attach_single(self, prob, **settings):
         """Single-instance handle (FP32) of the same family, for light-load sequence launches."""
         self.spec["single"] = settings
-        self.bytes += footprint(prob.n, prob.m, prob.nx, batch=1, precision="fp32", engine="single",
-                                **settings)["resident"]
+        fp = footprint(prob.n, prob.m, prob.nx, batch=1, precision="fp32", engine="single", **settings)
+        self.bytes += fp["resident"]
+        self.residual += fp["results"]
         if self.resident:
             self._load_single()
         return self
@@ -101,6 +108,13 @@ class Family:
         """Build the family's device handles (setup on the device: factorizations per penalty)."""
         if self.resident:
             return
+        if self.spilled:  # back from pinned host memory, exactly as it was
+            for s in (self.solver, self.single):
+                if s is not None:
+                    s.restore()
+            self.spilled = False
+            self.free, self.busy, self.pin = list(range(self.spec["slots"])), {}, None
+            return
         sp = self.spec
         prob, slots = sp["prob"], sp["slots"]
         zq = np.zeros((slots, prob.n))
@@ -114,14 +128,27 @@ class Family:
             self._load_single()
 
     def unload(self):
-        """Free the family's device handles (no slot may be busy); queued requests stay queued."""
+        """Take the family's handles out of HBM (no slot may be busy): spilled to pinned host
+        memory, or freed; queued requests stay queued."""
         assert not self.busy, "unload with busy slots"
+        self.pin, self.free = None, []
+        if self.spill:
+            for s in (self.solver, self.single):
+                if s is not None:
+                    s.offload()
+            self.spilled = True
+            return
         for s in (self.solver, self.single):
             if s is not None:
                 s.close()
-        self.solver, self.single, self.pin = None, None, None
-        self.free = []
+        self.solver, self.single = None, None
         torch.cuda.empty_cache()  # hand the result tensors' memory back for the next handle
+
+    def close(self):
+        for s in (self.solver, self.single):
+            if s is not None:
+                s.close()
+        self.solver, self.single, self.spilled = None, None, False
 
 
 class MemoryPolicy:
@@ -136,34 +163,50 @@ class MemoryPolicy:
         self.evictions = 0
         self.peak = 0
 
+    @staticmethod
+    def _held(f) -> int:
+        """Device bytes a family holds: all of them while resident, its result tensors while
+        spilled, nothing while freed."""
+        if f.resident:
+            return f.bytes
+        return getattr(f, "residual", 0) if getattr(f, "spilled", False) else 0
+
+    @staticmethod
+    def _freed(g) -> int:
+        return g.bytes - (getattr(g, "residual", 0) if getattr(g, "spill", False) else 0)
+
     def used(self, families) -> int:
-        return sum(f.bytes for f in families if f.resident)
+        return sum(self._held(f) for f in families)
 
     def check(self, families):
         if self.budget is None:
             return
         for f in families:
-            if f.bytes > self.budget:
-                raise ValueError(f"a family needs {f.bytes} bytes, more than the budget {self.budget}")
+            # resident beside everything the other families keep while they are out of HBM
+            others = sum(getattr(g, "residual", 0) for g in families if g is not f and getattr(g, "spill", False))
+            if f.bytes + others > self.budget:
+                raise ValueError(f"a family needs {f.bytes} bytes (+{others} kept by the others), more than the "
+                                 f"budget {self.budget}")
         if self.used(families) > self.budget:
             raise ValueError("the families already resident exceed the budget")
 
     def _fit(self, fam, families) -> bool:
         used = self.used(families)
-        if used + fam.bytes <= self.budget:
+        if used + fam.bytes - self._held(fam) <= self.budget:
             return True
         head = fam.queue[0].t_arrival
         cands = [g for g in families if g is not fam and g.resident and not g.busy
                  and (not g.queue or g.queue[0].t_arrival > head)]
         cands.sort(key=lambda g: (bool(g.queue), g.last_used))
-        free_able = sum(g.bytes for g in cands)
-        if used - free_able + fam.bytes > self.budget:
+        need = fam.bytes - self._held(fam)  # a spilled family already holds its result tensors
+        free_able = sum(self._freed(g) for g in cands)
+        if used - free_able + need > self.budget:
             return False  # not even with every candidate gone: unload nothing yet
         for g in cands:
             g.unload()
             self.evictions += 1
-            used -= g.bytes
-            if used + fam.bytes <= self.budget:
+            used -= self._freed(g)
+            if used + need <= self.budget:
                 break
         return True
 
@@ -192,7 +235,7 @@ class Server:
     """Serves requests over families with continuous batching on one device stream."""
 
     def __init__(self, families: list[Family], n_checks: int = 1, warm: bool = True, light: int = 8,
-                 hbm_budget: int | None = None):
+                 hbm_budget: int | None = None, spill: bool = True):
         """light: a family with at most this many queued requests and no busy slot is served by
         a sequence launch of its single-instance handle (if attached). hbm_budget: device bytes
         the families' handles may hold together (None: every family stays resident)."""
@@ -201,6 +244,8 @@ class Server:
         self.warm = warm
         self.light = light
         self.memory = MemoryPolicy(hbm_budget)
+        for f in families:
+            f.spill = spill
         self.memory.check(families)
         if hbm_budget is None:
             for f in families:

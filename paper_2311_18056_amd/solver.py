@@ -295,6 +295,14 @@ class Solver:
         check(lib().relu_qp_get_tile(self._h, byref(t), us))
         return t.value, {128: us[0], 64: us[1]}
 
+    def offload(self):
+        """Move the handle's device memory to pinned host memory (the result tensors stay)."""
+        check(lib().relu_qp_offload(self._h))
+
+    def restore(self):
+        """Bring an offloaded handle back to the device, exactly as it was."""
+        check(lib().relu_qp_restore(self._h))
+
     def device_bytes(self) -> int:
         """Device bytes this solver holds: the library's resident allocations + result tensors."""
         b = c_size_t()

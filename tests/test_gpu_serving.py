@@ -181,7 +181,7 @@ def test_server_two_families(rq, light):
     summ = latency_summary(reqs)
     assert summ["completed"] == len(reqs)
     for f in fams:
-        f.unload()
+        f.close()
 
 
 @pytest.mark.parametrize("kw", [dict(precision="fp64", engine="single"), dict(precision="fp32", engine="single"),
@@ -209,7 +209,8 @@ def test_footprint_matches_the_bytes_a_handle_holds(rq, kw):
     sol.close()
 
 
-def test_server_admits_families_by_memory(rq):
+@pytest.mark.parametrize("spill", [False, True])
+def test_server_admits_families_by_memory(rq, spill):
     """A budget that holds one family at a time: families are loaded and unloaded as their
     requests come, the budget is never exceeded, and every result still matches the oracle."""
     from paper_2311_18056_amd.serving import Family, Server, latency_summary, poisson_requests
@@ -217,17 +218,21 @@ def test_server_admits_families_by_memory(rq):
     probs = [make_config("c0"), make_config("c0", seed=7), make_config("c0", seed=9)]
     fams = [Family.from_mpc(p, slots=8, precision="fp32", keep_x=True, lazy=True, n_rho=8).attach_single(p, n_rho=8)
             for p in probs]
-    budget = max(f.bytes for f in fams) + 1
+    # one family at a time (with spilling, the others keep their result tensors on the device)
+    budget = max(f.bytes for f in fams) + (sum(f.residual for f in fams) if spill else 0) + 1
     assert sum(f.bytes for f in fams) > budget
     gens = [lambda rng, p=p: 5.0 * rng.uniform(-1, 1, p.nx) for p in probs]
     reqs = poisson_requests(3000.0, 90, 10.0, gens, seed=6)
-    srv = Server(fams, n_checks=1, warm=True, light=8, hbm_budget=budget)
+    srv = Server(fams, n_checks=1, warm=True, light=8, hbm_budget=budget, spill=spill)
     assert not any(f.resident for f in fams)
     srv.run(reqs, time_limit=60.0)
     assert srv.memory.evictions >= 1 and srv.memory.loads >= 3
     assert srv.memory.peak <= budget
-    held = sum(f.solver.device_bytes() + f.single.device_bytes() for f in fams if f.resident)
+    # device_bytes() counts the library's allocations (none while spilled) and the result tensors
+    held = sum(f.solver.device_bytes() + f.single.device_bytes() for f in fams if f.solver is not None)
     assert held <= budget
+    if spill:
+        assert any(f.spilled for f in fams) and all(f.solver is not None for f in fams)
     for r in reqs:
         assert r.status == rq.RQP_SOLVED, r.rid
         p = probs[r.family]
@@ -236,8 +241,7 @@ def test_server_admits_families_by_memory(rq):
         assert _rel(r.x, xs) < 5e-2, r.rid
     assert latency_summary(reqs)["completed"] == len(reqs)
     for f in fams:
-        if f.resident:
-            f.unload()
+        f.close()
 
 
 def test_full_size_family_alone_equals_in_the_mix(rq):
@@ -282,3 +286,37 @@ def test_full_size_family_alone_equals_in_the_mix(rq):
         err = max(_rel(d[name], getattr(ref, name)) for name in ("x", "z"))
         print(f"\nf3200 request {req}: {d['iterations']} iterations, BF16x3 error vs FP64 oracle {err:.2e}")
         assert err < 5e-3
+
+
+@pytest.mark.parametrize("engine", ["single", "batch"])
+def test_offload_restore_round_trip(rq, engine):
+    """A handle taken out of HBM and restored continues exactly as one that never left."""
+    prob = make_config("c0")
+    x0 = 5.0 * x0_batch(prob.nx, 3, 3300)
+    B = 1 if engine == "single" else 3
+    q, l, u = prob.instance(x0[:B] if B > 1 else x0[0])
+    kw = dict(precision="fp32", n_rho=8, engine=engine, max_iter=100, eps_abs=0.0, eps_rel=0.0)
+    a = rq.Solver(prob.P, q, prob.A, l, u, **kw)
+    b = rq.Solver(prob.P, q, prob.A, l, u, **kw)
+    for s in (a, b):
+        s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+        s.set_warm(True)
+        s.update_x0_device(_dev(x0[:B]))
+        s.solve()
+    full = a.device_bytes()
+    a.offload()
+    a.offload()  # no-op
+    # the library holds nothing on the device now; only the result tensors remain
+    assert a.device_bytes() == rq.footprint(prob.n, prob.m, prob.nx, batch=B, **kw)["results"] < full
+    with pytest.raises(rq.ReluQPError):
+        a.solve()
+    a.restore()
+    assert a.device_bytes() == full
+    for s in (a, b):
+        s.update_x0_device(_dev(x0[-B:]))
+        s.solve()  # warm from the state before the offload
+    ra, rb = a.result(), b.result()
+    for name in ("x", "y", "z", "iterations", "status", "rho_index"):
+        assert np.array_equal(ra[name], rb[name]), name
+    a.close()
+    b.close()

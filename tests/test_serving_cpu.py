@@ -150,3 +150,31 @@ def test_policy_rejects_a_family_larger_than_the_budget():
     with pytest.raises(ValueError):
         MemoryPolicy(10).check(_fams({"a": 11}, []))
     MemoryPolicy(None).check(_fams({"a": 11}, []))
+
+
+def test_policy_counts_what_spilled_families_keep():
+    from paper_2311_18056_amd.serving import MemoryPolicy
+
+    log = []
+    a, b = _fams({"a": 60, "b": 60}, log)
+    for f in (a, b):
+        f.spill, f.residual = True, 5
+    # 60 + 5 must fit: 64 is too small
+    with pytest.raises(ValueError):
+        MemoryPolicy(64).check([a, b])
+    pol = MemoryPolicy(70)
+    pol.check([a, b])
+    a.queue.append(_Req(0.0))
+    pol.schedule([a, b])
+    a.queue.clear()
+    b.queue.append(_Req(1.0))
+    a.spilled = False
+    orig = a.unload
+
+    def spill_a():
+        orig()
+        a.spilled = True
+
+    a.unload = spill_a
+    assert pol.schedule([a, b]) == set()
+    assert b.resident and not a.resident and pol.used([a, b]) == 65 and pol.peak <= 70
