@@ -408,6 +408,8 @@ int alloc_exchange(relu_qp_handle* h) {
   HIP_OR_FAIL(dmalloc(h, &h->xu, (size_t)2 * rqp::kMaxPlant * 2 * 8));
   HIP_OR_FAIL(hipMemset(h->xu, 0, (size_t)2 * rqp::kMaxPlant * 2 * 8));
   HIP_OR_FAIL(dmalloc(h, &h->xpl, (size_t)2 * rqp::kMaxGrid * rqp::kMaxPlant * 8));
+  HIP_OR_FAIL(dmalloc(h, &h->axs, (size_t)h->m * 8));
+  HIP_OR_FAIL(hipMemset(h->axs, 0, (size_t)h->m * 8));
   HIP_OR_FAIL(hipMemset(h->xw, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xc, 0, h->xw_words * 8));
   HIP_OR_FAIL(hipMemset(h->xn, 0, h->xn_words * 8));
@@ -823,15 +825,13 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
       dmalloc(h, &h->q, (size_t)n * h->esize) != hipSuccess || dmalloc(h, &h->l, (size_t)m * h->esize) != hipSuccess ||
       dmalloc(h, &h->u, (size_t)m * h->esize) != hipSuccess || dmalloc(h, &h->xs, (size_t)n * h->esize) != hipSuccess ||
       dmalloc(h, &h->zs, (size_t)m * h->esize) != hipSuccess || dmalloc(h, &h->ys, (size_t)m * h->esize) != hipSuccess ||
-      dmalloc(h, &h->js, sizeof(int)) != hipSuccess || dmalloc(h, &h->err, sizeof(unsigned)) != hipSuccess ||
-      dmalloc(h, &h->axs, (size_t)m * 8) != hipSuccess) {
+      dmalloc(h, &h->js, sizeof(int)) != hipSuccess || dmalloc(h, &h->err, sizeof(unsigned)) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(RQP_ENOMEM, "device allocation failed (n=%d, m=%d, %zu penalties)", n, m, nr));
   }
   if ((rc = upload(h, h->q, q, n)) || (rc = upload(h, h->l, l, m)) || (rc = upload(h, h->u, u, m))) return bail(rc);
   if (hipMemset(h->xs, 0, (size_t)n * h->esize) != hipSuccess || hipMemset(h->zs, 0, (size_t)m * h->esize) != hipSuccess ||
       hipMemset(h->ys, 0, (size_t)m * h->esize) != hipSuccess || hipMemset(h->js, 0, sizeof(int)) != hipSuccess ||
-      hipMemset(h->axs, 0, (size_t)m * 8) != hipSuccess ||
       hipMemset(h->err, 0, sizeof(unsigned)) != hipSuccess)
     return bail(fail(RQP_EHIP, "initial copies failed"));
 
