@@ -63,7 +63,30 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, OUT)
+    build_example()
     return OUT
+
+
+EXAMPLE = os.path.join(HERE, "relu_qp_example")
+
+
+def build_example() -> str:
+    """The plain-C user of the ABI (capi_example.c), linked against the in-tree library and the
+    HIP runtime; it finds the library next to itself."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        raise RuntimeError("no C compiler for the C example")
+    tmp = EXAMPLE + ".tmp"
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I",
+           os.path.join(rocm, "include"), os.path.join(HERE, "capi_example.c"), "-L", HERE, "-lrelu_qp", "-L",
+           os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib"),
+           "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("C example build failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":
