@@ -192,7 +192,8 @@ int relu_qp_solve_paper_form(relu_qp_handle* h, int iters, void* stream, relu_qp
  * (DEVICE FP64, caller-owned, written asynchronously on stream); out: results of each step at
  * index s as in relu_qp_solve_sequence. Needs parametric data (RQP_ESTATE); RQP_EINVAL for
  * NULL pointers, steps < 1, nu outside [1, min(m, 256)], nx > 256, or a handle with Ruiz
- * scaling; RQP_ESTATE on the batched engine. */
+ * scaling; RQP_ESTATE on the batched engine. relu_qp_abort is seen at checks only, so a loop
+ * whose budget stays below check_interval runs all its steps. */
 int relu_qp_closed_loop(relu_qp_handle* h, const double* x0, int steps, const double* Ad, const double* Bd, int nu,
                         double* traj_x, double* traj_u, void* stream, relu_qp_result* out);
 
