@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--x0-scale", type=float, default=1.0, help="x0 ~ scale * U[-1,1]^nx (1 = the workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--steady-iters", type=int, default=2000, help="iterations of the fixed-iteration probe")
+    ap.add_argument("--steady-iters", type=int, default=4000, help="iterations of the fixed-iteration probe")
     ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
     ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
     ap.add_argument("--form-iters", type=int, default=2000, help="forms: layers per timed run")
@@ -477,6 +477,8 @@ def bench_batch(args):
         "admm_iters_per_s": float(np.sum(it)) / wall,
         "iters_per_solve": float(np.mean(it)),
         "status_counts": {rq.STATUS_NAMES[int(s)]: int(np.sum(st == s)) for s in np.unique(st)},
+        "latency_ms": {"p50": float(np.percentile(kern_ms, 50)), "p99": float(np.percentile(kern_ms, 99)),
+                       "note": "every instance of a step completes with its launch: the launch duration (events)"},
         "setup_ms": setup_ms,
         "tile_autotuner": {"rows": sol.tile()[0], "us_per_iter": sol.tile()[1]},
         "steady_state": steady,
