@@ -213,7 +213,7 @@ def cpu_baseline_pool(name, x0s, budget_s, workers=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
