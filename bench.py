@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steady-iters", type=int, default=4000, help="iterations of the fixed-iteration probe")
     ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
+    ap.add_argument("--grid", type=int, default=0, help="c0/c1/c2: workgroups per launch (0 = the library's choice)")
+    ap.add_argument("--grid-sweep", default=None,
+                    help="c0/c1/c2: workgroup counts for extra fixed-iteration probes (default: c0 1,2,5,10,20,40)")
     ap.add_argument("--latency-solves", type=int, default=300, help="one-solve launches timed for latency")
     ap.add_argument("--form-iters", type=int, default=2000, help="forms: layers per timed run")
     ap.add_argument("--closed-nu", default="10,40,50", help="closed: control dimensions")
@@ -58,8 +61,10 @@ def parse():
     ap.add_argument("--dense-problems", type=int, default=10, help="dense: problems per size")
     ap.add_argument("--dense-reps", type=int, default=3, help="dense: timed solves per problem")
     ap.add_argument("--dense-precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--workload", choices=["c1", "c2", "batch", "serve", "dense", "closed", "forms"], default="c1",
-                    help="c1: one instance per solve (the headline, n = m = 1600); c2: one instance per solve "
+    ap.add_argument("--workload", choices=["c0", "c1", "c2", "batch", "serve", "dense", "closed", "forms"],
+                    default="c1",
+                    help="c1: one instance per solve (the headline, n = m = 1600); c0: the n = m = 20 FP64 "
+                         "instance with a fixed penalty 0.1 (latency-bound); c2: one instance per solve "
                          "of the n = 600, m = 1800 family; batch: 4096 instances of the c1 family per solve on "
                          "the matrix cores; serve: continuous batching of MPC requests; dense: random dense QPs "
                          "with equality rows to eps 1e-6; closed: closed-loop MPC, fixed iterations per step; forms: compact vs the "
@@ -97,14 +102,14 @@ def measured_traffic(iters_per_solve, solves_per_launch):
     return (rec["fetch_kib_per_dispatch"] * rec["fetch_factor"] + rec["write_kib_per_dispatch"] * rec["write_factor"]) * 1024
 
 
-def _oracle_stream(prob, x0s, budget_s):
+def _oracle_stream(prob, x0s, budget_s, n_rho=8):
     """Solves of the x0 stream by the FP64 oracle (explicit-inverse layer form, same settings)
     until the budget is spent; the offline stage (the factorisation) runs first, untimed.
     Returns (solves, ADMM iterations, seconds)."""
     import oracle
     from oracle import admm
 
-    s = admm.Settings(n_rho=8)
+    s = admm.Settings(n_rho=n_rho)
     cache = {}
     q, l, u = prob.instance(x0s[0])
     oracle.solve(prob.P, q, prob.A, l, u, s, cache=cache)  # offline stage, not timed
@@ -119,7 +124,7 @@ def _oracle_stream(prob, x0s, budget_s):
     return done, iters, time.perf_counter() - t0
 
 
-def cpu_baseline(prob, x0s, budget_s):
+def cpu_baseline(prob, x0s, budget_s, n_rho=8):
     """The FP64 oracle on the host cores: the solve stream with the BLAS threads it has (the
     reported value), then the same with BLAS on one thread."""
     try:
@@ -128,7 +133,7 @@ def cpu_baseline(prob, x0s, budget_s):
         cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     except Exception:  # pragma: no cover
         threadpool_limits, cores = None, os.cpu_count()
-    done, iters, dt = _oracle_stream(prob, x0s, budget_s / 2)
+    done, iters, dt = _oracle_stream(prob, x0s, budget_s / 2, n_rho)
     out = {
         "value": done / dt,
         "unit": "solves/s",
@@ -136,12 +141,31 @@ def cpu_baseline(prob, x0s, budget_s):
         "kind": "oracle",
         "sample": f"first {done} solves of the same x0 stream (FP64 NumPy, {iters} ADMM iterations, "
                   f"{iters / dt:.0f} iters/s), offline stage excluded",
+        "host": host_cpu(),
     }
     if threadpool_limits is not None:
         with threadpool_limits(limits=1, user_api="blas"):
-            d1, i1, t1 = _oracle_stream(prob, x0s, budget_s / 2)
+            d1, i1, t1 = _oracle_stream(prob, x0s, budget_s / 2, n_rho)
         out["single_thread"] = {"value": d1 / t1, "cores": 1, "sample": f"first {d1} solves, BLAS on one thread"}
     return out
+
+
+def host_cpu():
+    """The host the CPU baseline ran on: CPU model, logical CPUs, and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = None
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
 
 
 _POOL_BARRIER = None
@@ -207,6 +231,7 @@ def cpu_baseline_pool(name, x0s, budget_s, workers=None):
         "kind": "oracle",
         "sample": f"{workers} processes, one instance at a time each, BLAS on one thread: {done} solves of the same "
                   f"x0 stream ({iters} ADMM iterations), offline stage excluded",
+        "host": host_cpu(),
     }
 
 
@@ -239,13 +264,17 @@ def main():
     x0_host = x0_batch(nx, total, 1000, scale=args.x0_scale)
     q0, l0, u0 = prob.instance(x0_host[0])
 
-    settings = dict(precision="fp32", n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000,
-                    check_interval=25)
+    small = args.workload == "c0"  # FP64 with one fixed penalty 0.1; the others FP32 over 8
+    settings = dict(precision="fp64" if small else "fp32", n_rho=1 if small else 8, rho0=0.1, sigma=1e-6,
+                    alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000, check_interval=25)
+    esize = 8 if small else 4
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
     sol = rq.Solver(prob.P, q0, prob.A, l0, u0, **settings)
     setup_ms = (time.perf_counter() - t_setup) * 1e3
     sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+    if args.grid:
+        sol.set_launch(args.grid)
     grid_wg, block = sol.launch()
 
     x0_dev = torch.tensor(x0_host, dtype=torch.float64, device=dev)  # resident before timing
@@ -277,7 +306,7 @@ def main():
     kern_ms = np.array([ev1[c].elapsed_time(ev2[c]) for c in range(nw, nl)])
     solves_per_s = args.steps / wall
     checks = -(-it // 25)
-    bytes_per_unit = (n * n + 2 * m * n) * 4
+    bytes_per_unit = (n * n + 2 * m * n) * esize
     alg_bytes = float(np.sum((it + checks) * bytes_per_unit))
     achieved_gbs = alg_bytes / (np.sum(kern_ms) * 1e-3) / 1e9
 
@@ -296,11 +325,12 @@ def main():
     step_ms = np.array(lat_ms) if lat_ms else np.array([np.nan])
 
     # fixed-iteration probe: per-iteration time of the same kernel without the stopping test
-    steady = None
-    if args.steady_iters > 0:
+    def fixed_probe(grid):
         fx = rq.Solver(prob.P, q0, prob.A, l0, u0, **dict(settings, eps_abs=0.0, eps_rel=0.0,
                                                           max_iter=args.steady_iters))
         fx.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
+        if grid:
+            fx.set_launch(grid)
         fx.update_x0_device(x0_dev[0], stream)
         fx.solve(stream)
         torch.cuda.synchronize()
@@ -312,23 +342,51 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
+        fx.close()
         ms = min(times)
         k = args.steady_iters
         nck = -(-k // 25)
-        steady = {
+        return {
             "iterations": k,
             "ms": ms,
             "us_per_iter": ms * 1e3 / k,
             "effective_GBs": (k + nck) * bytes_per_unit / (ms * 1e-3) / 1e9,
         }
-        fx.close()
+
+    steady = fixed_probe(args.grid) if args.steady_iters > 0 else None
+    sweep_arg = args.grid_sweep if args.grid_sweep is not None else ("1,2,5,10,20,40" if small else "")
+    sweep = None
+    if args.steady_iters > 0 and sweep_arg:
+        sweep = {}
+        for g in (int(v) for v in sweep_arg.split(",")):
+            print(f"fixed-iteration probe at {g} workgroups", file=sys.stderr, flush=True)
+            sweep[str(g)] = fixed_probe(g)["us_per_iter"] * 1e3
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(prob, x0_host[args.warmup:], args.cpu_seconds)
+        cpu = cpu_baseline(prob, x0_host[args.warmup:], args.cpu_seconds, settings["n_rho"])
 
     traffic_bytes = measured_traffic(float(np.mean(it)), C) if args.workload == "c1" else None
     avg_launch_s = float(np.mean(kern_ms)) * 1e-3
+    roof = {
+        "bound": "hbm",
+        "achieved": achieved_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved_gbs / HBM_PEAK_GBS,
+        # measured HBM bytes per launch (rocprofv3 counters) over the same launch duration
+        "traffic": None if traffic_bytes is None else traffic_bytes / avg_launch_s / 1e9,
+        "traffic_bytes_per_launch": traffic_bytes,
+        "kernel": ("layer_kernel<float, 4, 8, 8, false>" if args.workload == "c1"
+                   else f"layer_kernel<{'double' if small else 'float'}, ...>"),
+        "alg_bytes_per_unit": bytes_per_unit,
+        "avg_launch_us": float(np.mean(kern_ms) * 1e3),
+    }
+    if small:
+        # n = m = 20: the layer weights sit in registers and an iteration is one on-chip exchange of
+        # the 40-entry layer input, so its time is a latency, not a share of a bandwidth or a peak
+        roof.update(bound="latency", achieved=steady["us_per_iter"] * 1e3 if steady else None, peak=None,
+                    unit="ns/iteration", frac=None, hbm_equivalent_GBs=achieved_gbs)
     out = {
         "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
         "value": solves_per_s,
@@ -340,13 +398,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if small else "f32",
         "data": "synthetic",
         "config": {
             "workload": (f"random linear MPC, LQR-condensed dense QP, n={n}, m={m} "
                          f"(nx={nx}, nu={prob.nu}, N={prob.N})"),
             "x0": f"{args.x0_scale:g} * U[-1,1]^{nx}, seed 1000",
-            "penalties": "8 log-spaced 1e-3..1e3",
+            "penalties": "fixed 0.1" if small else "8 log-spaced 1e-3..1e3",
             "eps": 1e-3,
             "launch": {"grid": grid_wg, "block": block},
         },
@@ -358,19 +416,8 @@ def main():
         "solves_per_launch": C,
         "setup_ms": setup_ms,
         "steady_state": steady,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved_gbs / HBM_PEAK_GBS,
-            # measured HBM bytes per launch (rocprofv3 counters) over the same launch duration
-            "traffic": None if traffic_bytes is None else traffic_bytes / avg_launch_s / 1e9,
-            "traffic_bytes_per_launch": traffic_bytes,
-            "kernel": "layer_kernel<float, 4, 8, 8, false>",
-            "alg_bytes_per_unit": bytes_per_unit,
-            "avg_launch_us": float(np.mean(kern_ms) * 1e3),
-        },
+        "ns_per_iter_by_grid": sweep,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     sol.close()
@@ -482,6 +529,7 @@ def bench_batch(args):
         "setup_ms": setup_ms,
         "tile_autotuner": {"rows": sol.tile()[0], "us_per_iter": sol.tile()[1]},
         "steady_state": steady,
+        "ns_per_iter_by_grid": sweep,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,
@@ -600,7 +648,8 @@ def dense_cpu_baseline(settings, budget_s):
         dt += time.perf_counter() - t0
         done += 1
     return {"value": done / dt, "unit": "solves/s at n=2000", "cores": int(cores), "kind": "oracle",
-            "sample": f"{done} of the n = 2000 problems, each solved once to 1e-6 after an untimed setup"}
+            "sample": f"{done} of the n = 2000 problems, each solved once to 1e-6 after an untimed setup",
+            "host": host_cpu()}
 
 
 def bench_forms(args):

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "librelu_qp.so")
-SOURCES = ["setup_kernels.hip", "layer_kernel.hip", "batch_kernel.hip", "paper_layer.hip", "relu_qp_api.hip"]
+SOURCES = ["setup_kernels.hip", "layer_kernel.hip", "batch_kernel.hip", "paper_layer.hip", "small_kernel.hip",
+           "relu_qp_api.hip"]
 ARCH = os.environ.get("RELU_QP_ARCH", "gfx950")
 
 HIP_FLAGS = [

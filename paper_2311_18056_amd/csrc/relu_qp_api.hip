@@ -17,6 +17,7 @@
 #include "layer_kernel.h"
 #include "paper_layer.h"
 #include "setup_kernels.h"
+#include "small_kernel.h"
 
 namespace {
 
@@ -65,6 +66,7 @@ struct relu_qp_handle {
   std::vector<unsigned char> eq;
   int j0 = 0;
   int grid_wg = 0;   // workgroups of the persistent launch
+  bool small = false;  // plain solves run on the single-workgroup kernel (n + m <= kSmallRows)
   rqp::LaunchPlan plan{};    // plain solves
   rqp::LaunchPlan plan_xt{}; // closed loops and Ruiz-scaled problems
   // device
@@ -384,6 +386,7 @@ int set_grid(relu_qp_handle* h, int grid) {
   h->plan = p;
   h->plan_xt = px;
   h->grid_wg = grid;
+  h->small = false;
   return RQP_OK;
 }
 
@@ -395,7 +398,9 @@ int choose_grid(relu_qp_handle* h) {
   int g = cus < h->L ? cus : h->L;
   if (g > 256) g = 256;
   if (g < need) g = need;
-  return set_grid(h, g);
+  const int rc = set_grid(h, g);  // closed loops and scaled problems keep the persistent grid
+  if (rc == RQP_OK) h->small = h->L <= rqp::kSmallRows;
+  return rc;
 }
 
 int alloc_exchange(relu_qp_handle* h) {
@@ -1138,8 +1143,12 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
     a.final_check = 0;
   }
   const rqp::LaunchPlan& plan = (cl || h->scl) ? h->plan_xt : h->plan;
-  hipError_t e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, h->grid_wg, st)
-                               : rqp::launch_layer<float>(a, plan, h->grid_wg, st);
+  hipError_t e;
+  if (h->small && !cl && !h->scl)
+    e = h->esize == 8 ? rqp::launch_small<double>(a, st) : rqp::launch_small<float>(a, st);
+  else
+    e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, h->grid_wg, st)
+                      : rqp::launch_layer<float>(a, plan, h->grid_wg, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
   h->tag += span * (uint32_t)count;
   h->warm_pending = false;
@@ -1415,7 +1424,7 @@ int relu_qp_set_launch(relu_qp_handle* h, int grid) {
 
 int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
-  if (grid) *grid = h->batched ? h->bplan.grid : h->grid_wg;
+  if (grid) *grid = h->batched ? h->bplan.grid : (h->small ? 1 : h->grid_wg);
   if (block) *block = h->batched ? rqp::kBatchBlock : rqp::kLayerBlock;
   return RQP_OK;
 }

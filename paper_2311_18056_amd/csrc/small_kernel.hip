@@ -1,0 +1,350 @@
+// Single-workgroup ReLU-QP kernel for small problems (n + m <= 128): every iteration, check and
+// penalty switch of Algorithm 1 (online stage) in one launch of one workgroup.
+//
+// The iteration is the compact layer of the persistent kernel (Sec. III-A with OSQP
+// over-relaxation): w = [sigma x - q ; rho z - y], one product with
+// Wc_j = [D_j, D_j A'; A D_j, A D_j A'] gives xt and A xt, and the relaxation, the clamp
+// (eq. clamp) and the dual update are row-local. At these sizes an iteration is a few hundred
+// multiply-adds, so its time is set by latency, not by bandwidth: a persistent grid would spend
+// it on the cross-workgroup exchange of w. Here Wc_j lives in LDS for the whole solve (reloaded
+// when the penalty changes), w is exchanged through LDS, and one workgroup barrier per
+// iteration is the only synchronisation.
+//
+// Layout: row r of Wc_j is split over S consecutive lanes (S = 1024 / L rounded to a power of
+// two, at most 16); lane s of the row multiplies the columns c = s, s + S, ... and DPP lane
+// moves sum the S partials, leaving the row's value in all S lanes. LDS holds the matrix as
+// [column block i][row r][lane s], so the 64 lanes of a wave read 64 consecutive words.
+//
+// Every check_interval iterations (Sec. III-C) the rows of [P, A'] [x; y] are formed with FP64
+// accumulation from the check matrix in global memory (cached; read once per check), A x is the
+// product the constraint rows carry along in FP64, and the seven inf-norms are reduced as
+// ordered bit patterns (exact and NaN-propagating). The stopping test (eqs. primal, dual) and
+// the penalty rule (eq. rho_update, nearest grid value) are those of the persistent kernel.
+#include "small_kernel.h"
+
+#include "device_common.h"
+
+namespace rqp {
+namespace {
+
+constexpr int SB = kSmallBlock;
+constexpr int SWAVES = SB / kWave;
+constexpr int kRhoMax = 64;  // the host accepts at most 64 penalty values
+
+enum { S_RUNNING = 0, S_SOLVED = 1, S_MAX_ITER = 2, S_NONFINITE = 3, S_ABORTED = 4 };
+enum { K_RP = 0, K_RD, K_AX, K_Z, K_PX, K_ATY, K_Q, K_NORMS };
+
+// Lanes per row: the largest power of two S <= 16 with S * L <= 1024.
+constexpr int kMaxLanes = 16;
+__host__ __device__ inline int lanes_per_row(int L) {
+  int p = 1;
+  while (p < L) p <<= 1;
+  const int s = SB / p;
+  return s > kMaxLanes ? kMaxLanes : s;
+}
+
+// Sum over the S lanes of a row (S in 1, 2, 4, 8, 16; the lanes are consecutive and S-aligned)
+// with DPP lane moves (VALU, no LDS round trip): swaps of neighbours and of pairs within a quad,
+// then the half-row and row mirrors. Every lane of the row ends with the same sum (each step
+// adds the same two partial sums, in either order).
+template <typename T>
+__device__ __forceinline__ T row_sum(T v, int S) {
+  if (S >= 2) v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  if (S >= 4) v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  if (S >= 8) v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  if (S >= 16) v = dpp_add<0x140, 0xf>(v); // row_mirror
+  return v;
+}
+
+// Layer matrix of penalty j into LDS as [i][r][s] (column c = i S + s; zero past column L).
+template <typename T>
+__device__ void load_layer(const LayerArgs& a, int j, int S, int nI, T* Wl) {
+  const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
+  const int L = a.L, blk = L * S, tot = nI * blk;
+  for (int e = threadIdx.x; e < tot; e += SB) {
+    const int i = e / blk, rem = e - i * blk, r = rem / S, s = rem - r * S, c = i * S + s;
+    Wl[e] = c < L ? Wj[(long)r * a.ldw + c] : (T)0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  T* Wl = reinterpret_cast<T*>(dyn_lds);
+  __shared__ T wb[2][kSmallRows];   // layer input w, two parities
+  __shared__ T cv[kSmallRows];      // [x; y] for the check and z = A x of a warm start
+  __shared__ T upd[kSmallRows][2];  // q, l, u from an initial state
+  __shared__ uint64_t nrm[K_NORMS][kSmallRows];
+  __shared__ uint64_t fin[K_NORMS + 1];
+  __shared__ double grid_s[kRhoMax], mid_s[kRhoMax];
+  __shared__ int decision[2];
+
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int n = a.n, L = a.L;
+  const int S = lanes_per_row(L), nI = (L + S - 1) / S;
+  const int r = tid / S, s = tid - r * S;  // this lane's row and column lane
+  const bool row = r < L, own = row && s == 0, xrow = r < n;
+  const bool seq = row && !xrow && a.eq[r - n] != 0;
+  const T* Cm = static_cast<const T*>(a.C);
+
+  if (tid < a.n_rho) grid_s[tid] = a.grid[tid];
+  if (tid < a.n_rho - 1) mid_s[tid] = a.mid[tid];
+  // entries past L are read as columns of the zero padding; keep them finite
+  if (tid < kSmallRows && tid >= L) wb[0][tid] = wb[1][tid] = cv[tid] = (T)0;
+
+  const int ci = a.check_interval, max_iter = a.max_iter;
+  const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
+  const double alpha_d = a.alpha, oma_d = 1.0 - a.alpha;
+  // the state of row r, held by all S lanes of the row (they compute the same values)
+  T sx = 0, sz = 0, sy = 0, sq = 0, sl = 0, su = 0;
+  double ax = 0.0;
+  int j = a.warm ? *a.js : a.j0;
+  int lds_j = -1;
+
+  for (int sv = 0; sv < a.count; ++sv) {
+    const bool warm = sv == 0 ? a.warm != 0 : a.chain != 0;
+    __syncthreads();  // upd[] of the previous solve has been read
+
+    // update from an initial state (Sec. IV): q = F x0, l = lo - E x0, u = hi - E x0, FP64
+    // products, one wave per row; written back to the handle's q, l, u
+    if (a.x0) {
+      const double* x0 = a.x0 + (long)sv * a.nx;
+      for (int rr = wave; rr < L; rr += SWAVES) {
+        const double* arow = rr < n ? a.F + (long)rr * a.nx : a.E + (long)(rr - n) * a.nx;
+        double dv = 0.0;
+        for (int c = lane; c < a.nx; c += kWave) dv = fma(arow[c], x0[c], dv);
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) dv += __shfl_xor(dv, off, kWave);
+        if (lane == 0) {
+          if (rr < n) {
+            upd[rr][0] = (T)dv;
+            static_cast<T*>(const_cast<void*>(a.q))[rr] = (T)dv;
+          } else {
+            const int i = rr - n;
+            upd[rr][0] = (T)(a.plo[i] - dv);
+            upd[rr][1] = (T)(a.phi[i] - dv);
+            static_cast<T*>(const_cast<void*>(a.l))[i] = upd[rr][0];
+            static_cast<T*>(const_cast<void*>(a.u))[i] = upd[rr][1];
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // cold start (zero state, start penalty), or warm from the handle (first solve) or from the
+    // previous solve of this launch
+    if (row) {
+      if (xrow) {
+        sq = a.x0 ? upd[r][0] : static_cast<const T*>(a.q)[r];
+        if (!warm) sx = (T)0;
+        else if (sv == 0) sx = static_cast<const T*>(a.xs)[r];
+      } else {
+        const int i = r - n;
+        sl = a.x0 ? upd[r][0] : static_cast<const T*>(a.l)[i];
+        su = a.x0 ? upd[r][1] : static_cast<const T*>(a.u)[i];
+        if (!warm) sy = (T)0;
+        else if (sv == 0) sy = static_cast<const T*>(a.ys)[i];
+        ax = 0.0;
+        sz = (T)0;
+      }
+    }
+    if (!warm) j = a.j0;
+    T srho = (T)(grid_s[j] * (seq ? a.rho_eq_scale : 1.0));
+    T rinv = (T)1 / srho;  // y / rho as y * (1 / rho): one rounding more, no division per iteration
+    if (j != lds_j) {
+      load_layer<T>(a, j, S, nI, Wl);
+      lds_j = j;
+    }
+
+    // warm start (Sec. II-B): z = A x with FP64 accumulation
+    if (warm) {
+      if (own) cv[r] = xrow ? sx : sy;
+      __syncthreads();
+      double p = 0.0;
+      if (row && !xrow)
+        for (int c = s; c < n; c += S) p += (double)Cm[(long)r * a.ldw + c] * (double)cv[c];
+      p = row_sum(p, S);
+      if (row && !xrow) {
+        sz = (T)p;
+        ax = p;
+      }
+    }
+    if (own) wb[1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
+    __syncthreads();  // w_1 and the LDS layer matrix
+
+    int k = 0, nchk = 0;
+    const long hoff = (long)sv * a.max_checks;
+    while (true) {
+      const int kend = (k / ci + 1) * ci < max_iter ? (k / ci + 1) * ci : max_iter;
+      while (k < kend) {
+        ++k;
+        // layer matvec: row r of Wc_j times w_k, then the row-local update
+        const T* w = wb[k & 1];
+        T acc = (T)0;
+        if (row) {
+          const T* wr = Wl + (long)r * S + s;
+          for (int i = 0; i < nI; ++i) acc = fma(wr[(long)i * L * S], w[i * S + s], acc);
+        }
+        const T v = row_sum(acc, S);
+        if (row) {
+          if (xrow) {
+            sx = alpha * v + oma * sx;
+          } else {
+            // A x_{k+1} = alpha A xt + (1 - alpha) A x_k, with A xt the layer output v
+            ax = fma(alpha_d, (double)v, oma_d * ax);
+            const T t = alpha * v + oma * sz + sy * rinv;
+            const T zn = box_clamp(t, sl, su);
+            sy = srho * (t - zn);
+            sz = zn;
+          }
+          if (own && k < kend) wb[(k + 1) & 1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
+        }
+        __syncthreads();
+      }
+
+      // check at iteration k: rows of [P, A'] [x; y] (dual side), the carried A x (primal side)
+      if (own) cv[r] = xrow ? sx : sy;
+      __syncthreads();
+      double pr = 0.0, ar = 0.0;
+      if (row && xrow) {
+        const T* Cr = Cm + (long)r * a.ldw;
+        for (int c = s; c < L; c += S) {
+          const double v = (double)Cr[c] * (double)cv[c];
+          if (c < n)
+            pr += v;
+          else
+            ar += v;
+        }
+      }
+      pr = row_sum(pr, S);
+      ar = row_sum(ar, S);
+      if (own) {
+        if (xrow) {
+          const double qv = (double)sq;
+          nrm[K_RD][r] = abs_bits(pr + qv + ar);
+          nrm[K_PX][r] = abs_bits(pr);
+          nrm[K_ATY][r] = abs_bits(ar);
+          nrm[K_Q][r] = abs_bits(qv);
+          nrm[K_RP][r] = nrm[K_AX][r] = nrm[K_Z][r] = 0;
+        } else {
+          nrm[K_RP][r] = abs_bits(ax - (double)sz);
+          nrm[K_AX][r] = abs_bits(ax);
+          nrm[K_Z][r] = abs_bits((double)sz);
+          nrm[K_RD][r] = nrm[K_PX][r] = nrm[K_ATY][r] = nrm[K_Q][r] = 0;
+        }
+      }
+      __syncthreads();
+      // wave w < 7 reduces norm w over the rows; wave 7 reads the host's abort flag
+      if (wave < K_NORMS) {
+        uint64_t m = 0;
+        for (int rr = lane; rr < L; rr += kWave) m = nrm[wave][rr] > m ? nrm[wave][rr] : m;
+        m = wave_max_u64(m);
+        if (lane == 0) fin[wave] = m;
+      } else if (wave == K_NORMS && lane == 0) {
+        // the host-mapped flag costs a PCIe round trip, so it is read at every kAbortEvery-th
+        // check only
+        const bool ab = (nchk % kAbortEvery) == kAbortEvery - 1 && a.abort_flag &&
+                        __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        fin[K_NORMS] = ab ? 1u : 0u;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        bool nonfinite = false;
+        for (int i = 0; i < K_NORMS; ++i) nonfinite |= fin[i] >= kInfBits;
+        const double rp = bits_to_double(fin[K_RP]), rd = bits_to_double(fin[K_RD]);
+        const double nax = bits_to_double(fin[K_AX]), nz = bits_to_double(fin[K_Z]);
+        const double npx = bits_to_double(fin[K_PX]), naty = bits_to_double(fin[K_ATY]);
+        const double nq = bits_to_double(fin[K_Q]);
+        int st = S_RUNNING;
+        if (nonfinite) {
+          st = S_NONFINITE;
+        } else if (a.terminate) {
+          const double eps_p = a.eps_abs + a.eps_rel * fmax(nax, nz);
+          const double eps_d = a.eps_abs + a.eps_rel * fmax(fmax(npx, naty), nq);
+          if (rp <= eps_p && rd <= eps_d) st = S_SOLVED;
+        }
+        if (st == S_RUNNING && k == max_iter) st = S_MAX_ITER;
+        if (st == S_RUNNING && fin[K_NORMS] == 1) st = S_ABORTED;
+        int jn = j;
+        if (st == S_RUNNING && a.n_rho > 1 && rp > 0.0 && rd > 0.0) {
+          const double num = rp * fmax(fmax(npx, naty), fmax(nq, 1e-4));
+          const double den = rd * fmax(fmax(nax, nz), 1e-4);
+          const double rh = grid_s[j] * sqrt(num / den);
+          jn = 0;
+          while (jn < a.n_rho - 1 && rh > mid_s[jn]) ++jn;
+        }
+        if (a.rho_hist) a.rho_hist[hoff + nchk] = jn;
+        if (a.prim_res) a.prim_res[hoff + nchk] = rp;
+        if (a.dual_res) a.dual_res[hoff + nchk] = rd;
+        decision[0] = st;
+        decision[1] = jn;
+      }
+      __syncthreads();
+      const int st = decision[0], jn = decision[1];
+      ++nchk;
+      if (st != S_RUNNING) {
+        if (own) {
+          if (xrow) {
+            static_cast<T*>(a.xs)[r] = sx;
+            static_cast<T*>(a.xo)[(long)sv * n + r] = sx;
+          } else {
+            const int i = r - n;
+            static_cast<T*>(a.zs)[i] = sz;
+            static_cast<T*>(a.ys)[i] = sy;
+            a.axs[i] = ax;
+            static_cast<T*>(a.zo)[(long)sv * a.m + i] = sz;
+            static_cast<T*>(a.yo)[(long)sv * a.m + i] = sy;
+          }
+        }
+        if (tid == 0) {
+          a.iterations[sv] = k;
+          a.status[sv] = st;
+          a.rho_index[sv] = j;
+          *a.js = j;
+        }
+        break;  // next solve of the sequence
+      }
+      if (jn != j) {
+        j = jn;
+        srho = (T)(grid_s[j] * (seq ? a.rho_eq_scale : 1.0));
+        rinv = (T)1 / srho;
+        load_layer<T>(a, j, S, nI, Wl);  // every lane is past its last read of the old rows
+        lds_j = j;
+      }
+      if (own) wb[(k + 1) & 1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
+      __syncthreads();  // w_{k+1}, the LDS layer matrix, decision[] and fin[] reuse
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+size_t small_lds_bytes(int L) {
+  const int S = lanes_per_row(L), nI = (L + S - 1) / S;
+  return (size_t)nI * L * S * sizeof(T);
+}
+
+template <typename T>
+hipError_t launch_small(const LayerArgs& a, hipStream_t st) {
+  if (a.L < 1 || a.L > kSmallRows || a.Ad || a.sc_dual || a.n_rho > kRhoMax) return hipErrorInvalidValue;
+  const void* fn = reinterpret_cast<const void*>(&small_kernel<T>);
+  static bool attr = false;  // one per instantiation
+  const size_t dyn = small_lds_bytes<T>(a.L);
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)small_lds_bytes<T>(kSmallRows));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  LayerArgs arg = a;
+  void* args[] = {&arg};
+  return hipLaunchKernel(fn, dim3(1), dim3(SB), args, dyn, st);
+}
+
+template size_t small_lds_bytes<float>(int);
+template size_t small_lds_bytes<double>(int);
+template hipError_t launch_small<float>(const LayerArgs&, hipStream_t);
+template hipError_t launch_small<double>(const LayerArgs&, hipStream_t);
+
+}  // namespace rqp

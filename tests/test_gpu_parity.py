@@ -111,6 +111,73 @@ def test_launch_shapes_and_streamed_rows(rq, prec, grid):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid", [1, 2, 7, 40])
+def test_c0_launch_shapes(rq, c0, prec, grid):
+    """The n = m = 20 instance on one workgroup (every row its own, no exchange partner) up to
+    one row per workgroup, per iterate against the oracle with limits binding."""
+    prob, x0 = c0
+    q, l, u = prob.instance(5.0 * x0[2])
+    res = _fixed_run(rq, prob.P, q, prob.A, l, u, prec, 200, grid=grid)
+    ref = oracle.solve(prob.P, q, prob.A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=200))
+    assert res["status"] == rq.RQP_MAX_ITER and res["iterations"] == 200
+    _compare(res, ref, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(1, 0, 1), (7, 2, 5), (20, 4, 16), (60, 8, 60), (61, 8, 60)])
+def test_single_workgroup_sizes(rq, prec, shape):
+    """Problems with n + m <= 128 run on one workgroup by default (lanes per row 64 down to 8,
+    128 rows at the top, equality rows with their scaled penalty); one row more takes the
+    persistent kernel. Per iterate against the oracle with the penalty schedule replayed."""
+    n, m_eq, m_ineq = shape
+    P, q, A, l, u = random_qp(n, m_eq, m_ineq, seed=100 + n)
+    sol = rq.Solver(P, q, A, l, u, precision=prec, n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=150)
+    assert sol.launch()[0] == (1 if n + m_eq + m_ineq <= 128 else min(256, n + m_eq + m_ineq))
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    ref = oracle.solve(P, q, A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=150, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    assert res["iterations"] == 150 and res["status"] == rq.RQP_MAX_ITER
+    _compare(res, ref, TOL[prec])
+
+
+def test_single_workgroup_matches_persistent(rq, c0):
+    """The same c0 solve to eps 1e-3 in FP64 on the single-workgroup kernel and on the persistent
+    one: equal iteration counts and penalty histories, iterates within the FP64 tolerance."""
+    prob, x0 = c0
+    q, l, u = prob.instance(5.0 * x0[3])
+    out = []
+    for grid in (0, 8):
+        sol = rq.Solver(prob.P, q, prob.A, l, u, precision="fp64", n_rho=8)
+        sol.set_launch(grid)
+        assert sol.launch()[0] == (1 if grid == 0 else grid)
+        sol.solve()
+        out.append(sol.result())
+        sol.close()
+    a, b = out
+    assert a["status"] == b["status"] == rq.RQP_SOLVED
+    assert a["iterations"] == b["iterations"] and a["rho_hist"] == b["rho_hist"]
+    for name in ("x", "y", "z"):
+        _close(a[name], b[name], TOL["fp64"], name)
+
+
+def test_abort_single_workgroup(rq):
+    import time
+
+    P, q, A, l, u = random_qp(20, 4, 16, seed=6)
+    sol = rq.Solver(P, q, A, l, u, precision="fp64", eps_abs=0.0, eps_rel=0.0, max_iter=20_000_000)
+    assert sol.launch()[0] == 1
+    sol.solve()
+    time.sleep(0.05)
+    sol.abort()
+    res = sol.result()
+    sol.close()
+    assert res["status"] == rq.RQP_ABORTED
+    assert 0 < res["iterations"] < 20_000_000 and res["iterations"] % 25 == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_c0_solves_to_tolerance(rq, c0, prec):
     prob, x0 = c0
     for i in range(3):
@@ -331,16 +398,18 @@ def test_solve_sequence_matches_separate_solves(rq, c0, prec, chain):
 
 
 def test_smallest_problem_and_infinite_bounds(rq):
-    """n = m = 1 (two layer rows on two workgroups), and a problem whose bounds are all
-    infinite, where the fixed point is the closed form x = -P^-1 q."""
+    """n = m = 1 (two layer rows: the single-workgroup kernel, and the persistent one on two
+    workgroups), and a problem whose bounds are all infinite, where the fixed point is the
+    closed form x = -P^-1 q."""
     P = np.array([[2.0]])
     q = np.array([1.0])
     A = np.array([[1.0]])
     for prec in ("fp64", "fp32"):
-        res = _fixed_run(rq, P, q, A, np.array([-0.25]), np.array([0.25]), prec, 50)
-        ref = oracle.solve(P, q, A, np.array([-0.25]), np.array([0.25]),
-                           _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=50))
-        _compare(res, ref, TOL[prec])
+        for grid in (None, 2):
+            res = _fixed_run(rq, P, q, A, np.array([-0.25]), np.array([0.25]), prec, 50, grid=grid)
+            ref = oracle.solve(P, q, A, np.array([-0.25]), np.array([0.25]),
+                               _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=50))
+            _compare(res, ref, TOL[prec])
     rng = np.random.default_rng(3)
     M = rng.standard_normal((30, 30))
     P = M @ M.T / 30 + np.eye(30)
