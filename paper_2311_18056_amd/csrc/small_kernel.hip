@@ -6,17 +6,17 @@
 // Wc_j = [D_j, D_j A'; A D_j, A D_j A'] gives xt and A xt, and the relaxation, the clamp
 // (eq. clamp) and the dual update are row-local. At these sizes an iteration is a few hundred
 // multiply-adds, so its time is set by latency, not by bandwidth: a persistent grid would spend
-// it on the cross-workgroup exchange of w. Here Wc_j lives in LDS for the whole solve (reloaded
-// when the penalty changes), w is exchanged through LDS, and one workgroup barrier per
+// it on the cross-workgroup exchange of w. Here Wc_j lives in registers for the whole solve
+// (reloaded when the penalty changes), w is exchanged through LDS, and one workgroup barrier per
 // iteration is the only synchronisation.
 //
-// Layout: row r of Wc_j is split over S consecutive lanes (S = 1024 / L rounded to a power of
-// two, at most 16); lane s of the row multiplies the columns c = s, s + S, ... and DPP lane
-// moves sum the S partials, leaving the row's value in all S lanes. LDS holds the matrix as
-// [column block i][row r][lane s], so the 64 lanes of a wave read 64 consecutive words.
+// Layout: row r of Wc_j is split over S consecutive lanes (S = 16 for L <= 64, 8 for L <= 128);
+// lane s of the row holds and multiplies the columns c = s, s + S, ... (at most 16 values) and
+// DPP lane moves sum the S partials, leaving the row's value in all S lanes. Waves that hold
+// no row skip the product.
 //
 // Every check_interval iterations (Sec. III-C) the rows of [P, A'] [x; y] are formed with FP64
-// accumulation from the check matrix in global memory (cached; read once per check), A x is the
+// accumulation from the check matrix, held in LDS for the whole launch, A x is the
 // product the constraint rows carry along in FP64, and the seven inf-norms are reduced as
 // ordered bit patterns (exact and NaN-propagating). The stopping test (eqs. primal, dual) and
 // the penalty rule (eq. rho_update, nearest grid value) are those of the persistent kernel.
@@ -34,43 +34,81 @@ constexpr int kRhoMax = 64;  // the host accepts at most 64 penalty values
 enum { S_RUNNING = 0, S_SOLVED = 1, S_MAX_ITER = 2, S_NONFINITE = 3, S_ABORTED = 4 };
 enum { K_RP = 0, K_RD, K_AX, K_Z, K_PX, K_ATY, K_Q, K_NORMS };
 
-// Lanes per row: the largest power of two S <= 16 with S * L <= 1024.
-constexpr int kMaxLanes = 16;
-__host__ __device__ inline int lanes_per_row(int L) {
-  int p = 1;
-  while (p < L) p <<= 1;
-  const int s = SB / p;
-  return s > kMaxLanes ? kMaxLanes : s;
-}
+// Shapes: S lanes per row and NI column blocks (columns c = i S + s, zero past L): S = 16,
+// NI = 4 for L <= 64 (a wave holds 4 rows); S = 8 and NI = 12 or 16 for L <= 96 or 128.
+constexpr int kBatch = 4;  // loads issued together (NI is a multiple)
+__host__ __device__ constexpr int small_lanes(int L) { return L <= 64 ? 16 : 8; }
+__host__ __device__ constexpr int small_blocks(int L) { return L <= 64 ? 4 : (L <= 96 ? 12 : 16); }
 
 // Sum over the S lanes of a row (S in 1, 2, 4, 8, 16; the lanes are consecutive and S-aligned)
 // with DPP lane moves (VALU, no LDS round trip): swaps of neighbours and of pairs within a quad,
 // then the half-row and row mirrors. Every lane of the row ends with the same sum (each step
 // adds the same two partial sums, in either order).
-template <typename T>
-__device__ __forceinline__ T row_sum(T v, int S) {
-  if (S >= 2) v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
-  if (S >= 4) v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
-  if (S >= 8) v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
-  if (S >= 16) v = dpp_add<0x140, 0xf>(v); // row_mirror
+template <int S, typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  if constexpr (S >= 2) v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  if constexpr (S >= 4) v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  if constexpr (S >= 8) v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  if constexpr (S >= 16) v = dpp_add<0x140, 0xf>(v); // row_mirror
   return v;
 }
 
-// Layer matrix of penalty j into LDS as [i][r][s] (column c = i S + s; zero past column L).
-template <typename T>
-__device__ void load_layer(const LayerArgs& a, int j, int S, int nI, T* Wl) {
-  const T* Wj = static_cast<const T*>(a.W) + (long)j * a.w_stride;
-  const int L = a.L, blk = L * S, tot = nI * blk;
-  for (int e = threadIdx.x; e < tot; e += SB) {
-    const int i = e / blk, rem = e - i * blk, r = rem / S, s = rem - r * S, c = i * S + s;
-    Wl[e] = c < L ? Wj[(long)r * a.ldw + c] : (T)0;
+// This lane's entries of row r of the layer matrix of penalty j: W[r][i S + s], i < NI (zero
+// for rows or columns past L). Lanes of a row read consecutive columns.
+template <typename T, int S, int NI>
+__device__ __forceinline__ void load_row(const LayerArgs& a, int j, bool row, int r, int s, T (&wst)[NI]) {
+  const T* Wr = static_cast<const T*>(a.W) + (long)j * a.w_stride + (long)(row ? r : 0) * a.ldw;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int c = i * S + s;
+    wst[i] = (row && c < a.L) ? Wr[c] : (T)0;
   }
 }
 
-template <typename T>
+// The check matrix [P, A'; A, 0] into LDS as [i][t]: thread t = r S + s finds C[r][i S + s] at
+// i * 1024 + t (zero for rows or columns past L). Loaded once per launch.
+template <typename T, int S, int NI>
+__device__ void load_check(const LayerArgs& a, T* Cl) {
+  const T* Cm = static_cast<const T*>(a.C);
+  const int L = a.L;
+  for (int e = threadIdx.x; e < NI * SB; e += SB) {
+    const int i = e / SB, t = e - i * SB, r = t / S, c = i * S + (t - r * S);
+    Cl[e] = (r < L && c < L) ? Cm[(long)r * a.ldw + c] : (T)0;
+  }
+}
+
+// Products of this lane's part of its row of the check matrix with cv over the columns
+// c = i S + s < cend, FP64, split at column n (the P or A part and the A' part), accumulated in
+// ascending column order; columns out of range contribute zero.
+template <typename T, int S, int NI>
+__device__ __forceinline__ void check_products(const LayerArgs& a, const T* Cl, int s, int cend, const T* cv,
+                                               double& lo, double& hi) {
+  lo = 0.0;
+  hi = 0.0;
+#pragma unroll
+  for (int i0 = 0; i0 < NI; i0 += kBatch) {
+    T cval[kBatch], xval[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      cval[b] = Cl[(i0 + b) * SB + threadIdx.x];
+      xval[b] = cv[(i0 + b) * S + s];
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int c = (i0 + b) * S + s;
+      const double v = c < cend ? (double)cval[b] * (double)xval[b] : 0.0;
+      if (c < a.n)
+        lo += v;
+      else
+        hi += v;
+    }
+  }
+}
+
+template <typename T, int S, int NI>
 __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  T* Wl = reinterpret_cast<T*>(dyn_lds);
+  T* Cl = reinterpret_cast<T*>(dyn_lds);  // the check matrix, NI * 1024 entries
   __shared__ T wb[2][kSmallRows];   // layer input w, two parities
   __shared__ T cv[kSmallRows];      // [x; y] for the check and z = A x of a warm start
   __shared__ T upd[kSmallRows][2];  // q, l, u from an initial state
@@ -81,16 +119,16 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
 
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int n = a.n, L = a.L;
-  const int S = lanes_per_row(L), nI = (L + S - 1) / S;
   const int r = tid / S, s = tid - r * S;  // this lane's row and column lane
+  const bool wave_rows = wave * (kWave / S) < L;  // the wave holds at least one row
   const bool row = r < L, own = row && s == 0, xrow = r < n;
   const bool seq = row && !xrow && a.eq[r - n] != 0;
-  const T* Cm = static_cast<const T*>(a.C);
 
   if (tid < a.n_rho) grid_s[tid] = a.grid[tid];
   if (tid < a.n_rho - 1) mid_s[tid] = a.mid[tid];
   // entries past L are read as columns of the zero padding; keep them finite
   if (tid < kSmallRows && tid >= L) wb[0][tid] = wb[1][tid] = cv[tid] = (T)0;
+  load_check<T, S, NI>(a, Cl);
 
   const int ci = a.check_interval, max_iter = a.max_iter;
   const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
@@ -99,7 +137,8 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
   T sx = 0, sz = 0, sy = 0, sq = 0, sl = 0, su = 0;
   double ax = 0.0;
   int j = a.warm ? *a.js : a.j0;
-  int lds_j = -1;
+  int held_j = -1;
+  T wst[NI];  // this lane's entries of its row of the layer matrix, for penalty held_j
 
   for (int sv = 0; sv < a.count; ++sv) {
     const bool warm = sv == 0 ? a.warm != 0 : a.chain != 0;
@@ -151,26 +190,25 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
     if (!warm) j = a.j0;
     T srho = (T)(grid_s[j] * (seq ? a.rho_eq_scale : 1.0));
     T rinv = (T)1 / srho;  // y / rho as y * (1 / rho): one rounding more, no division per iteration
-    if (j != lds_j) {
-      load_layer<T>(a, j, S, nI, Wl);
-      lds_j = j;
+    if (j != held_j) {
+      load_row<T, S, NI>(a, j, row, r, s, wst);
+      held_j = j;
     }
 
     // warm start (Sec. II-B): z = A x with FP64 accumulation
     if (warm) {
       if (own) cv[r] = xrow ? sx : sy;
       __syncthreads();
-      double p = 0.0;
-      if (row && !xrow)
-        for (int c = s; c < n; c += S) p += (double)Cm[(long)r * a.ldw + c] * (double)cv[c];
-      p = row_sum(p, S);
+      double p, unused;
+      check_products<T, S, NI>(a, Cl, s, n, cv, p, unused);  // rows past L hold zeros
+      p = row_sum<S>(p);
       if (row && !xrow) {
         sz = (T)p;
         ax = p;
       }
     }
     if (own) wb[1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
-    __syncthreads();  // w_1 and the LDS layer matrix
+    __syncthreads();  // w_1
 
     int k = 0, nchk = 0;
     const long hoff = (long)sv * a.max_checks;
@@ -179,14 +217,19 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
       while (k < kend) {
         ++k;
         // layer matvec: row r of Wc_j times w_k, then the row-local update
-        const T* w = wb[k & 1];
-        T acc = (T)0;
-        if (row) {
-          const T* wr = Wl + (long)r * S + s;
-          for (int i = 0; i < nI; ++i) acc = fma(wr[(long)i * L * S], w[i * S + s], acc);
-        }
-        const T v = row_sum(acc, S);
-        if (row) {
+        if (wave_rows) {
+          const T* w = wb[k & 1];
+          T acc = (T)0;
+#pragma unroll
+          for (int i0 = 0; i0 < NI; i0 += kBatch) {
+            T xv[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) xv[b] = w[(i0 + b) * S + s];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) acc = fma(wst[i0 + b], xv[b], acc);
+          }
+          const T v = row_sum<S>(acc);
+          if (row) {
           if (xrow) {
             sx = alpha * v + oma * sx;
           } else {
@@ -197,7 +240,8 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
             sy = srho * (t - zn);
             sz = zn;
           }
-          if (own && k < kend) wb[(k + 1) & 1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
+            if (own && k < kend) wb[(k + 1) & 1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
+          }
         }
         __syncthreads();
       }
@@ -205,19 +249,10 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
       // check at iteration k: rows of [P, A'] [x; y] (dual side), the carried A x (primal side)
       if (own) cv[r] = xrow ? sx : sy;
       __syncthreads();
-      double pr = 0.0, ar = 0.0;
-      if (row && xrow) {
-        const T* Cr = Cm + (long)r * a.ldw;
-        for (int c = s; c < L; c += S) {
-          const double v = (double)Cr[c] * (double)cv[c];
-          if (c < n)
-            pr += v;
-          else
-            ar += v;
-        }
-      }
-      pr = row_sum(pr, S);
-      ar = row_sum(ar, S);
+      double pr, ar;
+      check_products<T, S, NI>(a, Cl, s, L, cv, pr, ar);
+      pr = row_sum<S>(pr);
+      ar = row_sum<S>(ar);
       if (own) {
         if (xrow) {
           const double qv = (double)sq;
@@ -308,32 +343,24 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
         j = jn;
         srho = (T)(grid_s[j] * (seq ? a.rho_eq_scale : 1.0));
         rinv = (T)1 / srho;
-        load_layer<T>(a, j, S, nI, Wl);  // every lane is past its last read of the old rows
-        lds_j = j;
+        load_row<T, S, NI>(a, j, row, r, s, wst);
+        held_j = j;
       }
       if (own) wb[(k + 1) & 1][r] = xrow ? sigma * sx - sq : srho * sz - sy;
-      __syncthreads();  // w_{k+1}, the LDS layer matrix, decision[] and fin[] reuse
+      __syncthreads();  // w_{k+1}; decision[] and fin[] are reused
     }
   }
 }
 
 }  // namespace
 
-template <typename T>
-size_t small_lds_bytes(int L) {
-  const int S = lanes_per_row(L), nI = (L + S - 1) / S;
-  return (size_t)nI * L * S * sizeof(T);
-}
-
-template <typename T>
-hipError_t launch_small(const LayerArgs& a, hipStream_t st) {
-  if (a.L < 1 || a.L > kSmallRows || a.Ad || a.sc_dual || a.n_rho > kRhoMax) return hipErrorInvalidValue;
-  const void* fn = reinterpret_cast<const void*>(&small_kernel<T>);
-  static bool attr = false;  // one per instantiation
-  const size_t dyn = small_lds_bytes<T>(a.L);
+template <typename T, int S, int NI>
+hipError_t launch_shape(const LayerArgs& a, hipStream_t st) {
+  const void* fn = reinterpret_cast<const void*>(&small_kernel<T, S, NI>);
+  const size_t dyn = (size_t)NI * SB * sizeof(T);  // at most 128 KB (FP64, NI = 16)
+  static bool attr = false;                       // one per instantiation
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)small_lds_bytes<T>(kSmallRows));
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
     attr = true;
   }
@@ -342,8 +369,14 @@ hipError_t launch_small(const LayerArgs& a, hipStream_t st) {
   return hipLaunchKernel(fn, dim3(1), dim3(SB), args, dyn, st);
 }
 
-template size_t small_lds_bytes<float>(int);
-template size_t small_lds_bytes<double>(int);
+template <typename T>
+hipError_t launch_small(const LayerArgs& a, hipStream_t st) {
+  if (a.L < 1 || a.L > kSmallRows || a.Ad || a.sc_dual || a.n_rho > kRhoMax) return hipErrorInvalidValue;
+  if (a.L <= 64) return launch_shape<T, 16, 4>(a, st);
+  if (a.L <= 96) return launch_shape<T, 8, 12>(a, st);
+  return launch_shape<T, 8, 16>(a, st);
+}
+
 template hipError_t launch_small<float>(const LayerArgs&, hipStream_t);
 template hipError_t launch_small<double>(const LayerArgs&, hipStream_t);
 
