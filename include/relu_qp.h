@@ -273,9 +273,9 @@ int relu_qp_max_checks(const relu_qp_handle* h);
 int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid /* n_rho */, int* n_rho);
 
 /* Launch shape of the single-instance solves. By default (grid 0) a problem with
- * n + m <= 128 runs its plain solves (relu_qp_solve, relu_qp_solve_x0, relu_qp_solve_sequence)
- * on one workgroup with the layer matrix in LDS, and larger problems, closed loops and scaled
- * problems run the persistent kernel on one workgroup per compute unit (at most one per row).
+ * n + m <= 128 runs its solves (relu_qp_solve, relu_qp_solve_x0, relu_qp_solve_sequence) on one
+ * workgroup with the layer matrix in registers, and larger problems and closed loops run the
+ * persistent kernel on one workgroup per compute unit (at most one per row).
  * A grid > 0 makes every solve use the persistent kernel on that many workgroups; it must lie
  * in [ceil((n+m)/64), min(n+m, the cooperative limit)]. relu_qp_get_launch reports the grid of
  * plain solves (1 for the single-workgroup kernel) and the workgroup size. */

@@ -398,7 +398,7 @@ int choose_grid(relu_qp_handle* h) {
   int g = cus < h->L ? cus : h->L;
   if (g > 256) g = 256;
   if (g < need) g = need;
-  const int rc = set_grid(h, g);  // closed loops and scaled problems keep the persistent grid
+  const int rc = set_grid(h, g);  // closed loops keep the persistent grid
   if (rc == RQP_OK) h->small = h->L <= rqp::kSmallRows;
   return rc;
 }
@@ -1144,7 +1144,7 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
   }
   const rqp::LaunchPlan& plan = (cl || h->scl) ? h->plan_xt : h->plan;
   hipError_t e;
-  if (h->small && !cl && !h->scl)
+  if (h->small && !cl)
     e = h->esize == 8 ? rqp::launch_small<double>(a, st) : rqp::launch_small<float>(a, st);
   else
     e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, h->grid_wg, st)

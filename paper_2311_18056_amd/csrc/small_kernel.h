@@ -13,8 +13,8 @@ namespace rqp {
 constexpr int kSmallRows = 128;
 constexpr int kSmallBlock = 1024;
 
-// Runs the solves described by `a` (plain solves and sequences; no closed loop, no scaling:
-// a.Ad and a.sc_dual must be null) as one workgroup.
+// Runs the solves described by `a` (plain solves and sequences, Ruiz-scaled or not; no closed
+// loop: a.Ad must be null) as one workgroup.
 template <typename T>
 hipError_t launch_small(const LayerArgs& a, hipStream_t st);
 

@@ -254,17 +254,20 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
       pr = row_sum<S>(pr);
       ar = row_sum<S>(ar);
       if (own) {
+        // a Ruiz-scaled problem weights each row's terms so that the norms are the original
+        // problem's: 1 / (c D_r) on the dual side, 1 / E_i on the primal side (1 otherwise)
         if (xrow) {
-          const double qv = (double)sq;
-          nrm[K_RD][r] = abs_bits(pr + qv + ar);
-          nrm[K_PX][r] = abs_bits(pr);
-          nrm[K_ATY][r] = abs_bits(ar);
-          nrm[K_Q][r] = abs_bits(qv);
+          const double qv = (double)sq, f = a.sc_dual ? a.sc_dual[r] : 1.0;
+          nrm[K_RD][r] = abs_bits(f * (pr + qv + ar));
+          nrm[K_PX][r] = abs_bits(f * pr);
+          nrm[K_ATY][r] = abs_bits(f * ar);
+          nrm[K_Q][r] = abs_bits(f * qv);
           nrm[K_RP][r] = nrm[K_AX][r] = nrm[K_Z][r] = 0;
         } else {
-          nrm[K_RP][r] = abs_bits(ax - (double)sz);
-          nrm[K_AX][r] = abs_bits(ax);
-          nrm[K_Z][r] = abs_bits((double)sz);
+          const double e = a.sc_prim ? a.sc_prim[r - n] : 1.0;
+          nrm[K_RP][r] = abs_bits(e * (ax - (double)sz));
+          nrm[K_AX][r] = abs_bits(e * ax);
+          nrm[K_Z][r] = abs_bits(e * (double)sz);
           nrm[K_RD][r] = nrm[K_PX][r] = nrm[K_ATY][r] = nrm[K_Q][r] = 0;
         }
       }
@@ -319,16 +322,17 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
       ++nchk;
       if (st != S_RUNNING) {
         if (own) {
+          // the handle keeps the (scaled) iterates; the outputs are in original units
           if (xrow) {
             static_cast<T*>(a.xs)[r] = sx;
-            static_cast<T*>(a.xo)[(long)sv * n + r] = sx;
+            static_cast<T*>(a.xo)[(long)sv * n + r] = a.un_x ? (T)(a.un_x[r] * (double)sx) : sx;
           } else {
             const int i = r - n;
             static_cast<T*>(a.zs)[i] = sz;
             static_cast<T*>(a.ys)[i] = sy;
             a.axs[i] = ax;
-            static_cast<T*>(a.zo)[(long)sv * a.m + i] = sz;
-            static_cast<T*>(a.yo)[(long)sv * a.m + i] = sy;
+            static_cast<T*>(a.zo)[(long)sv * a.m + i] = a.sc_prim ? (T)(a.sc_prim[i] * (double)sz) : sz;
+            static_cast<T*>(a.yo)[(long)sv * a.m + i] = a.un_y ? (T)(a.un_y[i] * (double)sy) : sy;
           }
         }
         if (tid == 0) {
@@ -371,7 +375,7 @@ hipError_t launch_shape(const LayerArgs& a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_small(const LayerArgs& a, hipStream_t st) {
-  if (a.L < 1 || a.L > kSmallRows || a.Ad || a.sc_dual || a.n_rho > kRhoMax) return hipErrorInvalidValue;
+  if (a.L < 1 || a.L > kSmallRows || a.Ad || a.n_rho > kRhoMax) return hipErrorInvalidValue;
   if (a.L <= 64) return launch_shape<T, 16, 4>(a, st);
   if (a.L <= 96) return launch_shape<T, 8, 12>(a, st);
   return launch_shape<T, 8, 16>(a, st);

@@ -37,16 +37,19 @@ def _close(a, b, tol, what):
     assert err <= tol * scale, f"{what}: |diff|={err:.3e} > {tol:.1e} * {scale:.3e}"
 
 
-def _badly_scaled(seed):
-    P, q, A, l, u = random_qp(120, 20, 40, seed=seed)
-    S = np.diag(10.0 ** np.random.default_rng(seed).uniform(-1.5, 1.5, 120))
+def _badly_scaled(seed, n=120, m_eq=20, m_ineq=40):
+    P, q, A, l, u = random_qp(n, m_eq, m_ineq, seed=seed)
+    S = np.diag(10.0 ** np.random.default_rng(seed).uniform(-1.5, 1.5, n))
     return S @ P @ S, S @ q, A @ S, l, u
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_scaled_per_iterate(rq, prec):
-    P, q, A, l, u = _badly_scaled(31)
+@pytest.mark.parametrize("shape", [(120, 20, 40), (30, 6, 20), (60, 10, 50)])
+def test_scaled_per_iterate(rq, prec, shape):
+    """n + m = 180 (persistent kernel), 56 and 120 (single-workgroup kernel, both lane shapes)."""
+    P, q, A, l, u = _badly_scaled(31, *shape)
     sol = rq.Solver(P, q, A, l, u, precision=prec, n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=200, scaling=10)
+    assert (sol.launch()[0] == 1) == (sum(shape) <= 128)
     sol.solve()
     r = sol.result()
     sol.close()
