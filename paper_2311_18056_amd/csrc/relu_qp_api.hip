@@ -399,8 +399,11 @@ int choose_grid(relu_qp_handle* h) {
   if (g > 256) g = 256;
   if (g < need) g = need;
   const int rc = set_grid(h, g);  // closed loops keep the persistent grid
-  if (rc == RQP_OK) h->small = h->L <= rqp::kSmallRows;
-  return rc;
+  if (rc != RQP_OK || h->L > rqp::kSmallRows) return rc;
+  const hipError_t e = h->esize == 8 ? rqp::prepare_small<double>(h->L) : rqp::prepare_small<float>(h->L);
+  if (e != hipSuccess) return fail(RQP_EHIP, "single-workgroup kernel: %s", hipGetErrorString(e));
+  h->small = true;
+  return RQP_OK;
 }
 
 int alloc_exchange(relu_qp_handle* h) {

@@ -13,6 +13,11 @@ namespace rqp {
 constexpr int kSmallRows = 128;
 constexpr int kSmallBlock = 1024;
 
+// Sets the kernel's LDS limit for L = n + m rows on the current device (once per handle, at
+// setup, before the first launch_small).
+template <typename T>
+hipError_t prepare_small(int L);
+
 // Runs the solves described by `a` (plain solves and sequences, Ruiz-scaled or not; no closed
 // loop: a.Ad must be null) as one workgroup.
 template <typename T>

@@ -356,21 +356,36 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
   }
 }
 
-}  // namespace
+template <typename T, int S, int NI>
+const void* shape_fn() {
+  return reinterpret_cast<const void*>(&small_kernel<T, S, NI>);
+}
+template <typename T, int S, int NI>
+constexpr size_t shape_lds() {
+  return (size_t)NI * SB * sizeof(T);  // the check matrix: at most 128 KB (FP64, NI = 16)
+}
+
+template <typename T, int S, int NI>
+hipError_t prepare_shape() {
+  return hipFuncSetAttribute(shape_fn<T, S, NI>(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)shape_lds<T, S, NI>());
+}
 
 template <typename T, int S, int NI>
 hipError_t launch_shape(const LayerArgs& a, hipStream_t st) {
-  const void* fn = reinterpret_cast<const void*>(&small_kernel<T, S, NI>);
-  const size_t dyn = (size_t)NI * SB * sizeof(T);  // at most 128 KB (FP64, NI = 16)
-  static bool attr = false;                       // one per instantiation
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   LayerArgs arg = a;
   void* args[] = {&arg};
-  return hipLaunchKernel(fn, dim3(1), dim3(SB), args, dyn, st);
+  return hipLaunchKernel(shape_fn<T, S, NI>(), dim3(1), dim3(SB), args, shape_lds<T, S, NI>(), st);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t prepare_small(int L) {
+  if (L < 1 || L > kSmallRows) return hipErrorInvalidValue;
+  if (L <= 64) return prepare_shape<T, 16, 4>();
+  if (L <= 96) return prepare_shape<T, 8, 12>();
+  return prepare_shape<T, 8, 16>();
 }
 
 template <typename T>
@@ -381,6 +396,8 @@ hipError_t launch_small(const LayerArgs& a, hipStream_t st) {
   return launch_shape<T, 8, 16>(a, st);
 }
 
+template hipError_t prepare_small<float>(int);
+template hipError_t prepare_small<double>(int);
 template hipError_t launch_small<float>(const LayerArgs&, hipStream_t);
 template hipError_t launch_small<double>(const LayerArgs&, hipStream_t);
 
