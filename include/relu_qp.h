@@ -146,9 +146,10 @@ int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int 
  * z = A x (the receding-horizon use of Sec. V-B). 0 (the default): cold starts. */
 int relu_qp_set_warm(relu_qp_handle* h, int enabled);
 
-/* Online loop of Algorithm 1, asynchronously on stream: one persistent kernel launch runs
- * every iteration, check and penalty switch. Results go to out (caller-owned device buffers);
- * read them after a stream synchronisation. */
+/* Online loop of Algorithm 1, asynchronously on stream: one kernel launch (the persistent grid,
+ * or one workgroup when n + m <= 128; see relu_qp_set_launch) runs every iteration, check and
+ * penalty switch. Results go to out (caller-owned device buffers); read them after a stream
+ * synchronisation. */
 int relu_qp_solve(relu_qp_handle* h, void* stream, relu_qp_result* out);
 
 /* relu_qp_update_x0_device followed by relu_qp_solve, in one launch for the single-instance
