@@ -113,8 +113,9 @@ def test_launch_shapes_and_streamed_rows(rq, prec, grid):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("grid", [1, 2, 7, 40])
 def test_c0_launch_shapes(rq, c0, prec, grid):
-    """The n = m = 20 instance on one workgroup (every row its own, no exchange partner) up to
-    one row per workgroup, per iterate against the oracle with limits binding."""
+    """The n = m = 20 instance on the persistent kernel (an explicit grid selects it), from one
+    workgroup (every row its own, no exchange partner) up to one row per workgroup, per iterate
+    against the oracle with limits binding."""
     prob, x0 = c0
     q, l, u = prob.instance(5.0 * x0[2])
     res = _fixed_run(rq, prob.P, q, prob.A, l, u, prec, 200, grid=grid)
