@@ -275,8 +275,10 @@ int relu_qp_get_rho_grid(const relu_qp_handle* h, double* grid /* n_rho */, int*
 
 /* Launch shape of the single-instance solves. By default (grid 0) a problem with
  * n + m <= 128 runs its solves (relu_qp_solve, relu_qp_solve_x0, relu_qp_solve_sequence) on one
- * workgroup with the layer matrix in registers, and larger problems and closed loops run the
- * persistent kernel on one workgroup per compute unit (at most one per row).
+ * workgroup with the layer matrix in registers; larger problems run the persistent kernel on
+ * about one workgroup per 12.5 rows (fewer when a workgroup holds fewer rows on chip, at most
+ * one per compute unit), and closed loops and Ruiz-scaled problems on one workgroup per compute
+ * unit (at most one per row).
  * A grid > 0 makes every solve use the persistent kernel on that many workgroups; it must lie
  * in [ceil((n+m)/64), min(n+m, the cooperative limit)]. relu_qp_get_launch reports the grid of
  * plain solves (1 for the single-workgroup kernel) and the workgroup size. */

@@ -65,7 +65,8 @@ struct relu_qp_handle {
   std::vector<double> grid, mid;
   std::vector<unsigned char> eq;
   int j0 = 0;
-  int grid_wg = 0;   // workgroups of the persistent launch
+  int grid_wg = 0;     // workgroups of the persistent launch (closed loops, scaled problems)
+  int grid_plain = 0;  // workgroups of the persistent launch of plain solves
   bool small = false;  // plain solves run on the single-workgroup kernel (n + m <= kSmallRows)
   rqp::LaunchPlan plan{};    // plain solves
   rqp::LaunchPlan plan_xt{}; // closed loops and Ruiz-scaled problems
@@ -386,9 +387,14 @@ int set_grid(relu_qp_handle* h, int grid) {
   h->plan = p;
   h->plan_xt = px;
   h->grid_wg = grid;
+  h->grid_plain = grid;
   h->small = false;
   return RQP_OK;
 }
+
+// Rows per workgroup that plain solves aim at: few workgroups (exchange participants), but never
+// more rows than a workgroup holds on chip (measured best at 2400 and 3200 rows in FP32).
+constexpr double kPlainRowsPerGroup = 12.5;
 
 int choose_grid(relu_qp_handle* h) {
   int cus = 0, dev = 0;
@@ -398,8 +404,22 @@ int choose_grid(relu_qp_handle* h) {
   int g = cus < h->L ? cus : h->L;
   if (g > 256) g = 256;
   if (g < need) g = need;
-  const int rc = set_grid(h, g);  // closed loops keep the persistent grid
-  if (rc != RQP_OK || h->L > rqp::kSmallRows) return rc;
+  const int rc = set_grid(h, g);  // closed loops and scaled problems: one workgroup per CU
+  if (rc != RQP_OK) return rc;
+  // plain solves: about kPlainRowsPerGroup rows per workgroup, at most the rows the kernel keeps
+  // on chip (registers + LDS), and at most the grid above
+  const double on_chip = (double)(h->plan.reg_rows + h->plan.lds_rows);
+  int gp = (int)std::ceil(h->L / std::min(kPlainRowsPerGroup, on_chip));
+  if (gp > g) gp = g;
+  if (gp < need) gp = need;
+  if (gp != g) {
+    const rqp::LaunchPlan p = make_plan(h, gp, false);
+    if (p.fn && gp <= p.max_grid) {
+      h->plan = p;
+      h->grid_plain = gp;
+    }
+  }
+  if (h->L > rqp::kSmallRows) return RQP_OK;
   const hipError_t e = h->esize == 8 ? rqp::prepare_small<double>(h->L) : rqp::prepare_small<float>(h->L);
   if (e != hipSuccess) return fail(RQP_EHIP, "single-workgroup kernel: %s", hipGetErrorString(e));
   h->small = true;
@@ -1145,13 +1165,14 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
     a.chain = 1;
     a.final_check = 0;
   }
-  const rqp::LaunchPlan& plan = (cl || h->scl) ? h->plan_xt : h->plan;
+  const bool xt = cl || h->scl;
+  const rqp::LaunchPlan& plan = xt ? h->plan_xt : h->plan;
+  const int grid = xt ? h->grid_wg : h->grid_plain;
   hipError_t e;
   if (h->small && !cl)
     e = h->esize == 8 ? rqp::launch_small<double>(a, st) : rqp::launch_small<float>(a, st);
   else
-    e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, h->grid_wg, st)
-                      : rqp::launch_layer<float>(a, plan, h->grid_wg, st);
+    e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, grid, st) : rqp::launch_layer<float>(a, plan, grid, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
   h->tag += span * (uint32_t)count;
   h->warm_pending = false;
@@ -1427,7 +1448,7 @@ int relu_qp_set_launch(relu_qp_handle* h, int grid) {
 
 int relu_qp_get_launch(const relu_qp_handle* h, int* grid, int* block) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
-  if (grid) *grid = h->batched ? h->bplan.grid : (h->small ? 1 : h->grid_wg);
+  if (grid) *grid = h->batched ? h->bplan.grid : (h->small ? 1 : h->grid_plain);
   if (block) *block = h->batched ? rqp::kBatchBlock : rqp::kLayerBlock;
   return RQP_OK;
 }

@@ -133,7 +133,8 @@ def test_single_workgroup_sizes(rq, prec, shape):
     n, m_eq, m_ineq = shape
     P, q, A, l, u = random_qp(n, m_eq, m_ineq, seed=100 + n)
     sol = rq.Solver(P, q, A, l, u, precision=prec, n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=150)
-    assert sol.launch()[0] == (1 if n + m_eq + m_ineq <= 128 else min(256, n + m_eq + m_ineq))
+    L = n + m_eq + m_ineq
+    assert sol.launch()[0] == (1 if L <= 128 else -(-L * 2 // 25))  # ceil(L / 12.5) above 128
     sol.solve()
     res = sol.result()
     sol.close()
@@ -284,14 +285,14 @@ def test_parametric_update_matches_oracle(rq, c0):
 def test_launch_shape_limits(rq):
     P, q, A, l, u = random_qp(120, 20, 40, seed=11)
     sol = rq.Solver(P, q, A, l, u, precision="fp32")
-    assert sol.launch() == (180, 1024)  # one row per workgroup when n + m < 256
+    assert sol.launch() == (15, 1024)  # plain solves: ceil(180 / 12.5) workgroups by default
     for bad in (1, 2, 181):  # at most 64 rows per workgroup, at least one row each
         with pytest.raises(rq.ReluQPError):
             sol.set_launch(bad)
     sol.set_launch(3)
     assert sol.launch()[0] == 3
     sol.set_launch(0)
-    assert sol.launch()[0] == 180
+    assert sol.launch()[0] == 15
     sol.close()
 
 
