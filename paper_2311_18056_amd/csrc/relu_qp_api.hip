@@ -374,8 +374,8 @@ rqp::LaunchPlan make_plan(const relu_qp_handle* h, int grid, bool xt) {
   return h->esize == 8 ? rqp::plan_layer<double>(h->L, grid, xt) : rqp::plan_layer<float>(h->L, grid, xt);
 }
 
-// Launch shape: one workgroup per compute unit (at most one per row), at most kMaxRows rows
-// per workgroup.
+// An explicit launch shape for every persistent launch of the handle: at least one row and at
+// most kMaxRows rows per workgroup, within the cooperative limit.
 int set_grid(relu_qp_handle* h, int grid) {
   const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
   const int top = h->L < 256 ? h->L : 256;  // the check gathers at most 8 * 256 norm partials
