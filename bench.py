@@ -9,15 +9,22 @@ max 4000 iterations, check every 25. Synthetic, seeded inputs (no dataset).
 
 One step = one QP solve of the whole online path: the update of q, l, u from a new initial
 state x0, then all iterations, residual checks and penalty switches until eps = 1e-3. Steps run
-in persistent launches of --chunk solves each (relu_qp_solve_sequence: every solve reads its
-own x0 and writes its own results; the layer weights stay on chip between the solves of a
-launch). The x0 of every step are resident in HBM before the timed region starts. A separate
-probe times one solve per launch (relu_qp_solve_x0) for the per-solve latency.
+in persistent launches of at most --chunk solves each (relu_qp_solve_sequence: every solve reads
+its own x0 and writes its own results; the layer weights stay on chip between the solves of a
+launch); the last launch of the warm-up and of the timed region holds the remainder. The x0 of
+every step are resident in HBM before the timed region starts. A separate probe times one solve
+per launch (relu_qp_solve_x0) for the per-solve latency.
 
 Prints one JSON line. `roofline` covers the persistent layer kernel: algorithmic bytes per
 launch = sum over its solves of (iterations + checks) * (n^2 + 2 m n) * 4 B, over its average
 launch duration from HIP events recorded on the solve stream around each launch in the timed
-region.
+region. The weights stay on chip, so this is an effective rate; `roofline.traffic` is the
+HBM rate the rocprofv3 counters saw for the same kernel sources (named file, else null).
+
+With the headline workload the same line carries, under `variants`: the same family with
+x0 scaled by 20 (limits bind, penalties switch), the batched matrix-core engine on 4096
+instances of the family in BF16x3 and in FP32, and a short served-vs-plain latency run over the
+four serving families.
 """
 
 from __future__ import annotations
@@ -36,6 +43,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3}  # dense bf16 / fp32 matrix-core peaks
+METRIC = "QP solves/sec + ADMM iters/sec at eps=1e-3; p50/p99 solve latency, served vs plain"
 
 
 def parse():
@@ -47,7 +55,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steady-iters", type=int, default=4000, help="iterations of the fixed-iteration probe")
-    ap.add_argument("--chunk", type=int, default=100, help="solves per persistent launch (steps %% chunk == 0)")
+    ap.add_argument("--chunk", type=int, default=100,
+                    help="solves per persistent launch (the last launch holds the remainder)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="c1: leave out the x0 x 20, batched and served-vs-plain sub-records")
+    ap.add_argument("--variant-steps", type=int, default=10, help="batched variants: timed steps (4096 solves each)")
+    ap.add_argument("--variant-rates", default="300,3000", help="served-vs-plain variant: request rates per second")
+    ap.add_argument("--variant-duration", type=float, default=2.0, help="served-vs-plain variant: seconds per rate")
     ap.add_argument("--grid", type=int, default=0, help="c0/c1/c2: workgroups per launch (0 = the library's choice)")
     ap.add_argument("--grid-sweep", default=None,
                     help="c0/c1/c2: workgroup counts for extra fixed-iteration probes (default: c0 1,2,5,10,20,40)")
@@ -80,26 +94,32 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_FILE = os.path.join("profiles", "layer_kernel_c1_n1600_traffic.json")
+
+
 def measured_traffic(iters_per_solve, solves_per_launch):
     """HBM bytes per launch of the layer kernel from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the counters read for a plain copy),
-    or None when the kernel sources changed since the counters were taken or the solves ran a
-    different number of iterations."""
+    and where they came from; (None, reason) when the kernel sources changed since the counters
+    were taken or no record has this launch shape (solves per launch, iterations per solve)."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "layer_kernel_c1_n1600_traffic.json")
+    path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
-        return None
+        return None, "no counter record"
     with open(path) as f:
         rec = json.load(f)
     h = hashlib.sha256()
     for src in rec["sources"]:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    if (h.hexdigest()[:16] != rec["source_sha256_16"] or abs(iters_per_solve - rec["iterations_per_solve"]) > 1e-9
-            or solves_per_launch != rec["solves_per_dispatch"]):
-        return None
-    return (rec["fetch_kib_per_dispatch"] * rec["fetch_factor"] + rec["write_kib_per_dispatch"] * rec["write_factor"]) * 1024
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None, f"{TRAFFIC_FILE}: kernel sources changed since the counters were taken"
+    for d in rec["dispatches"]:
+        if abs(iters_per_solve - d["iterations_per_solve"]) <= 1e-9 and solves_per_launch == d["solves_per_dispatch"]:
+            b = (d["fetch_kib_per_dispatch"] * rec["fetch_factor"] + d["write_kib_per_dispatch"] * rec["write_factor"])
+            return b * 1024, f"{TRAFFIC_FILE} (sources sha256 {rec['source_sha256_16']}, rocprofv3 --pmc)"
+    return None, f"{TRAFFIC_FILE}: no record for {solves_per_launch} solves per launch"
 
 
 def _oracle_stream(prob, x0s, budget_s, n_rho=8):
@@ -235,22 +255,58 @@ def cpu_baseline_pool(name, x0s, budget_s, workers=None):
     }
 
 
+def plan_launches(count: int, chunk: int) -> list:
+    """Sizes of the persistent launches that run `count` solves, at most `chunk` each (the last
+    holds the remainder); empty for count 0."""
+    if count < 0 or chunk < 1:
+        raise ValueError("count must be >= 0 and chunk >= 1")
+    return [min(chunk, count - s) for s in range(0, count, chunk)]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        raise SystemExit("--steps must be >= 1 and --warmup >= 0")
     if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "serve":
-        return bench_serve(args)
-    if args.workload == "dense":
+        out = bench_batch(args, args.steps, args.warmup, args.precision, args.x0_scale, not args.no_cpu_baseline)
+    elif args.workload == "serve":
+        out = bench_serve(args, args.rates, args.duration, args.slots)
+    elif args.workload == "dense":
         return bench_dense(args)
-    if args.workload == "closed":
+    elif args.workload == "closed":
         return bench_closed(args)
-    if args.workload == "forms":
+    elif args.workload == "forms":
         return bench_forms(args)
+    else:
+        out = bench_single(args, args.workload, args.x0_scale, args.steps, args.warmup, probes=True)
+        if args.workload == "c1" and not args.no_variants:
+            out["variants"] = variants(args)
+    print(json.dumps(out), flush=True)
 
+
+def variants(args):
+    """Sub-records of the headline line, each with its own workload: limits binding (x0 x 20),
+    the batched engine on 4096 instances (BF16x3 and FP32), served vs plain latency."""
+    v = {}
+    print("variant: c1, x0 x 20", file=sys.stderr, flush=True)
+    v["c1_x0x20"] = bench_single(args, "c1", 20.0, min(args.steps, 500), min(args.warmup, 50), probes=False,
+                                 latency_solves=100)
+    for prec in ("bf16x3", "fp32"):
+        print(f"variant: batched, {prec}", file=sys.stderr, flush=True)
+        v[f"batched_{prec}"] = bench_batch(args, args.variant_steps, 2, prec, 1.0, False, steady_iters=0)
+    bf, fp = v["batched_bf16x3"], v["batched_fp32"]
+    v["batched_bf16x3_over_fp32"] = bf["value"] / fp["value"]
+    print("variant: served vs plain", file=sys.stderr, flush=True)
+    v["served_vs_plain"] = bench_serve(args, args.variant_rates, args.variant_duration, 128)
+    return v
+
+
+def bench_single(args, workload, x0_scale, steps, warmup, probes=True, latency_solves=None):
+    """One instance per solve (c0, c1, c2): `steps` timed solves of a fresh x0 each, in
+    persistent sequence launches; returns the JSON record."""
     import torch
 
     import paper_2311_18056_amd as rq
@@ -258,13 +314,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    prob = make_config(args.workload)
+    prob = make_config(workload)
     n, m, nx = prob.n, prob.m, prob.nx
-    total = args.warmup + args.steps
-    x0_host = x0_batch(nx, total, 1000, scale=args.x0_scale)
+    total = warmup + steps
+    x0_host = x0_batch(nx, total, 1000, scale=x0_scale)
     q0, l0, u0 = prob.instance(x0_host[0])
 
-    small = args.workload == "c0"  # FP64 with one fixed penalty 0.1; the others FP32 over 8
+    small = workload == "c0"  # FP64 with one fixed penalty 0.1; the others FP32 over 8
     settings = dict(precision="fp64" if small else "fp32", n_rho=1 if small else 8, rho0=0.1, sigma=1e-6,
                     alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000, check_interval=25)
     esize = 8 if small else 4
@@ -279,17 +335,17 @@ def main():
 
     x0_dev = torch.tensor(x0_host, dtype=torch.float64, device=dev)  # resident before timing
     stream = torch.cuda.current_stream()
-    C = max(1, args.chunk)
-    if args.steps % C or args.warmup % C:
-        raise SystemExit("--steps and --warmup must be multiples of --chunk")
-    nl, nw = total // C, args.warmup // C
-    outs = [sol.sequence_slots(C) for _ in range(nl)]
+    sizes_w, sizes_t = plan_launches(warmup, args.chunk), plan_launches(steps, args.chunk)
+    sizes = sizes_w + sizes_t
+    starts = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
+    nl, nw = len(sizes), len(sizes_w)
+    outs = [sol.sequence_slots(c) for c in sizes]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
     ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(nl)]
 
     def launch(c):
         ev1[c].record(stream)
-        sol.solve_sequence(x0_dev[c * C:(c + 1) * C], stream, out=outs[c])
+        sol.solve_sequence(x0_dev[starts[c]:starts[c + 1]], stream, out=outs[c])
         ev2[c].record(stream)
 
     for c in range(nw):
@@ -304,7 +360,7 @@ def main():
     it = torch.cat([o["iterations"] for o in outs[nw:]]).cpu().numpy().astype(np.int64)
     st = torch.cat([o["status"] for o in outs[nw:]]).cpu().numpy()
     kern_ms = np.array([ev1[c].elapsed_time(ev2[c]) for c in range(nw, nl)])
-    solves_per_s = args.steps / wall
+    solves_per_s = steps / wall
     checks = -(-it // 25)
     bytes_per_unit = (n * n + 2 * m * n) * esize
     alg_bytes = float(np.sum((it + checks) * bytes_per_unit))
@@ -312,10 +368,11 @@ def main():
 
     # per-solve latency: one solve per launch, arrival of x0 (in HBM) to results written
     lat_ms = []
-    if args.latency_solves > 0:
+    n_lat = args.latency_solves if latency_solves is None else latency_solves
+    if n_lat > 0:
         slots1, res1 = sol.result_slots(1)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for i in range(args.latency_solves + 10):
+        for i in range(n_lat + 10):
             e0.record(stream)
             sol.solve_x0(x0_dev[i % total], stream, out=res1[0])
             e1.record(stream)
@@ -353,20 +410,22 @@ def main():
             "effective_GBs": (k + nck) * bytes_per_unit / (ms * 1e-3) / 1e9,
         }
 
-    steady = fixed_probe(args.grid) if args.steady_iters > 0 else None
+    steady = fixed_probe(args.grid) if probes and args.steady_iters > 0 else None
     sweep_arg = args.grid_sweep if args.grid_sweep is not None else ("1,2,5,10,20,40" if small else "")
     sweep = None
-    if args.steady_iters > 0 and sweep_arg:
+    if probes and args.steady_iters > 0 and sweep_arg:
         sweep = {}
         for g in (int(v) for v in sweep_arg.split(",")):
             print(f"fixed-iteration probe at {g} workgroups", file=sys.stderr, flush=True)
             sweep[str(g)] = fixed_probe(g)["us_per_iter"] * 1e3
 
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(prob, x0_host[args.warmup:], args.cpu_seconds, settings["n_rho"])
+    if probes and not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, x0_host[warmup:], args.cpu_seconds, settings["n_rho"])
 
-    traffic_bytes = measured_traffic(float(np.mean(it)), C) if args.workload == "c1" else None
+    traffic_bytes, traffic_src = None, None
+    if workload == "c1":
+        traffic_bytes, traffic_src = measured_traffic(float(np.mean(it)), sizes_t[0] if len(set(sizes_t)) == 1 else -1)
     avg_launch_s = float(np.mean(kern_ms)) * 1e-3
     roof = {
         "bound": "hbm",
@@ -374,27 +433,34 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved_gbs / HBM_PEAK_GBS,
+        "frac_kind": "effective: algorithmic bytes of the two-GEMV form over the launch time; the weights stay "
+                     "on chip, so the kernel is bound by its per-iteration exchange latency, not by HBM",
         # measured HBM bytes per launch (rocprofv3 counters) over the same launch duration
         "traffic": None if traffic_bytes is None else traffic_bytes / avg_launch_s / 1e9,
+        "traffic_frac_of_peak": None if traffic_bytes is None else traffic_bytes / avg_launch_s / 1e9 / HBM_PEAK_GBS,
         "traffic_bytes_per_launch": traffic_bytes,
-        "kernel": ("layer_kernel<float, 4, 8, 8, false>" if args.workload == "c1"
+        "traffic_source": traffic_src,
+        "kernel": ("layer_kernel<float, 4, 8, 8, false>" if workload == "c1"
                    else f"layer_kernel<{'double' if small else 'float'}, ...>"),
         "alg_bytes_per_unit": bytes_per_unit,
         "avg_launch_us": float(np.mean(kern_ms) * 1e3),
+        "solves_per_launch": sizes_t,
     }
+    if steady:
+        roof["us_per_iter_fixed"] = steady["us_per_iter"]
     if small:
         # n = m = 20: the layer weights sit in registers and an iteration is one on-chip exchange of
         # the 40-entry layer input, so its time is a latency, not a share of a bandwidth or a peak
         roof.update(bound="latency", achieved=steady["us_per_iter"] * 1e3 if steady else None, peak=None,
                     unit="ns/iteration", frac=None, hbm_equivalent_GBs=achieved_gbs)
     out = {
-        "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
+        "metric": METRIC,
         "value": solves_per_s,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -402,18 +468,18 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"random linear MPC, LQR-condensed dense QP, n={n}, m={m} "
-                         f"(nx={nx}, nu={prob.nu}, N={prob.N})"),
-            "x0": f"{args.x0_scale:g} * U[-1,1]^{nx}, seed 1000",
+                         f"(nx={nx}, nu={prob.nu}, N={prob.N}), one instance per solve"),
+            "x0": f"{x0_scale:g} * U[-1,1]^{nx}, seed 1000",
             "penalties": "fixed 0.1" if small else "8 log-spaced 1e-3..1e3",
             "eps": 1e-3,
+            "step": "one solve: q, l, u from a new x0, iterations and checks to eps",
             "launch": {"grid": grid_wg, "block": block},
         },
         "admm_iters_per_s": float(np.sum(it)) / wall,
         "iters_per_solve": float(np.mean(it)),
         "status_counts": {rq.STATUS_NAMES[int(s)]: int(np.sum(st == s)) for s in np.unique(st)},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
-                       "note": "one solve per launch, events around the launch"},
-        "solves_per_launch": C,
+                       "note": "plain: one solve per launch, events around the launch"},
         "setup_ms": setup_ms,
         "steady_state": steady,
         "ns_per_iter_by_grid": sweep,
@@ -421,13 +487,13 @@ def main():
         "cpu_baseline": cpu,
     }
     sol.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_batch(args):
+def bench_batch(args, steps, warmup, precision, x0_scale, with_cpu, steady_iters=None):
     """B instances of the configuration-1 family (same P and A, x0 per instance) per solve on
     the batched matrix-core engine. One step = device update of every instance's q, l, u plus
-    one persistent solve of all of them to eps = 1e-3."""
+    one persistent solve of all of them to eps = 1e-3. Returns the JSON record."""
     import torch
 
     import paper_2311_18056_amd as rq
@@ -437,12 +503,12 @@ def bench_batch(args):
     torch.cuda.set_device(dev)
     prob = make_config("c1")
     n, m, nx, B = prob.n, prob.m, prob.nx, args.batch
-    steps, warmup = args.steps, args.warmup
     total = steps + warmup
+    steady_iters = args.steady_iters if steady_iters is None else steady_iters
     # instance i of step s: x0 from seed 3_000_000 + s (B rows)
-    x0_host = np.stack([x0_batch(nx, B, 3_000_000 + s, scale=args.x0_scale) for s in range(total)])
+    x0_host = np.stack([x0_batch(nx, B, 3_000_000 + s, scale=x0_scale) for s in range(total)])
     q0, l0, u0 = prob.instance(x0_host[0])
-    settings = dict(precision=args.precision, engine="batch", n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3,
+    settings = dict(precision=precision, engine="batch", n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3,
                     eps_rel=1e-3, max_iter=4000, check_interval=25)
     t_setup = time.perf_counter()
     sol = rq.Solver(prob.P, q0, prob.A, l0, u0, **settings)
@@ -479,11 +545,11 @@ def bench_batch(args):
     flops_per_unit = 2.0 * (n * n + 2 * m * n)  # useful flops per instance-iteration
     alg_flops = float(np.sum((it + checks) * flops_per_unit))
     achieved = alg_flops / (np.sum(kern_ms) * 1e-3) / 1e12
-    peak = MFMA_PEAK_TFLOPS[args.precision]
+    peak = MFMA_PEAK_TFLOPS[precision]
 
     steady = None
-    if args.steady_iters > 0:
-        k = min(args.steady_iters, 200)
+    if steady_iters > 0:
+        k = min(steady_iters, 200)
         fx = rq.Solver(prob.P, q0, prob.A, l0, u0, **dict(settings, eps_abs=0.0, eps_rel=0.0, max_iter=k))
         fx.set_tile(sol.tile()[0])  # the shape the timed solves ran with
         fx.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
@@ -502,7 +568,7 @@ def bench_batch(args):
         fx.close()
 
     out = {
-        "metric": "QP solves/sec at eps=1e-3 (with ADMM iters/sec and p50/p99 solve latency)",
+        "metric": METRIC,
         "value": B * steps / wall,
         "unit": "solves/s",
         "n_gpus": 1,
@@ -512,14 +578,15 @@ def bench_batch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3" if args.precision == "bf16x3" else "f32",
+        "dtype": "bf16x3" if precision == "bf16x3" else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"{B} instances per solve of the n=1600, m=1600 MPC family (nx=120, nu=40, N=40), "
                         "batched matrix-core engine",
-            "x0": f"{args.x0_scale:g} * U[-1,1]^120, seed 3000000 + step",
+            "x0": f"{x0_scale:g} * U[-1,1]^120, seed 3000000 + step",
             "penalties": "8 log-spaced 1e-3..1e3",
             "eps": 1e-3,
+            "step": f"q, l, u of {B} instances from new x0, one persistent solve of all of them to eps",
         },
         "admm_iters_per_s": float(np.sum(it)) / wall,
         "iters_per_solve": float(np.mean(it)),
@@ -529,7 +596,6 @@ def bench_batch(args):
         "setup_ms": setup_ms,
         "tile_autotuner": {"rows": sol.tile()[0], "us_per_iter": sol.tile()[1]},
         "steady_state": steady,
-        "ns_per_iter_by_grid": sweep,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,
@@ -537,15 +603,15 @@ def bench_batch(args):
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": None,
-            "kernel": f"batch_kernel<{1 if args.precision == 'bf16x3' else 0}, {sol.tile()[0]}>",
+            "kernel": f"batch_kernel<{1 if precision == 'bf16x3' else 0}, {sol.tile()[0]}>",
             "alg_flops_per_unit": flops_per_unit,
             "avg_launch_us": float(np.mean(kern_ms) * 1e3),
         },
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_pool("c1", x0_host[warmup:].reshape(-1, nx),
-                                                                            args.cpu_seconds),
+        "cpu_baseline": cpu_baseline_pool("c1", x0_host[warmup:].reshape(-1, nx), args.cpu_seconds) if with_cpu
+        else None,
     }
     sol.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def dense_sizes(count: int = 10):
@@ -767,9 +833,10 @@ def bench_closed(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(args):
+def bench_serve(args, rates, duration, slots):
     """Open-loop Poisson requests over four MPC families, served by continuous batching vs one
-    at a time on the single-instance engine; p50/p99 latency per offered rate."""
+    at a time on the single-instance engine; p50/p99 latency per offered rate. Returns the
+    JSON record."""
     import torch
 
     from paper_2311_18056_amd import Solver
@@ -781,7 +848,7 @@ def bench_serve(args):
     gens = [lambda rng, p=p: args.x0_scale * rng.uniform(-1.0, 1.0, p.nx) for p in probs]
     settings = dict(n_rho=8, sigma=1e-6, alpha=1.6, eps_abs=1e-3, eps_rel=1e-3, max_iter=4000, check_interval=25)
     budget = int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib > 0 else None
-    fams = [Family.from_mpc(p, slots=args.slots, precision=args.precision, lazy=budget is not None,
+    fams = [Family.from_mpc(p, slots=slots, precision=args.precision, lazy=budget is not None,
                             **settings).attach_single(p, **settings) for p in probs]
     singles = []
     for p in probs:
@@ -790,30 +857,31 @@ def bench_serve(args):
         s.set_parametric(p.F, p.E, p.lo, p.hi)
         singles.append(s)
     rows = []
-    for i, rate in enumerate(float(r) for r in args.rates.split(",")):
-        count = int(min(20000, rate * args.duration))
-        reqs = poisson_requests(rate, count, args.duration, gens, seed=4 + i)
+    for i, rate in enumerate(float(r) for r in rates.split(",")):
+        count = int(min(20000, rate * duration))
+        reqs = poisson_requests(rate, count, duration, gens, seed=4 + i)
         for f in fams:
             f.pin = None
         warm_s = 0.1 * max(r.t_arrival for r in reqs)  # arrivals in the first 10 % are warm-up
         srv = Server(fams, n_checks=1, warm=True, hbm_budget=budget)
-        srv.run(reqs, time_limit=args.duration * 3)
+        srv.run(reqs, time_limit=duration * 3)
         served = latency_summary(reqs, warmup=warm_s)
         mem = srv.memory
         served["memory"] = {"budget_gib": None if budget is None else budget / 2**30,
                             "peak_resident_gib": mem.peak / 2**30, "loads": mem.loads, "evictions": mem.evictions}
-        reqs = poisson_requests(rate, count, args.duration, gens, seed=4 + i)
-        serve_plain(singles, reqs, time_limit=args.duration * 3)
+        reqs = poisson_requests(rate, count, duration, gens, seed=4 + i)
+        serve_plain(singles, reqs, time_limit=duration * 3)
         plain = latency_summary(reqs, warmup=warm_s)
         rows.append({"rate": rate, "served": served, "plain": plain})
-        print(json.dumps(rows[-1]), flush=True)
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     out = {
         "metric": "p50/p99 solve latency, served vs plain",
         "unit": "ms",
         "n_gpus": 1,
         "data": "synthetic",
         "config": {"workload": "MPC families " + args.families + ", Poisson arrivals, family uniform",
-                   "slots_per_family": args.slots, "precision": args.precision, "x0_scale": args.x0_scale,
+                   "seconds_per_rate": duration,
+                   "slots_per_family": slots, "precision": args.precision, "x0_scale": args.x0_scale,
                    "family_gib": {name: f.bytes / 2**30 for name, f in zip(args.families.split(","), fams)}},
         "rates": rows,
     }
@@ -821,7 +889,7 @@ def bench_serve(args):
         f.close()
     for s in singles:
         s.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

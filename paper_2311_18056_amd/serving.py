@@ -99,8 +99,8 @@ class Family:
 
     def _load_single(self):
         prob, settings = self.spec["prob"], self.spec["single"]
-        q, l, u = prob.instance(np.zeros(prob.nx))
-        s = Solver(prob.P, q, prob.A, l, u, precision="fp32", engine="single", **settings)
+        # placeholder vectors (every request brings its own x0): q = 0, the limits' constant part
+        s = Solver(prob.P, np.zeros(prob.n), prob.A, prob.lo, prob.hi, precision="fp32", engine="single", **settings)
         s.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
         self.single = s
 
