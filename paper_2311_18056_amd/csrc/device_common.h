@@ -58,6 +58,12 @@ __device__ __forceinline__ uint64_t abs_bits(double v) {
 }
 __device__ __forceinline__ double bits_to_double(uint64_t b) { return __longlong_as_double((long long)b); }
 constexpr uint64_t kInfBits = 0x7ff0000000000000ull;
+
+// Lower bound of a norm term from its computed value v >= 0 and rounding bound d (NaN stays).
+__device__ __forceinline__ double lower_bound(double v, double d) {
+  const double w = v - d;
+  return w > 0.0 ? w : (w != w ? w : 0.0);
+}
 // the host's abort flag is polled at every kAbortEvery-th check of a launch
 constexpr int kAbortEvery = 16;
 

@@ -86,6 +86,38 @@ constexpr int kMaxGrid = 256;
 constexpr int kLayerBlock = 1024;
 constexpr int kMaxRows = 64;
 
+// Split of the residual check over the workgroups. The check reads n L entries of [P, A'] for
+// the x rows (dual side) and n m of [A, 0] for the constraint rows (primal side); each
+// workgroup forms the constraint rows it owns in the layer (rows split evenly, L / G each), and
+// the x rows are split so that every workgroup reads about (n L + n m) / G entries in all.
+// split_term(h) is the x-row work (in entries) before workgroup h under that rule; the first x
+// row of workgroup g is floor(max_{h <= g} split_term(h) / L), at most n (a running maximum
+// keeps the split monotone; g = G gives n). The quotients are formed in double: exact for
+// these magnitudes (every product is an integer below 2^53, and a non-integer quotient lies at
+// least 1/L from an integer), so host and device agree.
+__host__ __device__ inline double split_term(int h, int G, int n, int m, int L) {
+  const double total = (double)n * (double)L + (double)n * (double)m;
+  const double f = floor((double)h * total / (double)G);
+  const int rbase = L / G, rextra = L % G;
+  const double r0h = (double)h * rbase + (h < rextra ? h : rextra);
+  const double v = f - (double)n * (r0h > n ? r0h - n : 0.0);
+  return v > 0.0 ? v : 0.0;
+}
+__host__ __device__ inline int split_row(double best, int n, int L) {
+  const double cb = floor(best / (double)L);
+  return cb < (double)n ? (int)cb : n;
+}
+inline int check_split(int g, int G, int n, int m, int L) {
+  double best = 0.0;
+  for (int h = 1; h <= g; ++h) {
+    const double f = split_term(h, G, n, m, L);
+    best = f > best ? f : best;
+  }
+  return split_row(best, n, L);
+}
+// The largest share of x rows the split gives a workgroup: at most ceil(L / G) + 1.
+constexpr int kMaxCheckRows = kMaxRows + 2;
+
 // Kernel choice and resources for a problem with L = n + m rows on `grid` workgroups: the
 // first reg_rows rows of each block stay in registers and the next lds_rows in LDS for the
 // whole solve; further rows stream from memory every iteration.

@@ -205,70 +205,140 @@ struct Cols {
 template <typename T>
 struct RowState {
   T sx, sz, sy, sq;
-  double ax;  // constraint rows: (A x)_i of the current x, carried along the iteration
+  double ax;  // constraint rows, closed loops and scaled problems: (A x)_i carried along
   int R;
   bool own, xrow;
 };
 
-// Rows of [P, A'; A, 0] [x; y] for the block, FP64 accumulation. Returns, for the owner
-// thread, the product with the x part (P x or A x) in p_out and with the y part (A'y) in a_out.
+// Four consecutive entries of a row of the check matrix (16-byte aligned: ldw is a multiple
+// of 4) and of the staged check vector.
+__device__ __forceinline__ void load_quad(const float* p, float (&v)[4]) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  v[0] = t.x;
+  v[1] = t.y;
+  v[2] = t.z;
+  v[3] = t.w;
+}
+__device__ __forceinline__ void load_quad(const double* p, double (&v)[4]) {
+  const double2 t0 = *reinterpret_cast<const double2*>(p), t1 = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = t0.x;
+  v[1] = t0.y;
+  v[2] = t1.x;
+  v[3] = t1.y;
+}
+
+// Quads of a chunk of the check vector each lane of a wave takes (4 FP32 or 2 FP64 quads: 16
+// registers of loads in flight; more raise the kernel's register pressure enough to spill
+// loop-invariant values of the iteration loop), and the columns of the vector staged in LDS at a
+// time (4 KB).
+template <typename T>
+constexpr int check_quads() {
+  return sizeof(T) == sizeof(float) ? 4 : 2;
+}
+template <typename T>
+constexpr int check_chunk() {
+  return 4 * kWave * check_quads<T>();
+}
+
+// The rows of the residual check: dual rows cb .. cb + nck - 1 (x rows of [P, A'], all L
+// columns) and primal rows pb .. pb + np - 1 (constraint rows, [A, 0]: the first n columns),
+// times [x; y] (cv: this lane's gathered columns tid + BS k). The vector goes through LDS in
+// chunks of check_chunk() columns; each wave takes whole rows (rows w, w + NWAVE, ... of the
+// combined list) and each lane check_quads() quads of the chunk, all loaded at once with
+// 16-byte loads, so the wave has a whole row chunk in flight and reduces only over itself.
+// Row i of the list (dual rows first) leaves in res[i]: the product with the x part (P x, or
+// A x) and with the y part (A'y; zero for a primal row), both with FP64 accumulation of the
+// exact FP64 products, and (FP32 only) the sum of the absolute values of the products,
+// accumulated in FP32 (it only enters the rounding bound). Every thread of the workgroup must
+// call it.
 template <typename T, int NC>
-__device__ __forceinline__ void check_rows(const LayerArgs& a, int r0, int nrows, Cols<T, NC> cv, double& p_out,
-                                        double& a_out) {
-  __shared__ double redd[NWAVE][2 * kMaxRows];
+__device__ __forceinline__ void check_rows(const LayerArgs& a, int cb, int nck, int pb, int np,
+                                           const Cols<T, NC>& cv, double (*res)[3]) {
+  constexpr bool F32 = sizeof(T) == sizeof(float);
+  constexpr int QL = check_quads<T>(), CH = check_chunk<T>();
+  __shared__ __align__(16) T stage[CH];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int n = a.n, L = a.L;
   const long ldw = a.ldw;
   const T* Cm = static_cast<const T*>(a.C);
-  constexpr int RC = 16 / NC > 0 ? 16 / NC : 1;  // rows of the check matrix loaded together
-  for (int rr = 0; rr < nrows; rr += RC) {
-    // branch-free loads (masked entries read a valid address and are zeroed afterwards), so
-    // that all RC * NC loads are in flight together
-    T cr[RC][NC];
+  const int rows = nck + np;
+  for (int i = tid; i < 3 * rows; i += BS) res[i / 3][i % 3] = 0.0;
+  for (int c0 = 0; c0 < L; c0 += CH) {
+    __syncthreads();  // the previous chunk has been read (and res cleared)
 #pragma unroll
-    for (int b = 0; b < RC; ++b) {
-      const int Rr = r0 + rr + b;
-      const bool rv = rr + b < nrows;
-#pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int c = tid + BS * k;
-        const bool ld = rv && c < L && (Rr < n || c < n);
-        cr[b][k] = Cm[ld ? (long)Rr * ldw + c : 0];
-      }
+    for (int k = 0; k < NC; ++k) {
+      const int c = tid + BS * k;
+      if (c >= c0 && c < c0 + CH) stage[c - c0] = c < L ? cv.v[k] : (T)0;
     }
+    // columns of the chunk past L are staged as zero
+    if (c0 + CH > L)
+      for (int c = L - c0 + tid; c < CH; c += BS) stage[c] = (T)0;
+    __syncthreads();
+    for (int i = wave; i < rows; i += NWAVE) {
+      const bool dual = i < nck;
+      const int R = dual ? cb + i : pb + (i - nck);
+      const int cl = dual ? L : n;  // columns of this row in the check
+      if (c0 >= cl) continue;
+      const T* row = Cm + (long)R * ldw + c0;
+      T w[QL][4];
 #pragma unroll
-    for (int b = 0; b < RC; ++b) {
-      const int Rr = r0 + rr + b;
-      const bool rv = rr + b < nrows;
+      for (int u = 0; u < QL; ++u) {
+        const int cq = 4 * (lane + kWave * u);
+        if (c0 + cq < cl) {
+          load_quad(row + cq, w[u]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[u][e] = (T)0;
+        }
+      }
       double p = 0.0, q2 = 0.0;
+      float fa = 0.0f;
 #pragma unroll
-      for (int k = 0; k < NC; ++k) {
-        const int c = tid + BS * k;
-        const bool ld = rv && c < L && (Rr < n || c < n);
-        const double v = ld ? (double)cr[b][k] * (double)cv.v[k] : 0.0;
-        if (c < n)
-          p += v;
-        else
-          q2 += v;
+      for (int u = 0; u < QL; ++u) {
+        const int cq = 4 * (lane + kWave * u);
+        T v[4];
+        load_quad(stage + cq, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = c0 + cq + e;
+          const double prod = c < cl ? (double)w[u][e] * (double)v[e] : 0.0;
+          if (c < n)
+            p += prod;
+          else
+            q2 += prod;
+          if constexpr (F32) fa += c < cl ? fabsf(w[u][e] * v[e]) : 0.0f;
+        }
       }
       p = wave_sum_to_last(p);
       q2 = wave_sum_to_last(q2);
-      if (lane == kLastLane && rv) {
-        redd[wave][2 * (rr + b)] = p;
-        redd[wave][2 * (rr + b) + 1] = q2;
+      if constexpr (F32) fa = wave_sum_to_last(fa);
+      if (lane == kLastLane) {
+        res[i][0] += p;
+        res[i][1] += q2;
+        res[i][2] += (double)fa;
       }
     }
   }
   __syncthreads();
-  p_out = 0.0;
-  a_out = 0.0;
-  if (tid < nrows) {
-    for (int w = 0; w < NWAVE; ++w) {
-      p_out += redd[w][2 * tid];
-      a_out += redd[w][2 * tid + 1];
-    }
+}
+
+// Bound factor of the check in FP32: with the stored matrices and the returned x, z, y rounded
+// to FP32 (unit roundoff u = 2^-24), the products exact in FP64 and FP64 accumulation over at
+// most L terms here and in the CPU's evaluation, |computed - FP64 value| <= kappa0 * sum |a v|
+// per row with kappa0 = 2u + 2 (L + 8) 2^-53; the sum of absolute values is itself accumulated
+// in FP32 (relative error below 1e-3 for L <= 8192), hence the factor 1.02. FP64 handles
+// compute the FP64 residual itself (0).
+template <typename T>
+__device__ __forceinline__ double check_kappa(int L) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    return 0.0;
+  } else {
+    return 1.02 * (2.0 * 0x1p-24 + 2.0 * (double)(L + 8) * 0x1p-53);
   }
-  __syncthreads();
+}
+template <typename T>
+__device__ __forceinline__ double unit_roundoff() {
+  return sizeof(T) == sizeof(double) ? 0.0 : 1.01 * 0x1p-24;
 }
 
 struct CheckOut {
@@ -278,19 +348,27 @@ struct CheckOut {
 };
 
 // Residual check (eqs. primal, dual), stopping test and penalty rule (eq. rho_update; nearest
-// grid value, Sec. III-C) at iteration k, check number nchk. Every workgroup returns the same
-// result.
+// grid value, Sec. III-C) at iteration k, check number nchk, in two halves so that the caller
+// can reload its register rows while the norms are exchanged. Every workgroup takes the same
+// decision.
+//
+// check_partials: [x; y] to every workgroup; dual side: this workgroup's share of the x rows of
+// [P, A'] [x; y]; primal side: A x for the constraint rows it owns, formed afresh from the
+// check matrix (FP64 accumulation); the seven partial inf-norms published. With the iteration
+// in FP32 the published r_p and r_d are upper bounds, and ||Ax||, ||z||, ||Px||, ||A'y||,
+// ||q|| lower bounds, of the FP64 values a CPU evaluation of the returned x, z, y with the
+// caller's FP64 P, q, A gives (check_kappa), so SOLVED implies that the FP64 test passes. The
+// owner of a constraint row gets its fresh (A x)_i in ax_out. Returns false if an exchange
+// timed out.
 template <typename T, int NC, bool XT>
-__device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable& rt, RowState<T> rs, int cb,
-                                              int nck, const T* cq, int k, int nchk, int j, uint32_t tag,
-                                              long hoff) {
+__device__ __forceinline__ bool check_partials(const LayerArgs& a, const RowState<T>& rs, int r0, int nrows,
+                                               int cb, int nck, const T* cq, int k, int nchk, uint32_t tag,
+                                               double (*res)[3], double& ax_out) {
   __shared__ uint64_t nred[NWAVE][8];
-  __shared__ uint64_t nfin[8];
   constexpr int NW = LLWords<T>::kWords;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
   const int L = a.L;
-  CheckOut out{ST_RUNNING, j, true};
 
   // [x; y] to every workgroup
   const uint32_t ctag = tag + (uint32_t)k;
@@ -298,29 +376,32 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
   if (rs.own) ll_store(xc + (long)rs.R * NW, rs.xrow ? rs.sx : rs.sy, ctag);
   Cols<T, NC> cv;
   const bool ok2 = gather<T, NC>(xc, L, ctag, cv.v, a.err, tag);
-  if (__syncthreads_or(!ok2)) {
-    out.ok = false;
-    return out;
-  }
-  // dual side: rows cb .. cb + nck - 1 of [P, A'] [x; y] (this workgroup's even share of the x
-  // rows, whatever rows it owns in the layer), FP64 accumulation
-  double pr, ar;
-  check_rows<T, NC>(a, cb, nck, cv, pr, ar);
+  if (__syncthreads_or(!ok2)) return false;
+  const double kappa = check_kappa<T>(L), ut = unit_roundoff<T>();
   uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
+  // dual side: rows cb .. cb + nck - 1 of [P, A'] [x; y]; primal side: the constraint rows
+  // this workgroup owns, [A, 0] [x; y]
+  const int pb = r0 > a.n ? r0 : a.n;
+  const int np = r0 + nrows > pb ? r0 + nrows - pb : 0;
+  check_rows<T, NC>(a, cb, nck, pb, np, cv, res);
   if (tid < nck) {
-    const double qv = (double)cq[tid];
+    const double pr = res[tid][0], ar = res[tid][1], d = kappa * res[tid][2];
+    const double qv = (double)cq[tid], dq = ut * fabs(qv);
     const double f = XT && a.sc_dual ? a.sc_dual[cb + tid] : 1.0;  // original units
-    nb[N_RD] = abs_bits(f * (pr + qv + ar));
-    nb[N_PX] = abs_bits(f * pr);
-    nb[N_ATY] = abs_bits(f * ar);
-    nb[N_Q] = abs_bits(f * qv);
+    nb[N_RD] = abs_bits(f * (fabs(pr + qv + ar) + d + dq));
+    nb[N_PX] = abs_bits(f * lower_bound(fabs(pr), d));
+    nb[N_ATY] = abs_bits(f * lower_bound(fabs(ar), d));
+    nb[N_Q] = abs_bits(f * lower_bound(fabs(qv), dq));
   }
-  // primal side: A x is carried by the constraint-row owners (no product needed)
   if (rs.own && !rs.xrow) {
+    const int i = nck + rs.R - pb;
+    const double s = res[i][0], ds = kappa * res[i][2];
+    const double zv = (double)rs.sz, dz = ut * fabs(zv);
     const double e = XT && a.sc_prim ? a.sc_prim[rs.R - a.n] : 1.0;
-    nb[N_RP] = abs_bits(e * (rs.ax - (double)rs.sz));
-    nb[N_AX] = abs_bits(e * rs.ax);
-    nb[N_Z] = abs_bits(e * (double)rs.sz);
+    nb[N_RP] = abs_bits(e * (fabs(s - zv) + ds + dz));
+    nb[N_AX] = abs_bits(e * lower_bound(fabs(s), ds));
+    nb[N_Z] = abs_bits(e * lower_bound(fabs(zv), dz));
+    ax_out = s;
   }
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
@@ -341,7 +422,20 @@ __device__ __forceinline__ CheckOut run_check(const LayerArgs& a, const RhoTable
     }
     ll_store_bits64(a.xn + ((long)(nchk & 1) * G * 8 + (long)g * 8 + tid) * 2, v, ctag);
   }
-  __syncthreads();
+  return true;
+}
+
+// check_decide: every workgroup reads all partial norms, evaluates the stopping test and the
+// penalty rule, and records the check (workgroup 0).
+template <typename T>
+__device__ __forceinline__ CheckOut check_decide(const LayerArgs& a, const RhoTable& rt, int k, int nchk, int j,
+                                                 uint32_t tag, long hoff) {
+  __shared__ uint64_t nred[NWAVE][8];
+  __shared__ uint64_t nfin[8];
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid % kWave, wave = tid / kWave;
+  const uint32_t ctag = tag + (uint32_t)k;
+  CheckOut out{ST_RUNNING, j, true};
   uint64_t mx;
   const bool ok3 = gather_norms(a.xn + (long)(nchk & 1) * G * 8 * 2, G * 8, ctag, mx, a.err, tag);
   // lanes with equal tid % 8 hold the same norm index
@@ -484,7 +578,7 @@ __device__ __forceinline__ void load_lds_rows(const LayerArgs& a, int j, int r0,
 }
 
 // NRS rows of each block in registers, NLM in LDS, the rest streamed. The loop between two
-// checks is kept free of everything the check needs, and the register rows are reloaded after
+// checks is kept free of everything the check needs, and the register rows are reloaded at
 // every check, so the check code does not compete with them for registers.
 template <typename T, int NC, int NRS, int NLM, bool XT>
 __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
@@ -530,8 +624,39 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   int lds_j = -1;  // penalty index of the rows now in LDS
   __shared__ T upd[kMaxRows][2];
   // this workgroup's share of the x rows for the dual side of the check, and their q
-  const int cb = (int)((long)g * n / G), nck = (int)((long)(g + 1) * n / G) - cb;
-  __shared__ T cq[kMaxRows];
+  // (split_term, split_row: a running maximum over h <= g, here a prefix maximum over wave 0,
+  // lane l holding h = 4 l + 1 .. 4 l + 4; the grid has at most 256 workgroups)
+  __shared__ int split[2];
+  if (wave == 0) {
+    double run = 0.0, mh[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int h = 4 * lane + i + 1;
+      const double f = h <= G ? split_term(h, G, n, a.m, L) : 0.0;
+      run = f > run ? f : run;
+      mh[i] = run;
+    }
+    double inc = run;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const double o = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc = o > inc ? o : inc;
+    }
+    double exc = __shfl_up(inc, 1, kWave);
+    if (lane == 0) exc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int h = 4 * lane + i + 1;
+      const double best = exc > mh[i] ? exc : mh[i];
+      if (h == g) split[0] = split_row(best, n, L);
+      if (h == g + 1) split[1] = split_row(best, n, L);
+    }
+    if (g == 0 && lane == 0) split[0] = 0;
+  }
+  __syncthreads();
+  const int cb = split[0], nck = split[1] - split[0];
+  __shared__ T cq[kMaxCheckRows];
+  __shared__ double cres[kMaxCheckRows + kMaxRows][3];  // check_rows results: dual, then primal rows
   // closed loop: (E x_s)_i of the owned constraint rows; the applied control
   __shared__ double exs[kMaxRows];
   __shared__ double ucur[kMaxPlant];
@@ -633,11 +758,12 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         finish<T, XT>(a, rs, sv, 0, ST_INTERNAL, j, tag, exs);
         return;
       }
-      double ax, unused;
-      check_rows<T, NC>(a, r0, nrows, cv, ax, unused);
+      // the constraint rows of the block: [A, 0] [x; y]
+      const int pb = r0 > n ? r0 : n;
+      check_rows<T, NC>(a, 0, 0, pb, r0 + nrows > pb ? r0 + nrows - pb : 0, cv, cres);
       if (rs.own && !rs.xrow) {
-        rs.sz = (T)ax;
-        rs.ax = ax;
+        rs.ax = cres[rs.R - pb][0];
+        rs.sz = (T)rs.ax;
       }
     }
 
@@ -648,6 +774,8 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       if (rs.own) ll_store(a.xw + ((long)L + rs.R) * NW, w1, tag + 1u);
     }
 
+    // the register rows of the active penalty (reloaded at every check while the norms are
+    // exchanged, so that the check's own work does not compete with them for registers)
     int k = 0;
     while (true) {
       const int kend = (k / ci + 1) * ci < max_iter ? (k / ci + 1) * ci : max_iter;
@@ -655,7 +783,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         T wst[NRS][NC];
         load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
         const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
-        const double alpha_d = a.alpha, oma_d = 1.0 - a.alpha;
+        [[maybe_unused]] const double alpha_d = a.alpha, oma_d = 1.0 - a.alpha;
         uint64_t* xw = a.xw;
         while (k < kend) {
           ++k;
@@ -706,8 +834,9 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
             if (rs.xrow) {
               rs.sx = alpha * v + oma * rs.sx;
             } else {
-              // A x_{k+1} = alpha A x~ + (1 - alpha) A x_k, with A x~ the layer output v
-              rs.ax = fma(alpha_d, (double)v, oma_d * rs.ax);
+              // closed loops, scaled problems: A x_{k+1} = alpha A x~ + (1 - alpha) A x_k, with
+              // A x~ the layer output v (the z = A x of a warm start that continues this solve)
+              if constexpr (XT) rs.ax = fma(alpha_d, (double)v, oma_d * rs.ax);
               const T t = alpha * v + oma * rs.sz + rs.sy / srho;
               const T zn = box_clamp(t, sl, su);
               rs.sy = srho * (t - zn);
@@ -734,7 +863,10 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
 
       // check at iteration k (every check_interval iterations and at max_iter)
       __syncthreads();
-      const CheckOut co = run_check<T, NC, XT>(a, rt, rs, cb, nck, cq, k, nchk, j, tag, (long)sv * a.max_checks);
+      CheckOut co{ST_RUNNING, j, false};
+      if (check_partials<T, NC, XT>(a, rs, r0, nrows, cb, nck, cq, k, nchk, tag, cres, rs.ax)) {
+        co = check_decide<T>(a, rt, k, nchk, j, tag, (long)sv * a.max_checks);
+      }
       ++nchk;
       if (!co.ok) {
         if (tid == 0) err_raise(a.err, tag);

@@ -374,12 +374,25 @@ rqp::LaunchPlan make_plan(const relu_qp_handle* h, int grid, bool xt) {
   return h->esize == 8 ? rqp::plan_layer<double>(h->L, grid, xt) : rqp::plan_layer<float>(h->L, grid, xt);
 }
 
+// Every workgroup's share of the check's x rows fits the kernel's buffers (kMaxCheckRows; true
+// whenever a workgroup owns at most kMaxRows layer rows, checked once per grid).
+bool check_split_fits(int n, int m, int grid) {
+  int prev = rqp::check_split(0, grid, n, m, n + m);
+  for (int g = 1; g <= grid; ++g) {
+    const int next = rqp::check_split(g, grid, n, m, n + m);
+    if (next < prev || next - prev > rqp::kMaxCheckRows) return false;
+    prev = next;
+  }
+  return prev == n;
+}
+
 // An explicit launch shape for every persistent launch of the handle: at least one row and at
 // most kMaxRows rows per workgroup, within the cooperative limit.
 int set_grid(relu_qp_handle* h, int grid) {
   const int need = (h->L + rqp::kMaxRows - 1) / rqp::kMaxRows;
   const int top = h->L < 256 ? h->L : 256;  // the check gathers at most 8 * 256 norm partials
   if (grid < need || grid > top) return fail(RQP_EINVAL, "grid %d outside [%d, %d]", grid, need, top);
+  if (!check_split_fits(h->n, h->m, grid)) return fail(RQP_EINVAL, "grid %d: check split does not fit", grid);
   rqp::LaunchPlan p = make_plan(h, grid, false), px = make_plan(h, grid, true);
   if (!p.fn || !px.fn) return fail(RQP_EHIP, "no kernel resources for n + m = %d", h->L);
   const int lim = p.max_grid < px.max_grid ? p.max_grid : px.max_grid;
@@ -414,7 +427,7 @@ int choose_grid(relu_qp_handle* h) {
   if (gp < need) gp = need;
   if (gp != g) {
     const rqp::LaunchPlan p = make_plan(h, gp, false);
-    if (p.fn && gp <= p.max_grid) {
+    if (p.fn && gp <= p.max_grid && check_split_fits(h->n, h->m, gp)) {
       h->plan = p;
       h->grid_plain = gp;
     }

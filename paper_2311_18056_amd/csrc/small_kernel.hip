@@ -15,10 +15,10 @@
 // DPP lane moves sum the S partials, leaving the row's value in all S lanes. Waves that hold
 // no row skip the product.
 //
-// Every check_interval iterations (Sec. III-C) the rows of [P, A'] [x; y] are formed with FP64
-// accumulation from the check matrix, held in LDS for the whole launch, A x is the
-// product the constraint rows carry along in FP64, and the seven inf-norms are reduced as
-// ordered bit patterns (exact and NaN-propagating). The stopping test (eqs. primal, dual) and
+// Every check_interval iterations (Sec. III-C) the rows of [P, A'; A, 0] [x; y] (P x + A'y and
+// A x) are formed with FP64 accumulation from the check matrix, held in LDS for the whole
+// launch, and the seven inf-norms are reduced as ordered bit patterns (exact and
+// NaN-propagating). The stopping test (eqs. primal, dual) and
 // the penalty rule (eq. rho_update, nearest grid value) are those of the persistent kernel.
 #include "small_kernel.h"
 
@@ -79,12 +79,15 @@ __device__ void load_check(const LayerArgs& a, T* Cl) {
 
 // Products of this lane's part of its row of the check matrix with cv over the columns
 // c = i S + s < cend, FP64, split at column n (the P or A part and the A' part), accumulated in
-// ascending column order; columns out of range contribute zero.
+// ascending column order, with the sums of their absolute values (alo, ahi: the rounding bound
+// of the check); columns out of range contribute zero.
 template <typename T, int S, int NI>
 __device__ __forceinline__ void check_products(const LayerArgs& a, const T* Cl, int s, int cend, const T* cv,
-                                               double& lo, double& hi) {
+                                               double& lo, double& hi, double& alo, double& ahi) {
   lo = 0.0;
   hi = 0.0;
+  alo = 0.0;
+  ahi = 0.0;
 #pragma unroll
   for (int i0 = 0; i0 < NI; i0 += kBatch) {
     T cval[kBatch], xval[kBatch];
@@ -97,10 +100,13 @@ __device__ __forceinline__ void check_products(const LayerArgs& a, const T* Cl, 
     for (int b = 0; b < kBatch; ++b) {
       const int c = (i0 + b) * S + s;
       const double v = c < cend ? (double)cval[b] * (double)xval[b] : 0.0;
-      if (c < a.n)
+      if (c < a.n) {
         lo += v;
-      else
+        alo += fabs(v);
+      } else {
         hi += v;
+        ahi += fabs(v);
+      }
     }
   }
 }
@@ -132,8 +138,13 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
 
   const int ci = a.check_interval, max_iter = a.max_iter;
   const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
-  const double alpha_d = a.alpha, oma_d = 1.0 - a.alpha;
-  // the state of row r, held by all S lanes of the row (they compute the same values)
+  // rounding bound of the check (FP32 iterations): |computed - FP64| <= kappa * sum |a_ij v_j|
+  // per row, with the stored matrices and the outputs rounded to FP32 and FP64 accumulation over
+  // at most L terms on both sides; an FP64 handle computes the FP64 residual itself
+  const double kappa = sizeof(T) == sizeof(double) ? 0.0 : 1.01 * (2.0 * 0x1p-24 + 2.0 * (double)(L + 8) * 0x1p-53);
+  const double ut = sizeof(T) == sizeof(double) ? 0.0 : 1.01 * 0x1p-24;
+  // the state of row r, held by all S lanes of the row (they compute the same values); ax is
+  // the last check's (A x)_r of a constraint row
   T sx = 0, sz = 0, sy = 0, sq = 0, sl = 0, su = 0;
   double ax = 0.0;
   int j = a.warm ? *a.js : a.j0;
@@ -199,8 +210,8 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
     if (warm) {
       if (own) cv[r] = xrow ? sx : sy;
       __syncthreads();
-      double p, unused;
-      check_products<T, S, NI>(a, Cl, s, n, cv, p, unused);  // rows past L hold zeros
+      double p, unused, unused2, unused3;
+      check_products<T, S, NI>(a, Cl, s, n, cv, p, unused, unused2, unused3);  // rows past L hold zeros
       p = row_sum<S>(p);
       if (row && !xrow) {
         sz = (T)p;
@@ -233,8 +244,6 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
           if (xrow) {
             sx = alpha * v + oma * sx;
           } else {
-            // A x_{k+1} = alpha A xt + (1 - alpha) A x_k, with A xt the layer output v
-            ax = fma(alpha_d, (double)v, oma_d * ax);
             const T t = alpha * v + oma * sz + sy * rinv;
             const T zn = box_clamp(t, sl, su);
             sy = srho * (t - zn);
@@ -246,28 +255,37 @@ __global__ void __launch_bounds__(SB) small_kernel(LayerArgs a) {
         __syncthreads();
       }
 
-      // check at iteration k: rows of [P, A'] [x; y] (dual side), the carried A x (primal side)
+      // check at iteration k: rows of [P, A'; A, 0] [x; y], FP64 accumulation: P x + A'y for
+      // the x rows (dual side), A x for the constraint rows (primal side). In FP32 the published
+      // residuals are upper bounds and the norms lower bounds of the FP64 values of a CPU
+      // evaluation of the returned x, z, y with the caller's P, q, A (kappa), so SOLVED implies
+      // that the FP64 test passes.
       if (own) cv[r] = xrow ? sx : sy;
       __syncthreads();
-      double pr, ar;
-      check_products<T, S, NI>(a, Cl, s, L, cv, pr, ar);
+      double pr, ar, apr, aar;
+      check_products<T, S, NI>(a, Cl, s, L, cv, pr, ar, apr, aar);
       pr = row_sum<S>(pr);
       ar = row_sum<S>(ar);
+      apr = row_sum<S>(apr);
+      aar = row_sum<S>(aar);
+      if (row && !xrow) ax = pr;
       if (own) {
         // a Ruiz-scaled problem weights each row's terms so that the norms are the original
         // problem's: 1 / (c D_r) on the dual side, 1 / E_i on the primal side (1 otherwise)
         if (xrow) {
           const double qv = (double)sq, f = a.sc_dual ? a.sc_dual[r] : 1.0;
-          nrm[K_RD][r] = abs_bits(f * (pr + qv + ar));
-          nrm[K_PX][r] = abs_bits(f * pr);
-          nrm[K_ATY][r] = abs_bits(f * ar);
-          nrm[K_Q][r] = abs_bits(f * qv);
+          const double dpx = kappa * apr, daty = kappa * aar, dq = ut * fabs(qv);
+          nrm[K_RD][r] = abs_bits(f * (fabs(pr + qv + ar) + dpx + daty + dq));
+          nrm[K_PX][r] = abs_bits(f * lower_bound(fabs(pr), dpx));
+          nrm[K_ATY][r] = abs_bits(f * lower_bound(fabs(ar), daty));
+          nrm[K_Q][r] = abs_bits(f * lower_bound(fabs(qv), dq));
           nrm[K_RP][r] = nrm[K_AX][r] = nrm[K_Z][r] = 0;
         } else {
           const double e = a.sc_prim ? a.sc_prim[r - n] : 1.0;
-          nrm[K_RP][r] = abs_bits(e * (ax - (double)sz));
-          nrm[K_AX][r] = abs_bits(e * ax);
-          nrm[K_Z][r] = abs_bits(e * (double)sz);
+          const double ds = kappa * apr, zv = (double)sz, dz = ut * fabs(zv);
+          nrm[K_RP][r] = abs_bits(e * (fabs(pr - zv) + ds + dz));
+          nrm[K_AX][r] = abs_bits(e * lower_bound(fabs(pr), ds));
+          nrm[K_Z][r] = abs_bits(e * lower_bound(fabs(zv), dz));
           nrm[K_RD][r] = nrm[K_PX][r] = nrm[K_ATY][r] = nrm[K_Q][r] = 0;
         }
       }
