@@ -284,6 +284,9 @@ def main():
         out = bench_single(args, args.workload, args.x0_scale, args.steps, args.warmup, probes=True)
         if args.workload == "c1" and not args.no_variants:
             out["variants"] = variants(args)
+    import paper_2311_18056_amd as rq
+
+    rq.close_all()  # every handle is closed before the interpreter (and a profiler) shuts down
     print(json.dumps(out), flush=True)
 
 

@@ -21,4 +21,4 @@ from ._lib import (  # noqa: F401
     ReluQPError,
     lib,
 )
-from .solver import STATUS_NAMES, Solver, default_settings, footprint  # noqa: F401
+from .solver import STATUS_NAMES, Solver, close_all, default_settings, footprint, open_handles  # noqa: F401

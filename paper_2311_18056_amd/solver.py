@@ -6,7 +6,10 @@ provides the device memory of the result buffers and the stream.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from ctypes import POINTER, byref, c_double, c_int, c_size_t, c_void_p
 
 import numpy as np
@@ -17,6 +20,24 @@ from ._lib import (RQP_BF16X3, RQP_ENGINE_AUTO, RQP_ENGINE_BATCH, RQP_ENGINE_SIN
                    Settings, check, lib)
 
 STATUS_NAMES = {0: "running", 1: "solved", 2: "max_iter", 3: "nonfinite", 4: "aborted", 5: "internal", 6: "idle"}
+
+
+# Handles still open. They are closed by an exit hook, which runs before the interpreter tears
+# down its modules and while the HIP runtime (and a profiler attached to it) is still alive; a
+# handle freed later, from a finaliser during interpreter shutdown, would call into a runtime
+# that may already be gone.
+_OPEN = weakref.WeakSet()
+
+
+@atexit.register
+def close_all():
+    """Close every handle that is still open (also run at interpreter exit)."""
+    for s in list(_OPEN):
+        s.close()
+
+
+def open_handles() -> int:
+    return len(_OPEN)
 
 
 def _f64(a, shape=None):
@@ -101,6 +122,7 @@ class Solver:
         self._h = c_void_p()
         check(L.relu_qp_setup(byref(self._h), n, m, _ptr(P), _ptr(q), _ptr(A), _ptr(l), _ptr(u),
                               byref(self.settings), _stream_handle(stream)))
+        _OPEN.add(self)
         self.max_checks = check(L.relu_qp_max_checks(self._h))
         self.fp64 = self.settings.precision == RQP_FP64
         self.dtype = torch.float64 if self.fp64 else torch.float32
@@ -360,8 +382,13 @@ class Solver:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().relu_qp_cleanup(self._h)
             self._h = c_void_p()
+        _OPEN.discard(self)
 
     def __del__(self):
+        # during interpreter shutdown the exit hook has already closed every handle; never call
+        # into the HIP runtime from a finaliser that late
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
