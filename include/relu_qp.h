@@ -167,6 +167,20 @@ int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_
  * data; RQP_EINVAL if count < 1, on the batched engine, or count*(max_iter+2) >= 2^31. */
 int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, hosts that forbid hipMalloc at run time): relu_qp_solve_x0 with the launch's scratch
+ * (the exchange words of the layer input, the check vector and the norm partials, and the
+ * error word) in a device array inside the library instead of the handle's allocations. The
+ * call allocates nothing, frees nothing and issues no memset (the scratch is cleared by a
+ * kernel on first use on a GPU and whenever its tag sequence restarts). The array holds
+ * 1 MiB on each GPU the library runs on (enough for every n + m the single-instance engine
+ * accepts; RQP_EINVAL otherwise) and stays until the process ends. Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other threads) race, so
+ * serialise them. Same arguments, results and handle state as relu_qp_solve_x0; the current
+ * device must be the one the handle was set up on (RQP_ESTATE otherwise, also on the batched
+ * engine). */
+int relu_qp_solve_x0_noalloc(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out);
+
 /* The paper's literal layer (eq. gpu_update), for comparison with the compact form the solver
  * runs: v <- clamp(W v + b, c~, d~) with v = [x; z; lambda] (n + 2m), W the full
  * (n+2m) x (n+2m) weight matrix built from the handle's matrices at first use (FP64 products,

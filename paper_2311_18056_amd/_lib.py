@@ -38,6 +38,7 @@ EXPORTS = [
     "relu_qp_set_warm",
     "relu_qp_solve",
     "relu_qp_solve_x0",
+    "relu_qp_solve_x0_noalloc",
     "relu_qp_solve_sequence",
     "relu_qp_load_slots",
     "relu_qp_load_slots_x0",
@@ -125,6 +126,7 @@ def lib():
     L.relu_qp_set_warm.argtypes = [h, c_int]
     L.relu_qp_solve.argtypes = [h, c_void_p, POINTER(Result)]
     L.relu_qp_solve_x0.argtypes = [h, c_void_p, c_void_p, POINTER(Result)]
+    L.relu_qp_solve_x0_noalloc.argtypes = [h, c_void_p, c_void_p, POINTER(Result)]
     L.relu_qp_solve_sequence.argtypes = [h, c_void_p, c_int, c_void_p, POINTER(Result)]
     _ip = POINTER(c_int)
     L.relu_qp_load_slots.argtypes = [h, _ip, c_int, c_void_p, c_void_p, c_void_p, c_void_p]

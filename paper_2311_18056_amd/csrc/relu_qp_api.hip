@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,7 @@ struct DevBuf {
 
 struct relu_qp_handle {
   int n = 0, m = 0, L = 0, batch = 1;
+  int device = 0;  // the GPU the handle's memory lives on
   long ldw = 0;
   relu_qp_settings s{};
   size_t esize = 8;  // bytes per iterate element
@@ -193,6 +195,47 @@ void dfree(relu_qp_handle* h, void** p) {
 template <typename T>
 hipError_t dmalloc(relu_qp_handle* h, T** p, size_t bytes) {
   return dmalloc(h, reinterpret_cast<void**>(p), bytes);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Scratch of relu_qp_solve_x0_noalloc: the exchange words of one persistent launch (layer input,
+// check vector, norm partials) and its error word, in a file-scope device array instead of the
+// handle's allocations, so that the entry point allocates nothing. Every GPU the library runs on
+// holds its own copy until the process ends. On the host, `scratch` names a host-side stand-in,
+// not device memory: host code uses only the per-device address hipGetSymbolAddress returned
+// (kept in g_scratch). Layout: error word at 0, norm partials (2 x kMaxGrid x 8 x 2 words) at
+// 256, then the layer-input and check-vector words (2 x L x words each).
+constexpr size_t kScratchBytes = (size_t)1 << 20;
+constexpr size_t kScratchNormOff = 256;
+constexpr size_t kScratchNormWords = (size_t)2 * rqp::kMaxGrid * 8 * 2;
+constexpr size_t kScratchXwOff = kScratchNormOff + kScratchNormWords * 8;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+struct ScratchDev {
+  void* ptr = nullptr;  // the device address of this GPU's scratch
+  uint32_t tag = 1;     // next tag of the exchange words (monotone over every call on this GPU)
+  bool clean = false;   // cleared since the process started
+};
+std::mutex g_scratch_mu;
+ScratchDev g_scratch[kScratchDevices];
+
+// Once per device, with that device current (called from relu_qp_setup).
+int scratch_init(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return fail(RQP_EINVAL, "device %d beyond %d", dev, kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev].ptr) return RQP_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return fail(RQP_EHIP, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+  g_scratch[dev].ptr = ptr;
+  return RQP_OK;
+}
+
+// Zero fill by a kernel (no memset node, so a caller may capture the call in a graph).
+__global__ void clear_words(uint64_t* p, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 int validate_settings(const relu_qp_settings* s) {
@@ -775,7 +818,12 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
         return fail(RQP_EINVAL, "instance %d has another equality-row pattern (row %d)", b, i);
   }
 
+  int dev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev));
+  rc = scratch_init(dev);
+  if (rc) return rc;
   relu_qp_handle* h = new relu_qp_handle();
+  h->device = dev;
   h->n = n;
   h->m = m;
   h->L = n + m;
@@ -1075,35 +1123,9 @@ struct ClosedLoop {
   double* traj_u;
 };
 
-int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, relu_qp_result* out,
-               const ClosedLoop* cl = nullptr) {
-  if (!h) return fail(RQP_ESTATE, "NULL handle");
-  DEVICE_OR_FAIL(h);
-  if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
-    return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (x0 && !h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
-  if (h->batched) {
-    if (x0) HIP_OR_FAIL(rqp::mpc_vectors_tiled<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
-                                                static_cast<float*>(h->q), static_cast<float*>(h->l),
-                                                static_cast<float*>(h->u), st));
-    return solve_batched(h, st, out);
-  }
-  if (count < 1) return fail(RQP_EINVAL, "count must be >= 1");
-  if (count > 1 && h->batched) return fail(RQP_EINVAL, "solve sequences run on the single-instance engine");
-  const uint32_t span = (uint32_t)h->s.max_iter + 2u;
-  if ((uint64_t)span * (uint64_t)count >= 0x7fffffffull)
-    return fail(RQP_EINVAL, "count * (max_iter + 2) must stay below 2^31");
-  if ((uint64_t)h->tag + (uint64_t)span * count >= 0xffffffffull) {
-    // restart the tag sequence: clear every exchange word so no stale tag can match
-    HIP_OR_FAIL(hipMemsetAsync(h->xw, 0, h->xw_words * 8, st));
-    HIP_OR_FAIL(hipMemsetAsync(h->xc, 0, h->xw_words * 8, st));
-    HIP_OR_FAIL(hipMemsetAsync(h->xn, 0, h->xn_words * 8, st));
-    HIP_OR_FAIL(hipMemsetAsync(h->xu, 0, (size_t)2 * rqp::kMaxPlant * 2 * 8, st));
-    HIP_OR_FAIL(hipMemsetAsync(h->err, 0, sizeof(unsigned), st));
-    h->tag = 1;
-  }
-  __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
+// Arguments of a single-instance launch from the handle (its exchange words and tag).
+rqp::LayerArgs layer_args(relu_qp_handle* h, const double* x0, int count, relu_qp_result* out,
+                          const ClosedLoop* cl) {
   rqp::LayerArgs a{};
   a.n = h->n;
   a.m = h->m;
@@ -1178,20 +1200,69 @@ int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, rel
     a.chain = 1;
     a.final_check = 0;
   }
-  const bool xt = cl || h->scl;
+  return a;
+}
+
+// The launch itself: the single-workgroup kernel for small plain solves, else the persistent
+// grid (the XT instantiation for closed loops and scaled problems). The handle's warm state
+// advances with it.
+int launch_single(relu_qp_handle* h, const rqp::LayerArgs& a, bool closed, hipStream_t st) {
+  const bool xt = closed || h->scl;
   const rqp::LaunchPlan& plan = xt ? h->plan_xt : h->plan;
   const int grid = xt ? h->grid_wg : h->grid_plain;
   hipError_t e;
-  if (h->small && !cl)
+  if (h->small && !closed)
     e = h->esize == 8 ? rqp::launch_small<double>(a, st) : rqp::launch_small<float>(a, st);
   else
     e = h->esize == 8 ? rqp::launch_layer<double>(a, plan, grid, st) : rqp::launch_layer<float>(a, plan, grid, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "persistent launch failed: %s", hipGetErrorString(e));
-  h->tag += span * (uint32_t)count;
   h->warm_pending = false;
   h->have_prev = true;
   return RQP_OK;
 }
+
+int check_single_call(relu_qp_handle* h, const double* x0, int count, relu_qp_result* out) {
+  if (!h) return fail(RQP_ESTATE, "NULL handle");
+  DEVICE_OR_FAIL(h);
+  if (!out || !out->x || !out->y || !out->z || !out->iterations || !out->status || !out->rho_index)
+    return fail(RQP_EINVAL, "result buffers x, y, z, iterations, status and rho_index are required");
+  if (x0 && !h->F_d) return fail(RQP_ESTATE, "relu_qp_set_parametric has not been called");
+  if (count < 1) return fail(RQP_EINVAL, "count must be >= 1");
+  if (count > 1 && h->batched) return fail(RQP_EINVAL, "solve sequences run on the single-instance engine");
+  const uint64_t span = (uint64_t)h->s.max_iter + 2u;
+  if (span * (uint64_t)count >= 0x7fffffffull) return fail(RQP_EINVAL, "count * (max_iter + 2) must stay below 2^31");
+  return RQP_OK;
+}
+
+int solve_impl(relu_qp_handle* h, const double* x0, int count, void* stream, relu_qp_result* out,
+               const ClosedLoop* cl = nullptr) {
+  int rc = check_single_call(h, x0, h && h->batched ? 1 : count, out);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (h->batched) {
+    if (x0) HIP_OR_FAIL(rqp::mpc_vectors_tiled<float>(h->batch, h->n, h->m, h->nx, h->F_d, h->E_d, h->lo_d, h->hi_d, x0,
+                                                static_cast<float*>(h->q), static_cast<float*>(h->l),
+                                                static_cast<float*>(h->u), st));
+    return solve_batched(h, st, out);
+  }
+  const uint32_t span = (uint32_t)h->s.max_iter + 2u;
+  if ((uint64_t)h->tag + (uint64_t)span * count >= 0xffffffffull) {
+    // restart the tag sequence: clear every exchange word so no stale tag can match
+    HIP_OR_FAIL(hipMemsetAsync(h->xw, 0, h->xw_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xc, 0, h->xw_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xn, 0, h->xn_words * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->xu, 0, (size_t)2 * rqp::kMaxPlant * 2 * 8, st));
+    HIP_OR_FAIL(hipMemsetAsync(h->err, 0, sizeof(unsigned), st));
+    h->tag = 1;
+  }
+  __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
+  const rqp::LayerArgs a = layer_args(h, x0, count, out, cl);
+  rc = launch_single(h, a, cl != nullptr, st);
+  if (rc) return rc;
+  h->tag += span * (uint32_t)count;
+  return RQP_OK;
+}
+
 
 }  // namespace
 
@@ -1209,6 +1280,45 @@ int relu_qp_solve_x0(relu_qp_handle* h, const double* x0, void* stream, relu_qp_
 int relu_qp_solve_sequence(relu_qp_handle* h, const double* x0s, int count, void* stream, relu_qp_result* out) {
   if (!x0s) return fail(RQP_EINVAL, "x0s is NULL");
   return solve_impl(h, x0s, count, stream, out);
+}
+
+int relu_qp_solve_x0_noalloc(relu_qp_handle* h, const double* x0, void* stream, relu_qp_result* out) {
+  if (!x0) return fail(RQP_EINVAL, "x0 is NULL");
+  int rc = check_single_call(h, x0, 1, out);
+  if (rc) return rc;
+  if (h->batched) return fail(RQP_ESTATE, "relu_qp_solve_x0_noalloc runs on the single-instance engine");
+  const size_t words = h->esize == 8 ? 2 : 1;
+  const size_t need = kScratchXwOff + (size_t)2 * 2 * h->L * words * 8;
+  if (need > kScratchBytes)
+    return fail(RQP_EINVAL, "n + m = %d needs %zu bytes of scratch; the library holds %zu", h->L, need, kScratchBytes);
+  int cur = -1;
+  HIP_OR_FAIL(hipGetDevice(&cur));
+  if (cur != h->device) return fail(RQP_ESTATE, "the current device %d is not the handle's device %d", cur, h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rqp::LayerArgs a = layer_args(h, x0, 1, out, nullptr);
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchDev& sd = g_scratch[h->device];
+    if (!sd.ptr) return fail(RQP_ESTATE, "no scratch on device %d", h->device);
+    const uint32_t span = (uint32_t)h->s.max_iter + 2u;
+    unsigned char* base = static_cast<unsigned char*>(sd.ptr);
+    if (!sd.clean || (uint64_t)sd.tag + span >= 0xffffffffull) {
+      // first use on this GPU, or the tag sequence restarts: no stale tag may match
+      hipLaunchKernelGGL(clear_words, dim3(256), dim3(256), 0, st, reinterpret_cast<uint64_t*>(base),
+                         kScratchBytes / 8);
+      HIP_OR_FAIL(hipGetLastError());
+      sd.tag = 1;
+      sd.clean = true;
+    }
+    a.err = reinterpret_cast<unsigned*>(base);
+    a.xn = reinterpret_cast<uint64_t*>(base + kScratchNormOff);
+    a.xw = reinterpret_cast<uint64_t*>(base + kScratchXwOff);
+    a.xc = a.xw + (size_t)2 * h->L * words;
+    a.tag = sd.tag;
+    sd.tag += span;
+  }
+  __atomic_store_n(h->abort_h, 0, __ATOMIC_SEQ_CST);
+  return launch_single(h, a, false, st);
 }
 
 int relu_qp_solve_paper_form(relu_qp_handle* h, int iters, void* stream, relu_qp_result* out) {

@@ -192,6 +192,14 @@ class Solver:
         check(lib().relu_qp_solve_x0(self._h, c_void_p(x0.data_ptr()), _stream_handle(stream),
                                      byref(out if out is not None else self._res)))
 
+    def solve_x0_noalloc(self, x0: torch.Tensor, stream=None, out: Result | None = None):
+        """solve_x0 with the launch's scratch in the library's static device array: the call
+        allocates nothing (calls that overlap on one GPU race)."""
+        if x0.dtype != torch.float64 or not x0.is_cuda or not x0.is_contiguous():
+            raise ValueError("x0 must be a contiguous float64 cuda tensor")
+        check(lib().relu_qp_solve_x0_noalloc(self._h, c_void_p(x0.data_ptr()), _stream_handle(stream),
+                                             byref(out if out is not None else self._res)))
+
     def solve_sequence(self, x0s: torch.Tensor, stream=None, out=None):
         """len(x0s) solves in one launch of the single-instance engine, each from its own x0
         (float64 cuda, count x nx). Results go to ``out`` (a dict from ``sequence_slots``) or to
