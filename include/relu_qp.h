@@ -244,14 +244,17 @@ int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot
  * Needs max_iter % check_interval == 0 (RQP_EINVAL otherwise). */
 int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* out);
 
-/* Tile shape of the batched engine's GEMM: 128 or 64 matrix rows per tile (x 128 instances).
+/* Tile shape of the batched engine's GEMM: 128, 64 or 256 matrix rows per tile (x 128 instances).
  * relu_qp_setup of a batched handle runs an autotuner: every shape runs two check intervals of
  * all slots on the handle's own data, timed on the device, and the faster is kept (slots are
- * idle and the state zero afterwards). The shapes agree to rounding (the same products per
- * element, issued to the matrix cores in another interleaving).
- * relu_qp_get_tile: the shape in use and, in us_per_iter[2] (may be NULL), the autotuner's
- * microseconds per iteration for 128 and 64 rows. relu_qp_set_tile: force 128 or 64, or 0
- * for the autotuner's choice. RQP_ESTATE on a single-instance handle. */
+ * idle and the state zero afterwards). The choice and timings are cached for the rest of the
+ * process per device and problem shape (n, m, batch, precision, number of penalties): a later
+ * handle of the same shape (a family loaded again) takes them without timing. The shapes
+ * agree to rounding (the same products per element, issued to the matrix cores in another
+ * interleaving).
+ * relu_qp_get_tile: the shape in use and, in us_per_iter[3] (may be NULL), the autotuner's
+ * microseconds per iteration for 128, 64 and 256 rows. relu_qp_set_tile: force 128, 64 or 256,
+ * or 0 for the autotuner's choice. RQP_ESTATE on a single-instance handle. */
 int relu_qp_get_tile(const relu_qp_handle* h, int* tile_rows, double* us_per_iter);
 int relu_qp_set_tile(relu_qp_handle* h, int tile_rows);
 

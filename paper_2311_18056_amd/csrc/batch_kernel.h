@@ -22,7 +22,7 @@ struct SlotList {
 };
 
 constexpr int kTileM = 128;   // instances per tile
-constexpr int kTileN = 128;   // layer rows per tile (largest tile shape; 64 also exists)
+constexpr int kTileN = 256;   // layer rows per tile (largest tile shape; 128 and 64 also exist)
 constexpr int kTileK = 32;    // k per LDS stage
 constexpr int kBatchBlock = 256;
 
@@ -38,8 +38,7 @@ struct BatchArgs {
   const void* Wa;           // FP32 layer matrices, or BF16 high parts: n_rho blocked lpad x ldk
   const void* Wb;           // BF16 low parts (kBatchBF16x3), else null
   long w_stride;            // elements between penalty matrices
-  const void* Ca;           // check matrix [P, A'; A, 0], same format (blocked lpad x ldk)
-  const void* Cb;
+  const double* Cd;         // check matrix [P, A'; A, 0] in FP64, same format (blocked lpad x ldk)
   const float* Q;           // B x n
   const float* Lo;          // B x m
   const float* Up;          // B x m
@@ -57,8 +56,7 @@ struct BatchArgs {
   // rows are contiguous
   void* Va;                 // layer inputs, 2 parities x blocked bpad x ldk (FP32, or BF16 high)
   void* Vb;                 // BF16 low parts
-  void* CVa;                // check operand [x; y], blocked bpad x ldk
-  void* CVb;
+  double* CVd;              // check operand [x; y] in FP64 (exact copies of the FP32 iterates), blocked bpad x ldk
   int* jb;                  // B penalty indices (kept for running and warm-admitted slots)
   int* status;              // B slot states (kSlot* below, or a final status), persistent
   int* iterations;          // B iterations since admission, persistent
@@ -78,10 +76,12 @@ struct BatchPlan {
   const void* fn;
   int grid;
   size_t smem;
-  int tn;  // matrix rows per tile (128 or 64)
+  int tn;  // matrix rows per tile (256, 128 or 64)
 };
 
-// Kernel of the given precision and tile rows (128 or 64); fn == null if unavailable.
+// Kernel of the given precision and tile rows (256, 128 or 64); fn == null if unavailable.
+constexpr int kTileShapes = 3;
+constexpr int kTileRows[kTileShapes] = {128, 64, 256};
 BatchPlan plan_batch(int prec, int tn);
 // Set every slot's state (e.g. admit all for a whole-batch solve).
 hipError_t fill_status(int B, int value, int* status, hipStream_t st);
@@ -104,5 +104,9 @@ hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void*
                       hipStream_t st);
 hipError_t pad_f32(long rows, int cols, const double* src, long ld_src, float* dst, long lpad, long ldk,
                    hipStream_t st);
+hipError_t pad_f64(long rows, int cols, const double* src, long ld_src, double* dst, long lpad, long ldk,
+                   hipStream_t st);
+// Dynamic LDS bytes of the batched kernel with this plan (the larger of its GEMM tile stages).
+size_t batch_smem(int prec, int tn);
 
 }  // namespace rqp

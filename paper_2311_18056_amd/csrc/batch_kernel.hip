@@ -12,9 +12,11 @@
 // with three products hi*hi + lo*hi + hi*lo on v_mfma_f32_32x32x16_bf16 (FP32 accumulation),
 // which keeps ~16 significant bits of each operand; iterates stay FP32.
 //
-// Every check_interval iterations the same GEMM with the check matrix [P, A'; A, 0] and the
-// operand [x; y] gives P x, A'y and A x of every instance; per-instance inf-norms are reduced
-// with integer max on ordered FP64 bit patterns (atomics across row tiles), then one thread per
+// Every check_interval iterations a GEMM in FP64 with the check matrix [P, A'; A, 0] (the FP64
+// problem data) and the operand [x; y] (exact FP64 copies of the FP32 iterates) gives P x, A'y
+// and A x of every instance on the FP64 matrix cores, so the residuals of eqs. primal and dual
+// are FP64 evaluations of the state the solve returns; per-instance inf-norms are reduced with
+// integer max on ordered FP64 bit patterns (atomics across row tiles), then one thread per
 // instance applies the stopping test and the penalty rule. Phases are separated by a grid
 // barrier (cooperative launch). An instance's arithmetic never depends on which other
 // instances share its tiles, so a result is the same alone and in a batch.
@@ -101,9 +103,10 @@ __device__ __forceinline__ void put_operand(void* va, void* vb, long idx, float 
 }
 
 // ------------------------------------------------------------------------------------------
-// GEMM tile of TM instances x TNV matrix rows (TNV = 128 or 64): four waves in a 2 x 2 grid,
-// each owning 64 instances x TNV/2 rows as 2 x BJ blocks of 32 x 32 accumulators (lane layout
-// of v_mfma_f32_32x32x*). Operand A rows are list positions (instances), B rows are matrix
+// GEMM tile of TM instances x TNV matrix rows (TNV = 256, 128 or 64): four waves in a 2 x 2
+// grid, each owning 64 instances x TNV/2 rows as 2 x BJ blocks of 32 x 32 accumulators (lane
+// layout of v_mfma_f32_32x32x*). The larger tile reads fewer LDS bytes per product and fewer
+// operand bytes per flop; which wins depends on how many tiles a problem has (the autotuner). Operand A rows are list positions (instances), B rows are matrix
 // rows; both K-blocked (one K stage of a tile is one contiguous block).
 
 template <int PREC, int TNV>
@@ -263,18 +266,23 @@ __device__ __forceinline__ void compute(const Smem<PREC, TNV>& sm, int buf, floa
 }
 
 // acc = sum over k in [kb, ke) of A[row][k] B[col][k]. Stages of TK columns are double
-// buffered in LDS and fetched into a ring of kRing register stages, so that the global loads
-// run kRing - 1 stages ahead of the products. The stage count is rounded up to a multiple of
+// buffered in LDS and fetched into a ring of kRing (ring_of) register stages, so that the global
+// loads run kRing - 1 stages ahead of the products. The stage count is rounded up to a multiple of
 // kRing and every fetch is issued unconditionally (past the end it re-reads the last stage),
 // so every step has the same instruction stream and the wait before an LDS store covers the
 // loads of that stage only; a scheduling barrier keeps each fetch at the top of its step. The
 // extra stages lie in the operands' zero padding (or are masked).
-constexpr int kRing = 4;
+// The 256-row tile keeps a ring of two stages (its operand fragments take twice the registers).
+template <int TNV>
+constexpr int ring_of() {
+  return TNV > 128 ? 2 : 4;
+}
 template <int PREC, int TNV, bool MASK>
 __device__ __forceinline__ void tile_gemm(Smem<PREC, TNV>& sm, const void* Aa, const void* Ab, const void* Ba,
                                           const void* Bb, const long (&aoff)[Smem<PREC, TNV>::kRowsA],
                                           const long (&boff)[Smem<PREC, TNV>::kRowsB], long as, long bs, int kb,
                                           int ke, floatx16 (&acc)[2][TNV / 64]) {
+  constexpr int kRing = ring_of<TNV>();
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -301,6 +309,89 @@ __device__ __forceinline__ void tile_gemm(Smem<PREC, TNV>& sm, const void* Aa, c
     }
   }
 }
+
+// ------------------------------------------------------------------------------------------
+// FP64 GEMM tile of the residual check and of the warm start's z = A x: T64 = 64 list positions
+// x 64 matrix rows, K in stages of TK staged through LDS (double buffered, rows padded to
+// TK + 2 doubles: the fragment reads of a half-wave hit distinct banks), four waves in a 2 x 2
+// grid, each 32 x 32 as 2 x 2 blocks of v_mfma_f64_16x16x4f64 (lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step, and D[l / 16 + 4 v][l % 16] in element v:
+// checked on the device against a host product).
+// Products of FP64 data with FP32 iterates are exact in FP64, so the sums are FP64 dot products.
+constexpr int T64 = 64, PAD64 = 2;
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+struct Smem64 {
+  double a[2][T64][TK + PAD64];
+  double b[2][T64][TK + PAD64];
+};
+// One K stage of this thread's chunks: 4 of the operand tile and 4 of the matrix tile, two
+// doubles (16 bytes) each; chunk c = tid + 256 q covers row c / 16, columns 2 (c % 16) + {0, 1}.
+struct Frag64 {
+  double2 a[4], b[4];
+};
+__device__ __forceinline__ void fetch64(Frag64& f, const double* A, const double* Bm, long abase, long bbase, long as,
+                                        long bs, int stage) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = threadIdx.x + BS * q, row = c >> 4, kc = (c & 15) * 2;
+    f.a[q] = *reinterpret_cast<const double2*>(A + (long)stage * as + abase + (long)row * TK + kc);
+    f.b[q] = *reinterpret_cast<const double2*>(Bm + (long)stage * bs + bbase + (long)row * TK + kc);
+  }
+}
+// matrix entries with k outside [kb, ke) become zero
+__device__ __forceinline__ void stash64(Smem64& sm, int buf, const Frag64& f, int stage, int kb, int ke) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = threadIdx.x + BS * q, row = c >> 4, kc = (c & 15) * 2, k0 = stage * TK + kc;
+    double2 bv = f.b[q];
+    bv.x = (k0 >= kb && k0 < ke) ? bv.x : 0.0;
+    bv.y = (k0 + 1 >= kb && k0 + 1 < ke) ? bv.y : 0.0;
+    *reinterpret_cast<double2*>(&sm.a[buf][row][kc]) = f.a[q];
+    *reinterpret_cast<double2*>(&sm.b[buf][row][kc]) = bv;
+  }
+}
+__device__ __forceinline__ void compute64(const Smem64& sm, int buf, doublex4 (&acc)[2][2]) {
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int wm = wave / 2, wn = wave % 2;
+#pragma unroll
+  for (int kk = 0; kk < TK; kk += 4) {
+    double fa[2], fb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) fa[i] = sm.a[buf][wm * 32 + i * 16 + lane % 16][kk + lane / 16];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) fb[j] = sm.b[buf][wn * 32 + j * 16 + lane % 16][kk + lane / 16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+  }
+}
+// acc = sum over k in [kb, ke) of A[row][k] B[col][k] for the tile whose operand rows start at
+// element abase and matrix rows at bbase of a K block (as / bs elements per K block). The next
+// stage's loads are in flight while the current one is multiplied.
+__device__ __forceinline__ void tile_gemm64(Smem64& sm, const double* A, const double* Bm, long abase, long bbase,
+                                            long as, long bs, int kb, int ke, doublex4 (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int s0 = kb / TK, s1 = (ke + TK - 1) / TK;
+  if (s1 <= s0) return;
+  Frag64 f;
+  fetch64(f, A, Bm, abase, bbase, as, bs, s0);
+  stash64(sm, 0, f, s0, kb, ke);
+  __syncthreads();
+  for (int s = s0; s < s1; ++s) {
+    const int buf = (s - s0) & 1;
+    if (s + 1 < s1) fetch64(f, A, Bm, abase, bbase, as, bs, s + 1);
+    compute64(sm, buf, acc);
+    if (s + 1 < s1) stash64(sm, buf ^ 1, f, s + 1, kb, ke);
+    __syncthreads();
+  }
+}
+// Tile position of element v of FP64 block (i, j) for this lane: instance row, matrix column.
+__device__ __forceinline__ int acc64_row(int wm, int i, int v, int lane) { return wm * 32 + i * 16 + lane / 16 + 4 * v; }
+__device__ __forceinline__ int acc64_col(int wn, int j, int lane) { return wn * 32 + j * 16 + lane % 16; }
 
 // Position in the tile of accumulator element v of block (i, j) for this lane.
 __device__ __forceinline__ int acc_row(int wm, int i, int v, int lane) {
@@ -478,6 +569,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   using SM = Smem<PREC, TNV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   SM& sm = *reinterpret_cast<SM*>(smem_raw);
+  Smem64& sm64 = *reinterpret_cast<Smem64*>(smem_raw);  // the FP64 phases (check, warm start)
   __shared__ int s_count[64];
   __shared__ int s_list[TM];   // instance ids of the current M tile
   __shared__ float s_rho[64];  // grid penalties in FP32
@@ -548,32 +640,32 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       for (int u = 0; u < kU; ++u) {
         const long el = base + u * gstride;
         if (el >= (long)B * L || st[u] != kSlotAdmitWarm) continue;
-        put_operand<PREC>(a.CVa, a.CVb, opidx(a.bpad, ps[u], (int)(el % L)), xv[u]);
+        a.CVd[opidx(a.bpad, ps[u], (int)(el % L))] = (double)xv[u];
       }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
-    const int nt0 = n / TNV;  // first row tile holding constraint rows
-    const TileWalk tw(nmt, nt0, ntiles_n);
+    const TileWalk tw(2 * nmt, n / T64, (L + T64 - 1) / T64);  // 64-instance halves, constraint-row tiles
     for (int t = tw.first(); t < tw.count; t += tw.per) {
-      const MTile mt = mts[tw.mt(t)];
-      const int nt = tw.nt(t);
+      const int u = tw.mt(t), half = u % 2;
+      const MTile mt = mts[u / 2];
+      const int cnt = mt.cnt - T64 * half;
+      if (cnt <= 0) continue;  // the same for every thread of the workgroup
+      const int r0 = tw.nt(t) * T64;
       load_list(mt);
-      long aoff[SM::kRowsA], boff[SM::kRowsB];
-      tile_offsets<PREC, TNV>(a, mt, nt, 0, 0, aoff, boff);
-      floatx16 acc[2][BJ];
-      tile_gemm<PREC, TNV, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc);
+      doublex4 acc[2][2];
+      tile_gemm64(sm64, a.CVd, a.Cd, (long)(mt.off + T64 * half) * TK, (long)r0 * TK, as, bs, 0, n, acc);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j) {
-          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
+        for (int j = 0; j < 2; ++j) {
+          const int r = r0 + acc64_col(wn, j, lane);
           if (r < n || r >= L) continue;
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int ti = acc_row(wm, i, v, lane);
-            if (ti < mt.cnt) a.Z[(long)s_list[ti] * m + (r - n)] = acc[i][j][v];
+          for (int v = 0; v < 4; ++v) {
+            const int ti = acc64_row(wm, i, v, lane);
+            if (ti < cnt) a.Z[(long)s_list[T64 * half + ti] * m + (r - n)] = (float)acc[i][j][v];
           }
         }
     }
@@ -648,7 +740,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
             }
             const long oi = opidx(a.bpad, mt.off + ti, r);
             if (is_check)
-              put_operand<PREC>(a.CVa, a.CVb, oi, cv);
+              a.CVd[oi] = (double)cv;
             else
               put_operand<PREC>(a.Va, a.Vb, vout + oi, w);
           }
@@ -657,76 +749,70 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (!grid_barrier(a.bar, ++epoch)) return;
     if (!is_check) continue;
 
-    // ---- check GEMM: [P, A'; A, 0] [x; y]; K split at n keeps P x and A'y apart
-    for (int t = tw.first(); t < tw.count; t += tw.per) {
-      const MTile mt = mts[tw.mt(t)];
-      const int nt = tw.nt(t);
-      load_list(mt);
-      long aoff[SM::kRowsA], boff[SM::kRowsB];
-      tile_offsets<PREC, TNV>(a, mt, nt, 0, 0, aoff, boff);
-      floatx16 acc_p[2][BJ], acc_a[2][BJ];
-      tile_gemm<PREC, TNV, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, 0, n, acc_p);  // P x, A x
-      tile_gemm<PREC, TNV, true>(sm, a.CVa, a.CVb, a.Ca, a.Cb, aoff, boff, as, bs, n, L, acc_a);  // A'y, 0
-      // per instance (accumulator row) maxima over this tile's rows
+    // ---- check GEMM in FP64: [P, A'; A, 0] [x; y]; K split at n keeps P x and A'y apart, and
+    // the constraint rows ([A, 0]) need only K in [0, n). The dual residual uses q rounded to
+    // FP32 (the handle's copy): the published r_d adds that rounding (u |q_i|) and ||q|| drops it,
+    // so the test passes only if the FP64 test with the caller's q does.
+    {
+      const double uq = 1.01 * 0x1p-24;
+      const TileWalk tw64(2 * nmt, 0, (L + T64 - 1) / T64);
+      for (int t = tw64.first(); t < tw64.count; t += tw64.per) {
+        const int u = tw64.mt(t), half = u % 2;
+        const MTile mt = mts[u / 2];
+        const int cnt = mt.cnt - T64 * half;
+        if (cnt <= 0) continue;  // the same for every thread of the workgroup
+        const int r0 = tw64.nt(t) * T64;
+        load_list(mt);
+        const long abase = (long)(mt.off + T64 * half) * TK, bbase = (long)r0 * TK;
+        doublex4 acc_p[2][2], acc_a[2][2];
+        tile_gemm64(sm64, a.CVd, a.Cd, abase, bbase, as, bs, 0, n, acc_p);   // P x, A x
+        tile_gemm64(sm64, a.CVd, a.Cd, abase, bbase, as, bs, n, r0 < n ? L : n, acc_a);  // A'y (x rows)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        // q (x rows) or z (z rows) of the block's 2 x 16 elements, loaded together
-        float ext[BJ][16];
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j) {
-          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
-          const bool xr = r < n;
-          const int ri = xr ? r : (r < L ? r - n : 0);
+          for (int v = 0; v < 4; ++v) {
+            const int ti = acc64_row(wm, i, v, lane);
+            const bool valid_i = ti < cnt;
+            const long b = s_list[T64 * half + (valid_i ? ti : 0)];
+            uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const long b = s_list[acc_row(wm, i, v, lane)];
-            ext[j][v] = xr ? a.Q[b * n + ri] : a.Z[b * m + ri];
-          }
-        }
+            for (int j = 0; j < 2; ++j) {
+              const int r = r0 + acc64_col(wn, j, lane);
+              if (!valid_i || r >= L) continue;
+              const double pp = acc_p[i][j][v];
+              if (r < n) {
+                const double pa = acc_a[i][j][v], q = (double)a.Q[b * n + r], dq = uq * fabs(q);
+                const uint64_t vrd = abs_bits(fabs(pp + pa + q) + dq), vpx = abs_bits(pp), vat = abs_bits(pa);
+                const uint64_t vq = abs_bits(lower_bound(fabs(q), dq));
+                nb[N_RD] = vrd > nb[N_RD] ? vrd : nb[N_RD];
+                nb[N_PX] = vpx > nb[N_PX] ? vpx : nb[N_PX];
+                nb[N_ATY] = vat > nb[N_ATY] ? vat : nb[N_ATY];
+                nb[N_Q] = vq > nb[N_Q] ? vq : nb[N_Q];
+              } else {
+                const double z = (double)a.Z[b * m + (r - n)];
+                const uint64_t vrp = abs_bits(pp - z), vax = abs_bits(pp), vz = abs_bits(z);
+                nb[N_RP] = vrp > nb[N_RP] ? vrp : nb[N_RP];
+                nb[N_AX] = vax > nb[N_AX] ? vax : nb[N_AX];
+                nb[N_Z] = vz > nb[N_Z] ? vz : nb[N_Z];
+              }
+            }
+            // lanes with the same lane / 16 hold the same instance row: reduce over lane % 16
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int ti = acc_row(wm, i, v, lane);
-          const bool valid_i = ti < mt.cnt;
-          uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
+            for (int q = 0; q < 7; ++q) {
+              uint64_t x = nb[q];
 #pragma unroll
-          for (int j = 0; j < BJ; ++j) {
-            const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
-            if (!valid_i || r >= L) continue;
-            const double pp = (double)acc_p[i][j][v], pa = (double)acc_a[i][j][v];
-            if (r < n) {
-              const double q = (double)ext[j][v];
-              const double rd = pp + pa + q;  // P x + A'y + q
-              const uint64_t vrd = abs_bits(rd), vpx = abs_bits(pp), vat = abs_bits(pa), vq = abs_bits(q);
-              nb[N_RD] = vrd > nb[N_RD] ? vrd : nb[N_RD];
-              nb[N_PX] = vpx > nb[N_PX] ? vpx : nb[N_PX];
-              nb[N_ATY] = vat > nb[N_ATY] ? vat : nb[N_ATY];
-              nb[N_Q] = vq > nb[N_Q] ? vq : nb[N_Q];
-            } else {
-              const double z = (double)ext[j][v];
-              const uint64_t vrp = abs_bits(pp - z), vax = abs_bits(pp), vz = abs_bits(z);
-              nb[N_RP] = vrp > nb[N_RP] ? vrp : nb[N_RP];
-              nb[N_AX] = vax > nb[N_AX] ? vax : nb[N_AX];
-              nb[N_Z] = vz > nb[N_Z] ? vz : nb[N_Z];
+              for (int off = 1; off < 16; off <<= 1) {
+                const uint64_t o = __shfl_xor(x, off, 64);
+                x = o > x ? o : x;
+              }
+              nb[q] = x;
+            }
+            if (valid_i && (lane % 16) == 0) {
+#pragma unroll
+              for (int q = 0; q < 7; ++q)
+                if (nb[q]) atomicMax(a.norms + b * 8 + q, (unsigned long long)nb[q]);
             }
           }
-          // lanes with the same lane / 32 hold the same instance row: reduce over lane % 32
-#pragma unroll
-          for (int q = 0; q < 7; ++q) {
-            uint64_t x = nb[q];
-#pragma unroll
-            for (int off = 1; off < 32; off <<= 1) {
-              const uint64_t o = __shfl_xor(x, off, 64);
-              x = o > x ? o : x;
-            }
-            nb[q] = x;
-          }
-          if (valid_i && (lane % 32) == 0) {
-            const long b = s_list[ti];
-#pragma unroll
-            for (int q = 0; q < 7; ++q)
-              if (nb[q]) atomicMax(a.norms + b * 8 + q, (unsigned long long)nb[q]);
-          }
-        }
       }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
@@ -819,9 +905,16 @@ BatchPlan plan_batch(int prec, int tn) {
   } else if (prec == kBatchF32 && tn == 64) {
     fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 64>);
     smem = sizeof(Smem<kBatchF32, 64>);
+  } else if (prec == kBatchBF16x3 && tn == 256) {
+    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 256>);
+    smem = sizeof(Smem<kBatchBF16x3, 256>);
+  } else if (prec == kBatchF32 && tn == 256) {
+    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 256>);
+    smem = sizeof(Smem<kBatchF32, 256>);
   } else {
     return p;
   }
+  smem = smem > sizeof(Smem64) ? smem : sizeof(Smem64);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return p;
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return p;
@@ -961,6 +1054,15 @@ __global__ void split_kernel(long rows, int cols, const double* __restrict__ src
   hi[idx] = h;
   lo[idx] = bf16_bits((float)diff);
 }
+__global__ void pad64_kernel(long rows, int cols, const double* __restrict__ src, long ld_src,
+                             double* __restrict__ dst, long lpad, long ldk) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= lpad * ldk) return;
+  const long blk = idx / (lpad * TK), rem = idx % (lpad * TK);
+  const long r = rem / TK;
+  const int c = (int)(blk * TK + rem % TK);
+  dst[idx] = (r < rows && c < cols) ? src[r * ld_src + c] : 0.0;
+}
 __global__ void pad_kernel(long rows, int cols, const double* __restrict__ src, long ld_src, float* __restrict__ dst,
                            long lpad, long ldk) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -978,6 +1080,14 @@ hipError_t split_bf16(long rows, int cols, const double* src, long ld_src, void*
   const long total = lpad * ldk;
   hipLaunchKernelGGL(split_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, src, ld_src,
                      static_cast<unsigned short*>(hi), static_cast<unsigned short*>(lo), lpad, ldk);
+  return hipGetLastError();
+}
+
+hipError_t pad_f64(long rows, int cols, const double* src, long ld_src, double* dst, long lpad, long ldk,
+                   hipStream_t st) {
+  const long total = lpad * ldk;
+  hipLaunchKernelGGL(pad64_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, cols, src, ld_src,
+                     dst, lpad, ldk);
   return hipGetLastError();
 }
 

@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -119,15 +121,13 @@ struct relu_qp_handle {
   long ldk = 0, lpad = 0, bpad = 0;
   void* bWa = nullptr;
   void* bWb = nullptr;
-  void* bCa = nullptr;
-  void* bCb = nullptr;
+  double* bCd = nullptr;  // FP64 check matrix, K-blocked
   float* bX = nullptr;
   float* bZ = nullptr;
   float* bY = nullptr;
   void* bVa = nullptr;
   void* bVb = nullptr;
-  void* bCVa = nullptr;
-  void* bCVb = nullptr;
+  double* bCVd = nullptr;  // FP64 check operand [x; y], K-blocked
   int* bjb = nullptr;
   unsigned long long* bnorms = nullptr;
   int* blists = nullptr;
@@ -138,8 +138,9 @@ struct relu_qp_handle {
   int* biter = nullptr;     // iterations since admission
   float* bstage = nullptr;  // warm-start staging: n + m floats and one int
   rqp::BatchPlan bplan{};            // the tile shape in use
-  rqp::BatchPlan bplans[2]{};        // tile rows 128 and 64
-  double tile_us[2] = {0.0, 0.0};    // autotuner: microseconds per iteration of each shape
+  rqp::BatchPlan bplans[rqp::kTileShapes]{};  // tile rows rqp::kTileRows (128, 64, 256)
+  double tile_us[rqp::kTileShapes] = {};      // autotuner: microseconds per iteration of each shape
+  bool tile_cached = false;          // the choice came from the autotuner's cache
   size_t dev_bytes = 0;              // requested bytes of the resident device allocations
   // every resident device allocation (the handle field that holds it, its size, and its pinned
   // host copy once the handle has been offloaded)
@@ -158,8 +159,8 @@ void free_handle(relu_qp_handle* h) {
   if (!h) return;
   void* ptrs[] = {h->W,    h->C,    h->q,    h->l,    h->u,     h->eq_d,   h->grid_d,  h->mid_d,
                   h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs, h->scl, h->Wp, h->xwp,
-                  h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCa,     h->bCb,
-                  h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVa,   h->bCVb,    h->bjb,
+                  h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCd,
+                  h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVd,   h->bjb,
                   h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -539,11 +540,9 @@ int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hip
       HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, reinterpret_cast<float*>(static_cast<char*>(h->bWa) + off), h->lpad,
                                h->ldk, st));
   }
+  // the check matrix stays FP64 (the residuals are FP64 evaluations of the iterates)
   HIP_OR_FAIL(rqp::assemble_check<double>(n, m, P_d.d(), A_d.d(), Wd.d(), L, st));
-  if (h->bprec == rqp::kBatchBF16x3)
-    HIP_OR_FAIL(rqp::split_bf16(L, L, Wd.d(), L, h->bCa, h->bCb, h->lpad, h->ldk, st));
-  else
-    HIP_OR_FAIL(rqp::pad_f32(L, L, Wd.d(), L, static_cast<float*>(h->bCa), h->lpad, h->ldk, st));
+  HIP_OR_FAIL(rqp::pad_f64(L, L, Wd.d(), L, h->bCd, h->lpad, h->ldk, st));
   int hinfo = 0;
   HIP_OR_FAIL(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OR_FAIL(hipStreamSynchronize(st));
@@ -569,15 +568,15 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   h->w_stride = h->lpad * h->ldk;
   const size_t es = h->bprec == rqp::kBatchBF16x3 ? 2 : 4;
   const size_t nr = h->grid.size();
-  const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->w_stride * es;
-  const size_t vbytes = (size_t)h->bpad * h->ldk * es;
+  const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->w_stride * 8;
+  const size_t vbytes = (size_t)h->bpad * h->ldk * es, cvbytes = (size_t)h->bpad * h->ldk * 8;
   const size_t ntile_max = (size_t)B / rqp::kTileM + nr + 1;
   auto al = [h](void** p, size_t bytes) { return dmalloc(h, p, bytes) == hipSuccess; };
   const bool two = h->bprec == rqp::kBatchBF16x3;
-  if (!al(&h->bWa, wbytes) || (two && !al(&h->bWb, wbytes)) || !al(&h->bCa, cbytes) || (two && !al(&h->bCb, cbytes)) ||
+  if (!al(&h->bWa, wbytes) || (two && !al(&h->bWb, wbytes)) || !al((void**)&h->bCd, cbytes) ||
       !al((void**)&h->bX, (size_t)B * n * 4) || !al((void**)&h->bZ, (size_t)B * m * 4) ||
       !al((void**)&h->bY, (size_t)B * m * 4) || !al(&h->bVa, 2 * vbytes) || (two && !al(&h->bVb, 2 * vbytes)) ||
-      !al(&h->bCVa, vbytes) || (two && !al(&h->bCVb, vbytes)) || !al((void**)&h->bjb, (size_t)B * 4) ||
+      !al((void**)&h->bCVd, cvbytes) || !al((void**)&h->bjb, (size_t)B * 4) ||
       !al((void**)&h->bnorms, (size_t)B * 8 * 8) || !al((void**)&h->blists, (size_t)B * 4) ||
       !al((void**)&h->bpos, (size_t)B * 4) ||
       !al((void**)&h->bmtiles, (1 + 3 * ntile_max) * 4) || !al((void**)&h->bbar, 1024 * 4) ||
@@ -590,8 +589,7 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   // operand padding columns must read as zero
   HIP_OR_FAIL(hipMemset(h->bVa, 0, 2 * vbytes));
   if (two) HIP_OR_FAIL(hipMemset(h->bVb, 0, 2 * vbytes));
-  HIP_OR_FAIL(hipMemset(h->bCVa, 0, vbytes));
-  if (two) HIP_OR_FAIL(hipMemset(h->bCVb, 0, vbytes));
+  HIP_OR_FAIL(hipMemset(h->bCVd, 0, cvbytes));
   HIP_OR_FAIL(hipMemset(h->bnorms, 0, (size_t)B * 64));
   HIP_OR_FAIL(hipMemset(h->biter, 0, (size_t)B * 4));
   HIP_OR_FAIL(hipMemset(h->bX, 0, (size_t)B * n * 4));
@@ -606,9 +604,10 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
       (rc = upload_f32(static_cast<float*>(h->u), u, (size_t)B * m)))
     return rc;
   if ((rc = build_batch_weights(h, P, A, st))) return rc;
-  h->bplans[0] = rqp::plan_batch(h->bprec, 128);
-  h->bplans[1] = rqp::plan_batch(h->bprec, 64);
-  if (!h->bplans[0].fn || !h->bplans[1].fn) return fail(RQP_EHIP, "no resources for the batched kernel");
+  for (int v = 0; v < rqp::kTileShapes; ++v) {
+    h->bplans[v] = rqp::plan_batch(h->bprec, rqp::kTileRows[v]);
+    if (!h->bplans[v].fn) return fail(RQP_EHIP, "no resources for the batched kernel (%d-row tiles)", rqp::kTileRows[v]);
+  }
   h->bplan = h->bplans[0];
   return autotune_tiles(h, st);
 }
@@ -633,8 +632,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.Wa = h->bWa;
   a.Wb = h->bWb;
   a.w_stride = h->w_stride;
-  a.Ca = h->bCa;
-  a.Cb = h->bCb;
+  a.Cd = h->bCd;
   a.Q = static_cast<const float*>(h->q);
   a.Lo = static_cast<const float*>(h->l);
   a.Up = static_cast<const float*>(h->u);
@@ -657,8 +655,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.Y = h->bY;
   a.Va = h->bVa;
   a.Vb = h->bVb;
-  a.CVa = h->bCVa;
-  a.CVb = h->bCVb;
+  a.CVd = h->bCVd;
   a.jb = h->bjb;
   a.status = h->bstatus;
   a.iterations = h->biter;
@@ -689,14 +686,49 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
 // events; the faster one is kept. Slots, statuses and state are reset to idle afterwards. The
 // shapes agree to rounding (every accumulator element sees the same products, in another
 // interleaving on the matrix cores): few tiles (small batches) favour 64 rows, many 128.
+// The choice is cached per process and device for the problem shape (n, m, batch, precision,
+// penalties): a family loaded again (or another handle of the same shape) takes the cached
+// choice and timings without timing again.
+struct TileKey {
+  int dev, n, m, B, prec, n_rho;
+  bool operator<(const TileKey& o) const {
+    return std::tie(dev, n, m, B, prec, n_rho) < std::tie(o.dev, o.n, o.m, o.B, o.prec, o.n_rho);
+  }
+};
+struct TileChoice {
+  int best;
+  double us[rqp::kTileShapes];
+};
+std::mutex g_tile_mu;
+std::map<TileKey, TileChoice> g_tile_cache;
+
+// The shape with the fewest microseconds per iteration (ties to the earlier candidate).
+int best_tile(const relu_qp_handle* h) {
+  int best = 0;
+  for (int v = 1; v < rqp::kTileShapes; ++v)
+    if (h->tile_us[v] < h->tile_us[best]) best = v;
+  return best;
+}
+
 int autotune_tiles(relu_qp_handle* h, hipStream_t st) {
   const int B = h->batch, steps = 2 * h->s.check_interval;
+  const TileKey key{h->device, h->n, h->m, B, h->bprec, (int)h->grid.size()};
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    const auto it = g_tile_cache.find(key);
+    if (it != g_tile_cache.end()) {
+      for (int v = 0; v < rqp::kTileShapes; ++v) h->tile_us[v] = it->second.us[v];
+      h->bplan = h->bplans[it->second.best];
+      h->tile_cached = true;
+      return RQP_OK;
+    }
+  }
   hipEvent_t e0, e1;
   HIP_OR_FAIL(hipEventCreate(&e0));
   HIP_OR_FAIL(hipEventCreate(&e1));
   relu_qp_result tmp{h->bX, h->bY, h->bZ, h->biter, h->bstatus, h->bjb, nullptr, nullptr, nullptr};
   int rc = RQP_OK;
-  for (int v = 0; v < 2 && rc == RQP_OK; ++v) {
+  for (int v = 0; v < rqp::kTileShapes && rc == RQP_OK; ++v) {
     h->bplan = h->bplans[v];
     float best = 1e30f;
     for (int rep = 0; rep < 2 && rc == RQP_OK; ++rep) {  // the first run also warms caches
@@ -720,7 +752,14 @@ int autotune_tiles(relu_qp_handle* h, hipStream_t st) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  h->bplan = h->tile_us[1] < h->tile_us[0] ? h->bplans[1] : h->bplans[0];
+  const int best = best_tile(h);
+  h->bplan = h->bplans[best];
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    TileChoice c{best, {}};
+    for (int v = 0; v < rqp::kTileShapes; ++v) c.us[v] = h->tile_us[v];
+    g_tile_cache[key] = c;
+  }
   // back to idle slots with a zero state
   std::vector<int> j0(B, h->j0);
   HIP_OR_FAIL(rqp::fill_status(B, rqp::kSlotIdle, h->bstatus, st));
@@ -1484,20 +1523,20 @@ int relu_qp_get_tile(const relu_qp_handle* h, int* tile_rows, double* us_per_ite
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (!h->batched) return fail(RQP_ESTATE, "tile shapes exist only with the batched engine");
   if (tile_rows) *tile_rows = h->bplan.tn;
-  if (us_per_iter) {
-    us_per_iter[0] = h->tile_us[0];
-    us_per_iter[1] = h->tile_us[1];
-  }
+  if (us_per_iter)
+    for (int v = 0; v < rqp::kTileShapes; ++v) us_per_iter[v] = h->tile_us[v];
   return RQP_OK;
 }
 
 int relu_qp_set_tile(relu_qp_handle* h, int tile_rows) {
   if (!h) return fail(RQP_ESTATE, "NULL handle");
   if (!h->batched) return fail(RQP_ESTATE, "tile shapes exist only with the batched engine");
-  if (tile_rows == 128) h->bplan = h->bplans[0];
-  else if (tile_rows == 64) h->bplan = h->bplans[1];
-  else if (tile_rows == 0) h->bplan = h->tile_us[1] < h->tile_us[0] ? h->bplans[1] : h->bplans[0];
-  else return fail(RQP_EINVAL, "tile_rows must be 128, 64 or 0 (the autotuner's choice)");
+  int v = -1;
+  for (int c = 0; c < rqp::kTileShapes; ++c)
+    if (tile_rows == rqp::kTileRows[c]) v = c;
+  if (tile_rows == 0) v = best_tile(h);
+  if (v < 0) return fail(RQP_EINVAL, "tile_rows must be 128, 64, 256 or 0 (the autotuner's choice)");
+  h->bplan = h->bplans[v];
   return RQP_OK;
 }
 
@@ -1607,7 +1646,8 @@ int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* b
     const size_t w_stride = lpad * ldk, vbytes = bpad * ldk * es;
     const size_t ntile_max = B / rqp::kTileM + nr + 1;
     const size_t nw = two ? 2 : 1;
-    t += nw * (nr * w_stride * es + w_stride * es + 3 * vbytes);  // layer and check weights, V, CV
+    t += nw * (nr * w_stride * es + 2 * vbytes);                   // layer weights, V (two parities)
+    t += w_stride * 8 + bpad * ldk * 8;                            // FP64 check matrix and operand
     t += B * n * 4 + 2 * B * m * 4;                                // x, z, y
     t += B * 4 + B * 64 + B * 4 + B * 4;                           // penalty index, norms, lists, positions
     t += (1 + 3 * ntile_max) * 4 + 1024 * 4;                       // tile lists, barrier words

@@ -319,11 +319,12 @@ class Solver:
         return t, res
 
     def tile(self):
-        """(tile rows in use, {128: us/iter, 64: us/iter} from the autotuner) of a batched handle."""
+        """(tile rows in use, {128: us/iter, 64: us/iter, 256: us/iter} from the autotuner) of a
+        batched handle."""
         t = c_int()
-        us = (c_double * 2)()
+        us = (c_double * 3)()
         check(lib().relu_qp_get_tile(self._h, byref(t), us))
-        return t.value, {128: us[0], 64: us[1]}
+        return t.value, {128: us[0], 64: us[1], 256: us[2]}
 
     def offload(self):
         """Move the handle's device memory to pinned host memory (the result tensors stay)."""

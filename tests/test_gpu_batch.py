@@ -13,6 +13,7 @@ import oracle
 from oracle import admm
 from oracle.mpc_update import qp_vectors
 from workloads import make_config, random_qp, x0_batch
+from residual_check import assert_passes_fp64_test
 
 pytestmark = pytest.mark.gpu
 
@@ -73,9 +74,9 @@ def test_batch_several_tiles(rq, prec, m_eq):
     schedules replayed.
 
     With equality rows the dual update y = rho (t - z) multiplies the rounding of t by
-    rho_eq = 1000 rho: in FP32 the y of those rows carries errors of order
-    rho_eq * 2^-24 * max|t| per iteration (a plain FP32 emulation on the CPU shows 1e-4..2e-3
-    relative here), so y gets the tolerance scaled by rho_max * max(|z|, 1) / max(|y|, 1).
+    rho_eq = 1000 rho: the iteration holds y_i / rho_i to the FP32 precision, so the y of those
+    rows is compared at tol * rho_i * max(|z|, 1) (rho_i the largest penalty of the replayed
+    schedule on that row), the other rows at the usual tol * max(|y|, 1).
     """
     P, q0, A, l0, u0 = random_qp(150, m_eq, 80 - m_eq, seed=21)
     B = 300
@@ -94,13 +95,20 @@ def test_batch_several_tiles(rq, prec, m_eq):
         hist = res["rho_hist"][b][:3].tolist()
         ref = oracle.solve(P, q[b], A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60),
                            rho_replay=hist)
-        rho_max = max(grid[j] for j in hist + [2]) * (1e3 if m_eq else 1.0)
-        kappa = max(1.0, rho_max * max(np.max(np.abs(ref.z)), 1.0) / max(np.max(np.abs(ref.y)), 1.0))
-        for name in ("x", "z", "y"):
+        for name in ("x", "z"):
             e = _rel(res[name][b], getattr(ref, name))
-            t = tol * (kappa if (name == "y" and m_eq) else 1.0)
             worst[name] = max(worst.get(name, 0.0), e)
-            assert e <= t, (prec, m_eq, b, name, e, t)
+            assert e <= tol, (prec, m_eq, b, name, e, tol)
+        eq = l[b] == u[b]
+        dy = np.abs(res["y"][b] - ref.y)
+        e_in = np.max(dy[~eq]) / max(np.max(np.abs(ref.y)), 1.0)
+        worst["y"] = max(worst.get("y", 0.0), e_in)
+        assert e_in <= tol, (prec, m_eq, b, "y", e_in)
+        if eq.any():
+            rho_eq = max(grid[j] for j in hist + [2]) * 1e3
+            e_eq = np.max(dy[eq]) / (rho_eq * max(np.max(np.abs(ref.z)), 1.0))
+            worst["y_eq / rho"] = max(worst.get("y_eq / rho", 0.0), e_eq)
+            assert e_eq <= tol, (prec, m_eq, b, "y equality rows / rho", e_eq)
     print(f"\n{prec} m_eq={m_eq}: worst relative errors " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()))
 
 
@@ -136,9 +144,7 @@ def test_batch_solves_to_tolerance(rq, prec):
     assert np.all(res["status"] == rq.RQP_SOLVED)
     errs = []
     for b in range(0, B, 9):
-        nm = admm.residual_norms(prob.P, q[b], prob.A, res["x"][b], res["z"][b], res["y"][b])
-        assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
-        assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+        assert_passes_fp64_test(prob.P, q[b], prob.A, res["x"][b], res["z"][b], res["y"][b], what=f"instance {b}")
         xs = oracle.solve(prob.P, q[b], prob.A, l[b], u[b], _os(eps_abs=1e-10, eps_rel=1e-10, n_rho=8,
                                                                 max_iter=40000)).x
         errs.append(_rel(res["x"][b], xs))
@@ -209,9 +215,7 @@ def test_batch_ragged_tiles_mixed_statuses(rq):
     assert np.all(res["status"] == rq.RQP_SOLVED)
     assert len(set(res["iterations"].tolist())) > 1, "expected instances to finish at different checks"
     for b in list(range(0, B, 16)) + [B - 1]:
-        nm = admm.residual_norms(P, q[b], A, res["x"][b], res["z"][b], res["y"][b])
-        assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
-        assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+        assert_passes_fp64_test(P, q[b], A, res["x"][b], res["z"][b], res["y"][b], what=f"instance {b}")
         it = int(res["iterations"][b])
         ref = oracle.solve(P, q[b], A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=it),
                            rho_replay=res["rho_hist"][b][: it // 25].tolist())
@@ -221,7 +225,7 @@ def test_batch_ragged_tiles_mixed_statuses(rq):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
-    """The autotuner times both tile shapes at setup and keeps the faster; each shape, forced,
+    """The autotuner times every tile shape at setup and keeps the fastest; each shape, forced,
     matches the oracle with its own schedule replayed. (The shapes agree to rounding only: the
     matrix cores are fed the same products per element, but in another interleaving.)"""
     P, q0, A, l0, u0 = random_qp(150, 0, 80, seed=41)
@@ -232,10 +236,10 @@ def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
     u = np.repeat(u0[None, :], B, axis=0)
     sol = rq.Solver(P, q, A, l, u, precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60)
     tn, us = sol.tile()
-    assert tn in (64, 128) and us[128] > 0 and us[64] > 0
-    assert tn == (64 if us[64] < us[128] else 128)
+    assert tn in (64, 128, 256) and all(us[k] > 0 for k in (64, 128, 256))
+    assert us[tn] == min(us.values())
     tol = 1e-4 if prec == "fp32" else 5e-3
-    for shape in (128, 64):
+    for shape in (128, 64, 256):
         sol.set_tile(shape)
         assert sol.tile()[0] == shape
         sol.solve()
@@ -246,6 +250,10 @@ def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
             for name in ("x", "z", "y"):
                 assert _rel(res[name][b], getattr(ref, name)) <= tol, (prec, shape, b, name)
     sol.close()
+    # a second handle of the same shape takes the cached choice: the very same timings, no new run
+    again = rq.Solver(P, q, A, l, u, precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60)
+    assert again.tile() == (tn, us)
+    again.close()
     print(f"\n{prec}: autotuner us/iteration {us}, chose {tn}")
 
 
@@ -265,7 +273,7 @@ def test_batch_full_size_configuration_3(rq, prec, tol):
     sol.close()
     cache = {}
     worst = 0.0
-    for b in (0, 2047, B - 1):
+    for b in (0, 511, 1024, 1777, 2047, 2900, 3583, B - 1):
         ref = oracle.solve(prob.P, q[b], prob.A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=100),
                            rho_replay=res["rho_hist"][b][:4].tolist(), cache=cache)
         assert res["iterations"][b] == 100
@@ -278,10 +286,8 @@ def test_batch_full_size_configuration_3(rq, prec, tol):
     res = sol.result()
     sol.close()
     assert np.all(res["status"] == rq.RQP_SOLVED)
-    for b in (5, 3000):
+    for b in range(5, B, 511):
         x, z, y = (res[k][b].astype(np.float64) for k in ("x", "z", "y"))
-        nm = admm.residual_norms(prob.P, q[b], prob.A, x, z, y)
-        assert nm["r_p"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Ax"], nm["z"]))
-        assert nm["r_d"] <= 1.5 * (1e-3 + 1e-3 * max(nm["Px"], nm["Aty"], nm["q"]))
+        assert_passes_fp64_test(prob.P, q[b], prob.A, x, z, y, what=f"instance {b}")
     print(f"\n{prec} B={B}: worst sampled per-vector error after 100 iterations {worst:.3e}; "
           f"mean iterations to 1e-3 {np.mean(res['iterations']):.1f}")

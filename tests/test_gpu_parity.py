@@ -90,13 +90,24 @@ def test_c0_adaptive_rho_replayed(rq, c0, prec):
         # resolvable; once both sit at rounding level (about 1e-15 here) the ratio in the
         # penalty rule is rounding noise and either choice is valid.
         own = oracle.solve(prob.P, q, prob.A, l, u,
-                           _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=300, n_rho=8))
+                           _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=300, n_rho=8), record=True)
         resolvable = [c for c in range(len(own.rho_hist)) if min(own.prim_res[c], own.dual_res[c]) > 1e-10]
         assert len(resolvable) >= 4
         last = resolvable[-1]
         assert own.rho_hist[: last + 1] == res["rho_hist"][: last + 1]
-        np.testing.assert_allclose(res["prim_res"][: last + 1], own.prim_res[: last + 1], rtol=1e-5)
-        np.testing.assert_allclose(res["dual_res"][: last + 1], own.dual_res[: last + 1], rtol=1e-5)
+        # the residuals are FP64 evaluations of iterates that agree to the per-iterate tolerance
+        # (1e-9 relative), so they agree to 1e-7 relative plus 1e-9 times the row sums of |P|,
+        # |A| and |A'| scaled by max(||v||, 1) at that check
+        aP, aA = np.abs(prob.P), np.abs(prob.A)
+        for c in range(len(own.prim_res)):
+            if own.rho_hist[:c] != res["rho_hist"][:c]:
+                break  # past the resolvable checks the two may take other (equally valid) penalties
+            x, z, y = own.history[25 * (c + 1) - 1]
+            sx, sy = max(np.max(np.abs(x)), 1.0), max(np.max(np.abs(y)), 1.0)
+            bp = 1e-9 * (np.max(aA.sum(axis=1)) * sx + max(np.max(np.abs(z)), 1.0))
+            bd = 1e-9 * np.max(aP.sum(axis=1) * sx + aA.sum(axis=0) * sy)
+            assert abs(res["prim_res"][c] - own.prim_res[c]) <= 1e-7 * own.prim_res[c] + bp, c
+            assert abs(res["dual_res"][c] - own.dual_res[c]) <= 1e-7 * own.dual_res[c] + bd, c
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -431,10 +442,13 @@ def test_wide_rows_streamed_fp32(rq):
                        rho_replay=res["rho_hist"])
     _close(res["x"], ref.x, 1e-4, "x")
     _close(res["z"], ref.z, 1e-4, "z")
-    # y of the equality rows carries rho_eq * FP32 rounding (see the batched multi-tile test)
-    kappa = max(1.0, max(admm.rho_grid(_oracle_settings(n_rho=8))[j] for j in res["rho_hist"] + [2]) * 1e3
-                * max(np.max(np.abs(ref.z)), 1.0) / max(np.max(np.abs(ref.y)), 1.0))
-    _close(res["y"], ref.y, 1e-4 * kappa, "y")
+    # the iteration holds y_i / rho_i to FP32 precision: equality rows (rho_i = 1000 rho) are
+    # compared at 1e-4 rho_i max(|z|, 1), the others at 1e-4 max(|y|, 1)
+    eq = l == u
+    dy = np.abs(res["y"] - ref.y)
+    assert np.max(dy[~eq]) <= 1e-4 * max(np.max(np.abs(ref.y)), 1.0)
+    rho_eq = max(admm.rho_grid(_oracle_settings(n_rho=8))[j] for j in res["rho_hist"] + [2]) * 1e3
+    assert np.max(dy[eq]) <= 1e-4 * rho_eq * max(np.max(np.abs(ref.z)), 1.0)
 
 
 def test_c2_humanoid_shape_fp32(rq):
