@@ -151,6 +151,30 @@ class Family:
         self.solver, self.single, self.spilled = None, None, False
 
 
+def _staging(fam, name: str, rows: int, nx: int, device):
+    """A family's pinned host buffer and device buffer of at least ``rows`` x0 rows (FP64),
+    allocated once and kept with the family."""
+    key = "_stage_" + name
+    have = fam.__dict__.get(key)
+    if have is None or have[0].shape[0] < rows:
+        have = (torch.empty(rows, nx, dtype=torch.float64, pin_memory=True),
+                torch.empty(rows, nx, dtype=torch.float64, device=device))
+        fam.__dict__[key] = have
+    return have
+
+
+def _staging_results(fam, name: str, rows: int, solver):
+    """Pinned host buffers for ``rows`` results (status, iterations, x) of a family."""
+    key = "_res_" + name
+    have = fam.__dict__.get(key)
+    if have is None or have["status"].shape[0] < rows:
+        have = dict(status=torch.empty(rows, dtype=torch.int32, pin_memory=True),
+                    iterations=torch.empty(rows, dtype=torch.int32, pin_memory=True),
+                    x=torch.empty(rows, solver.n, dtype=solver.dtype, pin_memory=True))
+        fam.__dict__[key] = have
+    return have
+
+
 class MemoryPolicy:
     """Which families are resident under an HBM budget (host logic only).
 
@@ -253,12 +277,26 @@ class Server:
         self.memory.peak = self.memory.used(families)
 
     def _light_step(self, fam: Family):
-        """Solve the family's whole (short) queue in one single-instance sequence launch."""
+        """Solve the family's whole (short) queue in one single-instance sequence launch. The x0
+        go through a pinned staging buffer, and the result tensors of each sequence length are
+        allocated once per family (no fill kernels or allocations per request)."""
         reqs = list(fam.queue)
         fam.queue.clear()
-        x0 = torch.tensor(np.stack([r.x0 for r in reqs]), dtype=torch.float64, device=fam.single.device)
-        out = fam.single.solve_sequence(x0)
-        return reqs, out
+        k = len(reqs)
+        host, dev = _staging(fam, "light", self.light, fam.nx, fam.single.device)
+        for i, r in enumerate(reqs):
+            host[i].copy_(torch.from_numpy(r.x0))
+        dev[:k].copy_(host[:k], non_blocking=True)
+        outs = fam.__dict__.setdefault("_seq_out", {})
+        if k not in outs:
+            outs[k] = fam.single.sequence_slots(k)
+        out = fam.single.solve_sequence(dev[:k], out=outs[k])
+        # results come back through pinned buffers, read after the tick's synchronisation
+        res = _staging_results(fam, "light", self.light, fam.single)
+        res["status"][:k].copy_(out["status"], non_blocking=True)
+        res["iterations"][:k].copy_(out["iterations"], non_blocking=True)
+        res["x"][:k].copy_(out["x"], non_blocking=True)
+        return reqs, res
 
     def _admit(self, fam: Family):
         k = min(len(fam.queue), len(fam.free))
@@ -266,8 +304,11 @@ class Server:
             return
         reqs = [fam.queue.popleft() for _ in range(k)]
         slots = [fam.free.pop() for _ in range(k)]
-        x0 = torch.tensor(np.stack([r.x0 for r in reqs]), dtype=torch.float64, device=fam.solver.device)
-        fam.solver.load_slots_x0(slots, x0)
+        host, dev = _staging(fam, "admit", fam.spec["slots"], fam.nx, fam.solver.device)
+        for i, r in enumerate(reqs):
+            host[i].copy_(torch.from_numpy(r.x0))
+        dev[:k].copy_(host[:k], non_blocking=True)
+        fam.solver.load_slots_x0(slots, dev[:k])
         src = fam.pin if (self.warm and fam.pin is not None) else -1
         fam.solver.admit(slots, src_slot=src, shift_x=fam.stage, shift_y=fam.stage)
         for s, r in zip(slots, reqs):
@@ -276,12 +317,13 @@ class Server:
     def _retire(self, fam: Family, now: float):
         if not fam.busy:
             return
-        status = fam.solver.status.cpu().numpy()
-        iters = fam.solver.iterations.cpu().numpy()
+        res = _staging_results(fam, "slots", fam.spec["slots"], fam.solver)
+        status = res["status"].numpy()
+        iters = res["iterations"].numpy()
         done = [s for s in fam.busy if status[s] != RQP_RUNNING]
         if not done:
             return
-        xs = fam.solver.x.cpu().numpy() if getattr(fam, "keep_x", False) else None
+        xs = res["x"].numpy() if getattr(fam, "keep_x", False) else None
         for s in done:
             r = fam.busy.pop(s)
             r.t_done, r.status, r.iterations = now, int(status[s]), int(iters[s])
@@ -324,12 +366,17 @@ class Server:
                 if fam.busy:
                     fam.solver.step(self.n_checks)
                     fam.last_used = now
+            for fam in self.families:
+                if fam.busy:  # slot states and counts to pinned buffers, read after the sync
+                    res = _staging_results(fam, "slots", fam.spec["slots"], fam.solver)
+                    res["status"].copy_(fam.solver.status, non_blocking=True)
+                    res["iterations"].copy_(fam.solver.iterations, non_blocking=True)
+                    if getattr(fam, "keep_x", False):
+                        res["x"].copy_(fam.solver.x, non_blocking=True)
             torch.cuda.synchronize()
             now = time.perf_counter() - t0
-            for reqs, out in light:
-                st = out["status"].cpu().numpy()
-                it = out["iterations"].cpu().numpy()
-                xs = out["x"].cpu().numpy()
+            for reqs, res in light:
+                st, it, xs = res["status"].numpy(), res["iterations"].numpy(), res["x"].numpy()
                 for i, r in enumerate(reqs):
                     r.t_done, r.status, r.iterations = now, int(st[i]), int(it[i])
                     r.x = xs[i].astype(np.float64)
