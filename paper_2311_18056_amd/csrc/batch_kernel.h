@@ -32,13 +32,15 @@ struct BatchArgs {
   // rows is at ((c / kTileK) * rows + row) * kTileK + c % kTileK, so one K stage of a tile is
   // one contiguous block. ldk = columns (multiple of kTileK, with zero padding).
   long ldk;
-  long lpad;                // padded rows of the weight and check matrices (multiple of kTileN)
+  long lpad;                // padded rows of the layer matrices (multiple of kTileN)
+  long cpad;                // padded rows of the check matrix (at least L + 128: constraint-row
+                            // tiles start at row n)
   long bpad;                // padded rows (list positions) of the operands V and CV
   int prec;                 // BatchPrec
   const void* Wa;           // FP32 layer matrices, or BF16 high parts: n_rho blocked lpad x ldk
   const void* Wb;           // BF16 low parts (kBatchBF16x3), else null
   long w_stride;            // elements between penalty matrices
-  const double* Cd;         // check matrix [P, A'; A, 0] in FP64, same format (blocked lpad x ldk)
+  const double* Cd;         // check matrix [P, A'; A, 0] in FP64, same format (blocked cpad x ldk)
   const float* Q;           // B x n
   const float* Lo;          // B x m
   const float* Up;          // B x m
@@ -57,6 +59,8 @@ struct BatchArgs {
   void* Va;                 // layer inputs, 2 parities x blocked bpad x ldk (FP32, or BF16 high)
   void* Vb;                 // BF16 low parts
   double* CVd;              // check operand [x; y] in FP64 (exact copies of the FP32 iterates), blocked bpad x ldk
+  double* Rpx;              // B x n: P x of list position p in row p (check scratch)
+  double* Raty;             // B x n: A'y likewise
   int* jb;                  // B penalty indices (kept for running and warm-admitted slots)
   int* status;              // B slot states (kSlot* below, or a final status), persistent
   int* iterations;          // B iterations since admission, persistent

@@ -22,6 +22,8 @@
 // instances share its tiles, so a result is the same alone and in a batch.
 #include "batch_kernel.h"
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace rqp {
@@ -31,6 +33,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+
+// f(integral_constant<int, I>) for I in [I0, I1), unrolled at compile time.
+template <int I0, int I1, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I0 < I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
 
 constexpr int BS = kBatchBlock;
 constexpr int TM = kTileM, TN = kTileN, TK = kTileK;
@@ -49,7 +60,7 @@ __device__ __forceinline__ unsigned ld_acq(const unsigned* p) {
 // Counters are monotone: barrier number e completes when they reach e * size. Returns false
 // if a wait exceeded the spin bound or another workgroup gave up (bar[1] set); every
 // workgroup then leaves the kernel.
-__device__ bool grid_barrier(unsigned* bar, unsigned e) {
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned e) {
   __shared__ int ok_s;
   // every wave's stores are made visible at device scope before its workgroup arrives
   __threadfence();
@@ -101,144 +112,169 @@ __device__ __forceinline__ void put_operand(void* va, void* vb, long idx, float 
     static_cast<float*>(va)[idx] = v;
   }
 }
+// The same with a 32-bit element index (idx * 4 < 2^32).
+template <int PREC>
+__device__ __forceinline__ void put_operand32(void* va, void* vb, unsigned idx, float v) {
+  if constexpr (PREC == kBatchBF16x3) {
+    const unsigned short h = bf16_bits(v);
+    reinterpret_cast<unsigned short*>(static_cast<char*>(va) + idx * 2u)[0] = h;
+    reinterpret_cast<unsigned short*>(static_cast<char*>(vb) + idx * 2u)[0] = bf16_bits(v - bf16_float(h));
+  } else {
+    reinterpret_cast<float*>(static_cast<char*>(va) + idx * 4u)[0] = v;
+  }
+}
+
+// Element idx of an array addressed with a 32-bit byte offset (base in scalar registers, offset
+// in one vector register): the caller guarantees idx * sizeof(T) < 2^32.
+template <typename T>
+__device__ __forceinline__ T& at32(T* base, unsigned idx) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T& at32(const T* base, unsigned idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
 
 // ------------------------------------------------------------------------------------------
-// GEMM tile of TM instances x TNV matrix rows (TNV = 256, 128 or 64): four waves in a 2 x 2
-// grid, each owning 64 instances x TNV/2 rows as 2 x BJ blocks of 32 x 32 accumulators (lane
-// layout of v_mfma_f32_32x32x*). The larger tile reads fewer LDS bytes per product and fewer
-// operand bytes per flop; which wins depends on how many tiles a problem has (the autotuner). Operand A rows are list positions (instances), B rows are matrix
-// rows; both K-blocked (one K stage of a tile is one contiguous block).
-
-template <int PREC, int TNV>
-struct Smem;
-template <int TNV>
-struct Smem<kBatchBF16x3, TNV> {
-  static constexpr int kRowsA = TM / 64, kRowsB = TNV / 64;  // rows tid/4 + 64 q, 8 bf16 each
-  unsigned short a[2][2][TM][TK + PADB];                     // [stage][hi/lo][row][k]
-  unsigned short b[2][2][TNV][TK + PADB];
-};
-template <int TNV>
-struct Smem<kBatchF32, TNV> {
-  static constexpr int kRowsA = TM / 32, kRowsB = TNV / 32;  // rows tid/8 + 32 q, 4 floats each
-  float a[2][TM][TK + PADF];
-  float b[2][TNV][TK + PADF];
-};
-
-template <int PREC>
-__device__ __forceinline__ int loader_row(int q) {
-  if constexpr (PREC == kBatchBF16x3)
-    return threadIdx.x / 4 + 64 * q;
+// Operand staging. One K stage (TK = 32 columns) of a tile's operand rows goes from global
+// memory straight into LDS through global_load_lds_dwordx4, without passing through registers:
+// one wave instruction moves 64 chunks of 16 bytes to 1 KB of consecutive LDS bytes (lane i to
+// bytes 16 i). A row of the stage (32 elements: 64, 128 or 256 bytes) stays whole, and its
+// chunks are permuted by an XOR with a function of the row index (swz): lane i fetches the
+// global chunk that belongs at LDS position i. The matrix-core fragment reads (one row per
+// lane, the same chunk in all rows) then fall on distinct banks for every group of 8 or 16
+// lanes. Loads never branch: rows past a tile's valid range read valid padding rows (their
+// products land in results that are discarded).
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+template <int CPR>  // 16-byte chunks per row: 4 (BF16), 8 (FP32), 16 (FP64)
+__device__ __forceinline__ int swz(int r) {
+  if constexpr (CPR == 4)
+    return ((r >> 1) ^ (r >> 2)) & 3;
+  else if constexpr (CPR == 8)
+    return (r ^ (r >> 3)) & 7;
   else
-    return threadIdx.x / 8 + 32 * q;
+    return r & 15;
 }
-
-// One K stage of this thread's operand rows, held in registers between its global loads and
-// its LDS stores (so that the loads of the next stages are in flight during the products).
-template <int PREC, int TNV>
-struct Frag;
-template <int TNV>
-struct Frag<kBatchBF16x3, TNV> {
-  ushort8 a[2][TM / 64], b[2][TNV / 64];  // [hi/lo][row]
-};
-template <int TNV>
-struct Frag<kBatchF32, TNV> {
-  floatx4 a[TM / 32], b[TNV / 32];
-};
-
-// Loads never branch: a row outside the tile's valid range reads a valid dummy row (its
-// products land in accumulator rows or columns that are discarded).
-// aoff / boff: offsets of the thread's rows inside a K block; as / bs: elements per K block.
-template <int PREC, int TNV>
-__device__ __forceinline__ void fetch(Frag<PREC, TNV>& f, const void* Aa, const void* Ab, const void* Ba,
-                                      const void* Bb, const long (&aoff)[Smem<PREC, TNV>::kRowsA],
-                                      const long (&boff)[Smem<PREC, TNV>::kRowsB], long as, long bs, int stage) {
-  constexpr int RA = Smem<PREC, TNV>::kRowsA, RB = Smem<PREC, TNV>::kRowsB;
-  if constexpr (PREC == kBatchBF16x3) {
-    const long ka = (long)stage * as + (threadIdx.x % 4) * 8, kb = (long)stage * bs + (threadIdx.x % 4) * 8;
+// ROWS rows of one K block starting at byte address src (rows CPR * 16 bytes apart) to lds.
+template <int ROWS, int CPR>
+__device__ __forceinline__ void dma_panel(const unsigned char* src, unsigned char* lds, int wave) {
+  static_assert(ROWS * CPR % BS == 0, "a panel is a whole number of wave instructions per thread");
 #pragma unroll
-    for (int h = 0; h < RA; ++h) {
-      f.a[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Aa) + aoff[h] + ka);
-      f.a[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ab) + aoff[h] + ka);
-    }
+  for (int i = 0; i < ROWS * CPR / BS; ++i) {
+    // instruction i covers rows [i BS / CPR, (i + 1) BS / CPR): a uniform base plus a lane offset
+    const int ci = i * BS + threadIdx.x, row = ci / CPR, c = (ci % CPR) ^ swz<CPR>(row);
+    const unsigned off = (unsigned)((row - i * (BS / CPR)) * (CPR * 16) + c * 16);
+    __builtin_amdgcn_global_load_lds(src + i * BS * 16 + off, (lds_ptr_t)(lds + i * BS * 16 + wave * 1024), 16, 0, 0);
+  }
+}
+template <int CPR>
+__device__ __forceinline__ const unsigned char* frag_at(const unsigned char* panel, int row, int c) {
+  return panel + row * (CPR * 16) + 16 * (c ^ swz<CPR>(row));
+}
+// Waits until at most N vector memory operations of this wave are outstanding (loads into LDS
+// complete in issue order).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// Workgroup barrier that the compiler does not move memory operations across.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+// K loop over stages [s0, s1) with NST LDS buffers: the stages NST - 1 ahead are in flight while
+// one is multiplied; one barrier per stage (stage s has landed for every wave, and every wave is
+// done with the buffer that stage s + NST - 1 overwrites). issue(s, buf) starts the copy of
+// stage s (LOADS instructions per thread); comp(s, buf) multiplies it. On entry the LDS buffers
+// may still be read by the previous tile. Stores of the previous tile may still be in flight:
+// the vector memory counter also counts them, but they were issued before every copy of this
+// loop and copies complete in issue order, so "at most LOADS * k outstanding" still means that
+// every copy but the last k stages' has landed. Loads of the caller must be complete on entry.
+template <int NST, int LOADS, typename Issue, typename Comp>
+__device__ __forceinline__ void kloop(int s0, int s1, unsigned char* lds, int stage_bytes, Issue&& issue, Comp&& comp) {
+  static_assert(NST >= 2 && NST <= 4 && LOADS * (NST - 2) < 64, "pipeline depth");
+  lds_barrier();
 #pragma unroll
-    for (int h = 0; h < RB; ++h) {
-      f.b[0][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Ba) + boff[h] + kb);
-      f.b[1][h] = *reinterpret_cast<const ushort8*>(static_cast<const unsigned short*>(Bb) + boff[h] + kb);
-    }
-  } else {
-    const long ka = (long)stage * as + (threadIdx.x % 8) * 4, kb = (long)stage * bs + (threadIdx.x % 8) * 4;
-#pragma unroll
-    for (int h = 0; h < RA; ++h)
-      f.a[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Aa) + aoff[h] + ka);
-#pragma unroll
-    for (int h = 0; h < RB; ++h)
-      f.b[h] = *reinterpret_cast<const floatx4*>(static_cast<const float*>(Ba) + boff[h] + kb);
+  for (int p = 0; p < NST - 1; ++p)
+    if (s0 + p < s1) issue(s0 + p, lds + p * stage_bytes);
+  for (int s = s0; s < s1; ++s) {
+    const int ahead = min(s1 - 1 - s, NST - 2);  // stages issued after s
+    if (NST >= 4 && ahead >= 2)
+      wait_vm<LOADS*(NST >= 4 ? 2 : 0)>();
+    else if (NST >= 3 && ahead >= 1)
+      wait_vm<LOADS*(NST >= 3 ? 1 : 0)>();
+    else
+      wait_vm<0>();
+    lds_barrier();
+    const int q = s - s0;
+    if (s + NST - 1 < s1) issue(s + NST - 1, lds + ((q + NST - 1) % NST) * stage_bytes);
+    comp(s, lds + (q % NST) * stage_bytes);
   }
 }
 
-// LDS stores of one stage; with MASK, matrix entries with k outside [kb, ke) become zero.
-template <int PREC, int TNV, bool MASK>
-__device__ __forceinline__ void stash(Smem<PREC, TNV>& sm, int buf, const Frag<PREC, TNV>& f, int stage, int kb,
-                                      int ke) {
-  constexpr int RA = Smem<PREC, TNV>::kRowsA, RB = Smem<PREC, TNV>::kRowsB;
+// ------------------------------------------------------------------------------------------
+// Layer GEMM tile: TM instances (list positions) x TNV matrix rows (256, 128 or 64), four waves
+// in a 2 x 2 grid, each owning 64 instances x TNV/2 rows as 2 x BJ blocks of 32 x 32
+// accumulators (lane layout of v_mfma_f32_32x32x*). A stage holds the A rows (instances) then
+// the B rows (matrix rows): BF16 high and low panels of 64-byte rows, or FP32 panels of 128-byte
+// rows, (TM + TNV) x 128 bytes in both cases. A larger tile reads fewer LDS bytes per product
+// and fewer operand bytes per flop; which wins depends on how many tiles a problem has (the
+// autotuner).
+template <int TNV>
+struct LayerGeo {
+  static constexpr int BJ = TNV / 64;
+  static constexpr int STAGE = (TM + TNV) * 128;
+  static constexpr int LOADS = STAGE / 16 / BS;
+  static constexpr int NST = TNV >= 256 ? 3 : 4;
+  static constexpr size_t SMEM = (size_t)NST * STAGE;
+};
+
+template <int PREC, int TNV>
+__device__ __forceinline__ void layer_issue(const void* Aa, const void* Ab, const void* Ba, const void* Bb, long arow,
+                                            long brow, long as, long bs, int s, unsigned char* buf, int wave) {
   if constexpr (PREC == kBatchBF16x3) {
-    const int kc = (threadIdx.x % 4) * 8;
-    const int k0 = stage * TK + kc;
-#pragma unroll
-    for (int h = 0; h < RA; ++h)
-#pragma unroll
-      for (int p = 0; p < 2; ++p) *reinterpret_cast<ushort8*>(&sm.a[buf][p][loader_row<PREC>(h)][kc]) = f.a[p][h];
-#pragma unroll
-    for (int h = 0; h < RB; ++h)
-#pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        ushort8 bv = f.b[p][h];
-        if constexpr (MASK) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) bv[e] = (k0 + e >= kb && k0 + e < ke) ? bv[e] : (unsigned short)0;
-        }
-        *reinterpret_cast<ushort8*>(&sm.b[buf][p][loader_row<PREC>(h)][kc]) = bv;
-      }
+    const long ao = ((long)s * as + arow * TK) * 2, bo = ((long)s * bs + brow * TK) * 2;
+    dma_panel<TM, 4>(static_cast<const unsigned char*>(Aa) + ao, buf, wave);
+    dma_panel<TM, 4>(static_cast<const unsigned char*>(Ab) + ao, buf + TM * 64, wave);
+    dma_panel<TNV, 4>(static_cast<const unsigned char*>(Ba) + bo, buf + TM * 128, wave);
+    dma_panel<TNV, 4>(static_cast<const unsigned char*>(Bb) + bo, buf + TM * 128 + TNV * 64, wave);
   } else {
-    const int kc = (threadIdx.x % 8) * 4;
-    const int k0 = stage * TK + kc;
-#pragma unroll
-    for (int h = 0; h < RA; ++h) *reinterpret_cast<floatx4*>(&sm.a[buf][loader_row<PREC>(h)][kc]) = f.a[h];
-#pragma unroll
-    for (int h = 0; h < RB; ++h) {
-      floatx4 bv = f.b[h];
-      if constexpr (MASK) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) bv[e] = (k0 + e >= kb && k0 + e < ke) ? bv[e] : 0.0f;
-      }
-      *reinterpret_cast<floatx4*>(&sm.b[buf][loader_row<PREC>(h)][kc]) = bv;
-    }
+    const long ao = ((long)s * as + arow * TK) * 4, bo = ((long)s * bs + brow * TK) * 4;
+    dma_panel<TM, 8>(static_cast<const unsigned char*>(Aa) + ao, buf, wave);
+    dma_panel<TNV, 8>(static_cast<const unsigned char*>(Ba) + bo, buf + TM * 128, wave);
   }
 }
 
-// Products of one LDS stage into this wave's 64 x TNV/2 part.
+// Products of one stage into this wave's 64 x TNV/2 part. BF16: the three products
+// hi*hi + lo*hi + hi*lo per k step of 16; lane l reads chunk 2 kk + l / 32 of its row (8
+// elements), which is the k order of the 32x32x16 operand layout. FP32: lane l reads the chunk
+// pair (2 g + l / 32) as four floats and feeds component s to the s-th of four 32x32x2
+// products; A and B read the same chunks, so every product pairs equal k.
 template <int PREC, int TNV>
-__device__ __forceinline__ void compute(const Smem<PREC, TNV>& sm, int buf, floatx16 (&acc)[2][TNV / 64]) {
+__device__ __forceinline__ void layer_comp(const unsigned char* buf, floatx16 (&acc)[2][TNV / 64]) {
   constexpr int BJ = TNV / 64;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int wm = wave / 2, wn = wave % 2;
   if constexpr (PREC == kBatchBF16x3) {
+    const unsigned char *ah = buf, *al = buf + TM * 64, *bh = buf + TM * 128, *bl = buf + TM * 128 + TNV * 64;
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 16) {
-      const int kq = kk + 8 * (lane / 32);
-      bf16x8 fa[2][2], fb[BJ][2];  // [block][hi/lo]
+    for (int kk = 0; kk < 2; ++kk) {
+      const int c = 2 * kk + lane / 32;
+      bf16x8 fa[2][2], fb[BJ][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm * 64 + i * 32 + lane % 32;
+        fa[i][0] = *reinterpret_cast<const bf16x8*>(frag_at<4>(ah, r, c));
+        fa[i][1] = *reinterpret_cast<const bf16x8*>(frag_at<4>(al, r, c));
+      }
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
-          fa[i][p] = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const ushort8*>(&sm.a[buf][p][wm * 64 + i * 32 + lane % 32][kq]));
-#pragma unroll
-      for (int j = 0; j < BJ; ++j)
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-          fb[j][p] = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const ushort8*>(&sm.b[buf][p][wn * (TNV / 2) + j * 32 + lane % 32][kq]));
+      for (int j = 0; j < BJ; ++j) {
+        const int r = wn * (TNV / 2) + j * 32 + lane % 32;
+        fb[j][0] = *reinterpret_cast<const bf16x8*>(frag_at<4>(bh, r, c));
+        fb[j][1] = *reinterpret_cast<const bf16x8*>(frag_at<4>(bl, r, c));
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -249,149 +285,44 @@ __device__ __forceinline__ void compute(const Smem<PREC, TNV>& sm, int buf, floa
         }
     }
   } else {
+    const unsigned char *pa = buf, *pb = buf + TM * 128;
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 2) {
-      const int kq = kk + lane / 32;
-      float fa[2], fb[BJ];
+    for (int g = 0; g < 4; ++g) {
+      const int c = 2 * g + lane / 32;
+      floatx4 fa[2], fb[BJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = sm.a[buf][wm * 64 + i * 32 + lane % 32][kq];
+      for (int i = 0; i < 2; ++i) fa[i] = *reinterpret_cast<const floatx4*>(frag_at<8>(pa, wm * 64 + i * 32 + lane % 32, c));
 #pragma unroll
-      for (int j = 0; j < BJ; ++j) fb[j] = sm.b[buf][wn * (TNV / 2) + j * 32 + lane % 32][kq];
+      for (int j = 0; j < BJ; ++j)
+        fb[j] = *reinterpret_cast<const floatx4*>(frag_at<8>(pb, wn * (TNV / 2) + j * 32 + lane % 32, c));
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][s], fb[j][s], acc[i][j], 0, 0, 0);
     }
   }
 }
 
-// acc = sum over k in [kb, ke) of A[row][k] B[col][k]. Stages of TK columns are double
-// buffered in LDS and fetched into a ring of kRing (ring_of) register stages, so that the global
-// loads run kRing - 1 stages ahead of the products. The stage count is rounded up to a multiple of
-// kRing and every fetch is issued unconditionally (past the end it re-reads the last stage),
-// so every step has the same instruction stream and the wait before an LDS store covers the
-// loads of that stage only; a scheduling barrier keeps each fetch at the top of its step. The
-// extra stages lie in the operands' zero padding (or are masked).
-// The 256-row tile keeps a ring of two stages (its operand fragments take twice the registers).
-template <int TNV>
-constexpr int ring_of() {
-  return TNV > 128 ? 2 : 4;
-}
-template <int PREC, int TNV, bool MASK>
-__device__ __forceinline__ void tile_gemm(Smem<PREC, TNV>& sm, const void* Aa, const void* Ab, const void* Ba,
-                                          const void* Bb, const long (&aoff)[Smem<PREC, TNV>::kRowsA],
-                                          const long (&boff)[Smem<PREC, TNV>::kRowsB], long as, long bs, int kb,
-                                          int ke, floatx16 (&acc)[2][TNV / 64]) {
-  constexpr int kRing = ring_of<TNV>();
+// acc = sum over k in [0, L) of V[row][k] W[col][k] for the tile whose operand rows start at
+// list position arow and matrix rows at brow; V and W are zero past column L.
+template <int PREC, int TNV>
+__device__ __forceinline__ void layer_tile(unsigned char* lds, const void* Aa, const void* Ab, const void* Ba,
+                                           const void* Bb, long arow, long brow, long as, long bs, int L,
+                                           floatx16 (&acc)[2][TNV / 64]) {
+  using G = LayerGeo<TNV>;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < TNV / 64; ++j) acc[i][j] = floatx16{};
-  const int s0 = kb / TK;
-  int ns = (ke + TK - 1) / TK - s0;
-  ns = (ns + kRing - 1) / kRing * kRing;
-  // stage of visit position p (positions past the end re-read the last one)
-  auto stage = [&](int p) { return s0 + min(p, ns - 1); };
-  Frag<PREC, TNV> f[kRing];
-#pragma unroll
-  for (int r = 0; r < kRing; ++r) fetch<PREC, TNV>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(r));
-  stash<PREC, TNV, MASK>(sm, 0, f[0], stage(0), kb, ke);
-  __syncthreads();
-  for (int p = 0; p < ns; p += kRing) {
-#pragma unroll
-    for (int r = 0; r < kRing; ++r) {
-      // position p + r is in LDS buffer r & 1; f[r] is free again
-      fetch<PREC, TNV>(f[r], Aa, Ab, Ba, Bb, aoff, boff, as, bs, stage(p + r + kRing));
-      __builtin_amdgcn_sched_barrier(0);
-      compute<PREC, TNV>(sm, r & 1, acc);
-      stash<PREC, TNV, MASK>(sm, (r + 1) & 1, f[(r + 1) % kRing], stage(p + r + 1), kb, ke);
-      __syncthreads();
-    }
-  }
+    for (int j = 0; j < G::BJ; ++j) acc[i][j] = floatx16{};
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  kloop<G::NST, G::LOADS>(
+      0, (L + TK - 1) / TK, lds, G::STAGE,
+      [&](int s, unsigned char* buf) { layer_issue<PREC, TNV>(Aa, Ab, Ba, Bb, arow, brow, as, bs, s, buf, wave); },
+      [&](int, const unsigned char* buf) { layer_comp<PREC, TNV>(buf, acc); });
 }
-
-// ------------------------------------------------------------------------------------------
-// FP64 GEMM tile of the residual check and of the warm start's z = A x: T64 = 64 list positions
-// x 64 matrix rows, K in stages of TK staged through LDS (double buffered, rows padded to
-// TK + 2 doubles: the fragment reads of a half-wave hit distinct banks), four waves in a 2 x 2
-// grid, each 32 x 32 as 2 x 2 blocks of v_mfma_f64_16x16x4f64 (lane l holds A[l % 16][l / 16]
-// and B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step, and D[l / 16 + 4 v][l % 16] in element v:
-// checked on the device against a host product).
-// Products of FP64 data with FP32 iterates are exact in FP64, so the sums are FP64 dot products.
-constexpr int T64 = 64, PAD64 = 2;
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-struct Smem64 {
-  double a[2][T64][TK + PAD64];
-  double b[2][T64][TK + PAD64];
-};
-// One K stage of this thread's chunks: 4 of the operand tile and 4 of the matrix tile, two
-// doubles (16 bytes) each; chunk c = tid + 256 q covers row c / 16, columns 2 (c % 16) + {0, 1}.
-struct Frag64 {
-  double2 a[4], b[4];
-};
-__device__ __forceinline__ void fetch64(Frag64& f, const double* A, const double* Bm, long abase, long bbase, long as,
-                                        long bs, int stage) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = threadIdx.x + BS * q, row = c >> 4, kc = (c & 15) * 2;
-    f.a[q] = *reinterpret_cast<const double2*>(A + (long)stage * as + abase + (long)row * TK + kc);
-    f.b[q] = *reinterpret_cast<const double2*>(Bm + (long)stage * bs + bbase + (long)row * TK + kc);
-  }
-}
-// matrix entries with k outside [kb, ke) become zero
-__device__ __forceinline__ void stash64(Smem64& sm, int buf, const Frag64& f, int stage, int kb, int ke) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = threadIdx.x + BS * q, row = c >> 4, kc = (c & 15) * 2, k0 = stage * TK + kc;
-    double2 bv = f.b[q];
-    bv.x = (k0 >= kb && k0 < ke) ? bv.x : 0.0;
-    bv.y = (k0 + 1 >= kb && k0 + 1 < ke) ? bv.y : 0.0;
-    *reinterpret_cast<double2*>(&sm.a[buf][row][kc]) = f.a[q];
-    *reinterpret_cast<double2*>(&sm.b[buf][row][kc]) = bv;
-  }
-}
-__device__ __forceinline__ void compute64(const Smem64& sm, int buf, doublex4 (&acc)[2][2]) {
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int wm = wave / 2, wn = wave % 2;
-#pragma unroll
-  for (int kk = 0; kk < TK; kk += 4) {
-    double fa[2], fb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) fa[i] = sm.a[buf][wm * 32 + i * 16 + lane % 16][kk + lane / 16];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) fb[j] = sm.b[buf][wn * 32 + j * 16 + lane % 16][kk + lane / 16];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
-  }
-}
-// acc = sum over k in [kb, ke) of A[row][k] B[col][k] for the tile whose operand rows start at
-// element abase and matrix rows at bbase of a K block (as / bs elements per K block). The next
-// stage's loads are in flight while the current one is multiplied.
-__device__ __forceinline__ void tile_gemm64(Smem64& sm, const double* A, const double* Bm, long abase, long bbase,
-                                            long as, long bs, int kb, int ke, doublex4 (&acc)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
-  const int s0 = kb / TK, s1 = (ke + TK - 1) / TK;
-  if (s1 <= s0) return;
-  Frag64 f;
-  fetch64(f, A, Bm, abase, bbase, as, bs, s0);
-  stash64(sm, 0, f, s0, kb, ke);
-  __syncthreads();
-  for (int s = s0; s < s1; ++s) {
-    const int buf = (s - s0) & 1;
-    if (s + 1 < s1) fetch64(f, A, Bm, abase, bbase, as, bs, s + 1);
-    compute64(sm, buf, acc);
-    if (s + 1 < s1) stash64(sm, buf ^ 1, f, s + 1, kb, ke);
-    __syncthreads();
-  }
-}
-// Tile position of element v of FP64 block (i, j) for this lane: instance row, matrix column.
-__device__ __forceinline__ int acc64_row(int wm, int i, int v, int lane) { return wm * 32 + i * 16 + lane / 16 + 4 * v; }
-__device__ __forceinline__ int acc64_col(int wn, int j, int lane) { return wn * 32 + j * 16 + lane % 16; }
 
 // Position in the tile of accumulator element v of block (i, j) for this lane.
 __device__ __forceinline__ int acc_row(int wm, int i, int v, int lane) {
@@ -402,22 +333,76 @@ __device__ __forceinline__ int acc_col(int wn, int j, int lane) {
   return wn * (TNV / 2) + j * 32 + lane % 32;
 }
 
+// ------------------------------------------------------------------------------------------
+// FP64 GEMM tile of the residual check and of the warm start's z = A x: T64 = 128 list
+// positions x 128 matrix rows over one K range, four waves in a 2 x 2 grid, each 64 x 64 as
+// 4 x 4 blocks of v_mfma_f64_16x16x4f64 (lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 16 x 4 by 4 x 16 step, and D[l / 16 + 4 v][l % 16] in element v: checked on the device
+// against a host product). A stage is the A rows then the B rows, 256-byte rows, two buffers.
+// Lane group g = l / 16 reads chunk 4 h + g of its row (two doubles, k = 8 h + 2 g + {0, 1}) and
+// feeds component s to the s-th of two products, so one read serves two products. Products of
+// FP64 data with FP32 iterates are exact in FP64, so the sums are FP64 dot products.
+constexpr int T64 = 128;
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+struct CheckGeo {
+  static constexpr int STAGE = 2 * T64 * 256;
+  static constexpr int LOADS = STAGE / 16 / BS;
+  static constexpr int NST = 2;
+  static constexpr size_t SMEM = (size_t)NST * STAGE;
+};
+// acc = sum over k in [kb, ke) of A[row][k] B[col][k]; A rows start at list position arow, B rows
+// at matrix row brow (as / bs: elements per K block). Operand entries with k outside [kb, ke)
+// count as zero (the A side is masked, so a non-finite iterate outside the range does not leak
+// in through a zero matrix entry).
+__device__ __forceinline__ void check_tile(unsigned char* lds, const double* A, const double* Bm, long arow, long brow,
+                                           long as, long bs, int kb, int ke, doublex4 (&acc)[4][4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int lane = threadIdx.x % 64;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), wm = wave / 2, wn = wave % 2;
+  kloop<CheckGeo::NST, CheckGeo::LOADS>(
+      kb / TK, (ke + TK - 1) / TK, lds, CheckGeo::STAGE,
+      [&](int s, unsigned char* buf) {
+        dma_panel<T64, 16>(reinterpret_cast<const unsigned char*>(A + (long)s * as + arow * TK), buf, wave);
+        dma_panel<T64, 16>(reinterpret_cast<const unsigned char*>(Bm + (long)s * bs + brow * TK), buf + T64 * 256,
+                           wave);
+      },
+      [&](int s, const unsigned char* buf) {
+        const unsigned char *pa = buf, *pb = buf + T64 * 256;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int c = 4 * h + lane / 16, k0 = s * TK + 2 * c;
+          const bool m0 = k0 >= kb && k0 < ke, m1 = k0 + 1 >= kb && k0 + 1 < ke;
+          double2 fa[4], fb[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            fa[i] = *reinterpret_cast<const double2*>(frag_at<16>(pa, wm * 64 + i * 16 + lane % 16, c));
+            fa[i].x = m0 ? fa[i].x : 0.0;
+            fa[i].y = m1 ? fa[i].y : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            fb[j] = *reinterpret_cast<const double2*>(frag_at<16>(pb, wn * 64 + j * 16 + lane % 16, c));
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].x, acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j], 0, 0, 0);
+            }
+        }
+      });
+}
+// Tile position of element v of FP64 block (i, j) for this lane: instance row, matrix column.
+__device__ __forceinline__ int acc64_row(int wm, int i, int v, int lane) { return wm * 64 + i * 16 + lane / 16 + 4 * v; }
+__device__ __forceinline__ int acc64_col(int wn, int j, int lane) { return wn * 64 + j * 16 + lane % 16; }
+
 // M-tile descriptor: {penalty index, offset into lists, instance count}
 struct MTile {
   int j, off, cnt;
 };
-
-template <int PREC, int TNV>
-__device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt, int nt, long abase, long bbase,
-                                             long (&aoff)[Smem<PREC, TNV>::kRowsA],
-                                             long (&boff)[Smem<PREC, TNV>::kRowsB]) {
-  // operand rows are list positions, matrix rows are rows; rows past the tile's instances or
-  // past L hold other instances or zero padding (their results are discarded)
-#pragma unroll
-  for (int h = 0; h < Smem<PREC, TNV>::kRowsA; ++h) aoff[h] = abase + (long)(mt.off + loader_row<PREC>(h)) * TK;
-#pragma unroll
-  for (int h = 0; h < Smem<PREC, TNV>::kRowsB; ++h) boff[h] = bbase + (long)(nt * TNV + loader_row<PREC>(h)) * TK;
-}
 
 // XCD-aware walk over the grid of (M tile, N tile) pairs with N tiles in [n_begin, n_end).
 // Workgroup g runs on XCD g % 8 (consecutive workgroups of a launch go round-robin over the
@@ -427,7 +412,7 @@ __device__ __forceinline__ void tile_offsets(const BatchArgs& a, const MTile& mt
 struct TileWalk {
   int per, count, mx, m0, n0, nmt;
   bool by_m;
-  __device__ TileWalk(int nmt_, int n_begin, int n_end) : nmt(nmt_) {
+  __device__ __forceinline__ TileWalk(int nmt_, int n_begin, int n_end) : nmt(nmt_) {
     const int G = gridDim.x, x = blockIdx.x % 8, nn = n_end - n_begin;
     if (G % 8 != 0) {  // no XCD structure assumed: plain round robin
       per = G;
@@ -464,7 +449,8 @@ struct TileWalk {
 // are read in batches of kU per thread so that their loads overlap. The order inside a bucket
 // is not fixed (atomic cursors); an instance's arithmetic does not depend on it.
 constexpr int kU = 8;
-__device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */, int want, int from, int to) {
+template <typename AT>
+__device__ __forceinline__ void build_tiles(const AT& a, int* s_count /* LDS, kMaxRhoB */, int want, int from, int to) {
   const int tid = threadIdx.x, B = a.B;
   constexpr int kMaxRhoB = 64;
   __shared__ int s_cur[kMaxRhoB];
@@ -524,8 +510,8 @@ __device__ void build_tiles(const BatchArgs& a, int* s_count /* LDS, kMaxRhoB */
 
 // Layer input w = [sigma x - q; rho z - y] of every running slot into operand parity `par`,
 // kU elements per thread at a time (their loads overlap).
-template <int PREC>
-__device__ void layer_input(const BatchArgs& a, const float* s_rho, long vofs) {
+template <int PREC, typename AT>
+__device__ __forceinline__ void layer_input(const AT& a, const float* s_rho, long vofs) {
   const int n = a.n, m = a.m, L = a.L;
   const long total = (long)a.B * L, gstride = (long)gridDim.x * BS;
   const float sigma = (float)a.sigma, eqs = (float)a.rho_eq_scale;
@@ -563,13 +549,23 @@ __device__ void layer_input(const BatchArgs& a, const float* s_rho, long vofs) {
   }
 }
 
+// The kernel reads its arguments through the kernarg segment pointer made opaque at the start of
+// each phase (fresh), so the compiler loads the fields a phase needs where it needs them instead
+// of keeping every field of the persistent loop in scalar registers (which spills).
+typedef const __attribute__((address_space(4))) BatchArgs* cargs_t;
+__device__ __forceinline__ cargs_t fresh(cargs_t p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 template <int PREC, int TNV>
-__global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
+  (void)a_in;
+  const cargs_t kp = (cargs_t)__builtin_amdgcn_kernarg_segment_ptr();
+  const auto& a = *fresh(kp);
   constexpr int BJ = TNV / 64;
-  using SM = Smem<PREC, TNV>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  SM& sm = *reinterpret_cast<SM*>(smem_raw);
-  Smem64& sm64 = *reinterpret_cast<Smem64*>(smem_raw);  // the FP64 phases (check, warm start)
+  unsigned char* const lds = smem_raw;  // operand stages of the layer and check GEMMs
   __shared__ int s_count[64];
   __shared__ int s_list[TM];   // instance ids of the current M tile
   __shared__ float s_rho[64];  // grid penalties in FP32
@@ -579,7 +575,9 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   const int n = a.n, m = a.m, L = a.L, B = a.B;
   const long ldk = a.ldk;
   const long vpar = a.bpad * ldk;  // elements per parity of V
-  const long as = a.bpad * TK, bs = a.lpad * TK;  // elements per K block of operands / matrices
+  // elements per K block of the operands, the layer matrices and the check matrix
+  const long as = a.bpad * TK, bs = a.lpad * TK, cs = a.cpad * TK;
+  const int NX = (n + T64 - 1) / T64, NC = (m + T64 - 1) / T64;  // check row tiles: x rows, constraint rows
   const int ntiles_n = (L + TNV - 1) / TNV;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha), sigma = (float)a.sigma;
   const float eqs = (float)a.rho_eq_scale;
@@ -588,9 +586,9 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
   if (tid < a.n_rho) s_rho[tid] = (float)a.grid[tid];
 
   // M tile t's instance ids into s_list (entries past the tile's count repeat its first id)
-  auto load_list = [&](const MTile& mt) {
+  auto load_list = [&](const int* lists, const MTile& mt) {
     __syncthreads();  // the previous tile is done with s_list
-    if (tid < TM) s_list[tid] = a.lists[mt.off + (tid < mt.cnt ? tid : 0)];
+    if (tid < TM) s_list[tid] = lists[mt.off + (tid < mt.cnt ? tid : 0)];
     __syncthreads();
   };
 
@@ -620,7 +618,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     }
   }
   if (!grid_barrier(a.bar, ++epoch)) return;
-  if (g == 0) build_tiles(a, s_count, kSlotAdmitWarm, kSlotAdmitCold, ST_RUNNING);
+  if (g == 0) build_tiles(*fresh(kp), s_count, kSlotAdmitWarm, kSlotAdmitCold, ST_RUNNING);
   if (!grid_barrier(a.bar, ++epoch)) return;
   if (a.mtiles[0] > 0) {
     // warm start (Sec. II-B): check operand [x; y] of the warm slots at their list positions,
@@ -646,40 +644,39 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (!grid_barrier(a.bar, ++epoch)) return;
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
-    const TileWalk tw(2 * nmt, n / T64, (L + T64 - 1) / T64);  // 64-instance halves, constraint-row tiles
+    const TileWalk tw(nmt, 0, NC);  // constraint-row tiles
     for (int t = tw.first(); t < tw.count; t += tw.per) {
-      const int u = tw.mt(t), half = u % 2;
-      const MTile mt = mts[u / 2];
-      const int cnt = mt.cnt - T64 * half;
-      if (cnt <= 0) continue;  // the same for every thread of the workgroup
-      const int r0 = tw.nt(t) * T64;
-      load_list(mt);
-      doublex4 acc[2][2];
-      tile_gemm64(sm64, a.CVd, a.Cd, (long)(mt.off + T64 * half) * TK, (long)r0 * TK, as, bs, 0, n, acc);
+      const auto& a = *fresh(kp);
+      const MTile mt = mts[tw.mt(t)];
+      const int r0 = n + tw.nt(t) * T64;
+      load_list(a.lists, mt);
+      doublex4 acc[4][4];
+      check_tile(lds, a.CVd, a.Cd, mt.off, r0, as, cs, 0, n, acc);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 4; ++j) {
           const int r = r0 + acc64_col(wn, j, lane);
-          if (r < n || r >= L) continue;
+          if (r >= L) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int ti = acc64_row(wm, i, v, lane);
-            if (ti < cnt) a.Z[(long)s_list[T64 * half + ti] * m + (r - n)] = (float)acc[i][j][v];
+            if (ti < mt.cnt) a.Z[(long)s_list[ti] * m + (r - n)] = (float)acc[i][j][v];
           }
         }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
   }
-  if (g == 0) build_tiles(a, s_count, ST_RUNNING, kSlotAdmitWarm, ST_RUNNING);
+  if (g == 0) build_tiles(*fresh(kp), s_count, ST_RUNNING, kSlotAdmitWarm, ST_RUNNING);
   if (!grid_barrier(a.bar, ++epoch)) return;
   if (a.mtiles[0] == 0) return;  // nothing to run
   // ---- first layer input V_1 (parity 1)
-  layer_input<PREC>(a, s_rho, vpar);
+  layer_input<PREC>(*fresh(kp), s_rho, vpar);
   if (!grid_barrier(a.bar, ++epoch)) return;
 
   const int ci = a.check_interval;
   for (int k = 1; k <= a.steps; ++k) {
+    const auto& a = *fresh(kp);
     const bool is_check = (k % ci == 0) || (k == a.steps);
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
@@ -688,117 +685,140 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
 
     // ---- layer GEMM + fused update
     for (int t = tw.first(); t < tw.count; t += tw.per) {
+      const auto& a = *fresh(kp);
       const MTile mt = mts[tw.mt(t)];
       const int nt = tw.nt(t);
-      load_list(mt);
-      long aoff[SM::kRowsA], boff[SM::kRowsB];
-      tile_offsets<PREC, TNV>(a, mt, nt, vin, (long)mt.j * a.w_stride, aoff, boff);
+      load_list(a.lists, mt);
+      constexpr long es = PREC == kBatchBF16x3 ? 2 : 4;
+      const unsigned char* Aa = static_cast<const unsigned char*>(a.Va) + vin * es;
+      const unsigned char* Ab = a.Vb ? static_cast<const unsigned char*>(a.Vb) + vin * es : nullptr;
+      const unsigned char* Ba = static_cast<const unsigned char*>(a.Wa) + (long)mt.j * a.w_stride * es;
+      const unsigned char* Bb = a.Wb ? static_cast<const unsigned char*>(a.Wb) + (long)mt.j * a.w_stride * es : nullptr;
       floatx16 acc[2][BJ];
-      tile_gemm<PREC, TNV, false>(sm, a.Va, a.Vb, a.Wa, a.Wb, aoff, boff, as, bs, 0, L, acc);
+      layer_tile<PREC, TNV>(lds, Aa, Ab, Ba, Bb, mt.off, (long)nt * TNV, as, bs, L, acc);
       const float rho_bar = s_rho[mt.j];
-      // epilogue, one 32 x 32 block at a time: the 16 elements' state loads are issued
-      // together, then the row-local update (relaxation, clamp, dual) and the stores
+      // epilogue, one 32 x 32 block at a time (block indices are compile-time constants, so the
+      // accumulators stay in registers). A lane's 16 elements of a block share its column r (one
+      // layer row) and take 16 instances; the instances' state offsets are formed once per
+      // block row i. All state loads of a block are issued together, then the row-local update
+      // (relaxation, clamp, dual) and the stores; elements past the tile's instance count load
+      // valid rows (the list repeats its first id) and store nothing. Offsets are 32-bit
+      // (B * max(n, m) and the operand size, in bytes, are checked at setup).
+      const auto& ae = *fresh(kp);
+      unsigned char* const vo = static_cast<unsigned char*>(ae.Va) + vout * (PREC == kBatchBF16x3 ? 2 : 4);
+      unsigned char* const vo2 = ae.Vb ? static_cast<unsigned char*>(ae.Vb) + vout * 2 : nullptr;
+      static_for<0, 2>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        unsigned on[16], om[16], oo[16];
+        bool ok[16];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < BJ; ++j) {
-          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
-          const bool rin = r < L, xr = r < n;
-          const int ri = xr ? r : (rin ? r - n : 0);  // x index, or constraint index
-          const float rho = rho_bar * (!xr && a.eq[ri] ? eqs : 1.0f);
-          float u0[16], u1[16], u2[16], u3[16];
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const long b = s_list[acc_row(wm, i, v, lane)];
-            const long xi = b * n + (xr ? ri : 0), zi = b * m + (xr ? 0 : ri);
-            u0[v] = xr ? a.X[xi] : a.Z[zi];
-            u1[v] = xr ? a.Q[xi] : a.Y[zi];
-            u2[v] = a.Lo[zi];
-            u3[v] = a.Up[zi];
-          }
-          if (!rin) continue;
-#pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int ti = acc_row(wm, i, v, lane);
-            if (ti >= mt.cnt) continue;
-            const long b = s_list[ti];
-            const float s = acc[i][j][v];
-            float w, cv;
-            if (xr) {
-              const float x = alpha * s + oma * u0[v];
-              a.X[b * n + ri] = x;
-              w = sigma * x - u1[v];
-              cv = x;
-            } else {
-              const float t2 = alpha * s + oma * u0[v] + u1[v] / rho;
-              const float zn = t2 < u2[v] ? u2[v] : (t2 > u3[v] ? u3[v] : t2);
-              const float yn = rho * (t2 - zn);
-              a.Z[b * m + ri] = zn;
-              a.Y[b * m + ri] = yn;
-              w = rho * zn - yn;
-              cv = yn;
-            }
-            const long oi = opidx(a.bpad, mt.off + ti, r);
-            if (is_check)
-              a.CVd[oi] = (double)cv;
-            else
-              put_operand<PREC>(a.Va, a.Vb, vout + oi, w);
-          }
+        for (int v = 0; v < 16; ++v) {
+          const int ti = acc_row(wm, i, v, lane);
+          const unsigned b = (unsigned)s_list[ti];
+          on[v] = b * (unsigned)n;
+          om[v] = b * (unsigned)m;
+          oo[v] = (unsigned)ti * TK;
+          ok[v] = ti < mt.cnt;
         }
+        static_for<0, BJ>([&](auto J) {
+          constexpr int j = decltype(J)::value;
+          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
+          if (r >= L) return;
+          // operand index of element v: obase + oo[v] (K-blocked, list position mt.off + ti)
+          const unsigned obase = ((unsigned)(r / TK) * (unsigned)ae.bpad + (unsigned)mt.off) * TK + (unsigned)(r % TK);
+          if (r < n) {
+            float xo[16], qv[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              xo[v] = at32(ae.X, on[v] + r);
+              qv[v] = at32(ae.Q, on[v] + r);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const float x = alpha * acc[i][j][v] + oma * xo[v];
+              if (!ok[v]) continue;
+              at32(ae.X, on[v] + r) = x;
+              if (is_check)
+                at32(ae.CVd, obase + oo[v]) = (double)x;
+              else
+                put_operand32<PREC>(vo, vo2, obase + oo[v], sigma * x - qv[v]);
+            }
+          } else {
+            const int ri = r - n;
+            const float rho = rho_bar * (ae.eq[ri] ? eqs : 1.0f), rinv = 1.0f / rho;
+            float zo[16], yo[16], lo[16], up[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              zo[v] = at32(ae.Z, om[v] + ri);
+              yo[v] = at32(ae.Y, om[v] + ri);
+              lo[v] = at32(ae.Lo, om[v] + ri);
+              up[v] = at32(ae.Up, om[v] + ri);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const float t2 = alpha * acc[i][j][v] + oma * zo[v] + yo[v] * rinv;
+              const float zn = t2 < lo[v] ? lo[v] : (t2 > up[v] ? up[v] : t2);
+              const float yn = rho * (t2 - zn);
+              if (!ok[v]) continue;
+              at32(ae.Z, om[v] + ri) = zn;
+              at32(ae.Y, om[v] + ri) = yn;
+              if (is_check)
+                at32(ae.CVd, obase + oo[v]) = (double)yn;
+              else
+                put_operand32<PREC>(vo, vo2, obase + oo[v], rho * zn - yn);
+            }
+          }
+        });
+      });
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
     if (!is_check) continue;
 
-    // ---- check GEMM in FP64: [P, A'; A, 0] [x; y]; K split at n keeps P x and A'y apart, and
-    // the constraint rows ([A, 0]) need only K in [0, n). The dual residual uses q rounded to
-    // FP32 (the handle's copy): the published r_d adds that rounding (u |q_i|) and ||q|| drops it,
-    // so the test passes only if the FP64 test with the caller's q does.
+    // ---- check GEMM in FP64: [P, A'; A, 0] [x; y] as three kinds of tiles, each over one K
+    // range with one accumulator: P x (x rows, K in [0, n)), A'y (x rows, K in [n, L)) and A x
+    // (constraint rows, K in [0, n)). P x and A'y go to per-position buffers (the dual residual
+    // needs their sum, the tolerance each norm); the A x tiles finish the primal side at once.
     {
-      const double uq = 1.01 * 0x1p-24;
-      const TileWalk tw64(2 * nmt, 0, (L + T64 - 1) / T64);
+      const TileWalk tw64(nmt, 0, 2 * NX + NC);
       for (int t = tw64.first(); t < tw64.count; t += tw64.per) {
-        const int u = tw64.mt(t), half = u % 2;
-        const MTile mt = mts[u / 2];
-        const int cnt = mt.cnt - T64 * half;
-        if (cnt <= 0) continue;  // the same for every thread of the workgroup
-        const int r0 = tw64.nt(t) * T64;
-        load_list(mt);
-        const long abase = (long)(mt.off + T64 * half) * TK, bbase = (long)r0 * TK;
-        doublex4 acc_p[2][2], acc_a[2][2];
-        tile_gemm64(sm64, a.CVd, a.Cd, abase, bbase, as, bs, 0, n, acc_p);   // P x, A x
-        tile_gemm64(sm64, a.CVd, a.Cd, abase, bbase, as, bs, n, r0 < n ? L : n, acc_a);  // A'y (x rows)
+        const auto& a = *fresh(kp);
+        const MTile mt = mts[tw64.mt(t)];
+        const int u = tw64.nt(t);
+        const int kind = u < NX ? 0 : (u < 2 * NX ? 1 : 2);  // P x, A'y, A x (one kind per workgroup)
+        const int r0 = kind == 2 ? n + (u - 2 * NX) * T64 : (u - kind * NX) * T64;
+        load_list(a.lists, mt);
+        doublex4 acc[4][4];
+        check_tile(lds, a.CVd, a.Cd, mt.off, r0, as, cs, kind == 1 ? n : 0, kind == 1 ? L : n, acc);
+        double* const R = kind == 0 ? a.Rpx : a.Raty;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int ti = acc64_row(wm, i, v, lane);
-            const bool valid_i = ti < cnt;
-            const long b = s_list[T64 * half + (valid_i ? ti : 0)];
-            uint64_t nb[7] = {0, 0, 0, 0, 0, 0, 0};
+            const bool valid_i = ti < mt.cnt;
+            const long b = s_list[valid_i ? ti : 0];
+            uint64_t nb[3] = {0, 0, 0};
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < 4; ++j) {
               const int r = r0 + acc64_col(wn, j, lane);
-              if (!valid_i || r >= L) continue;
-              const double pp = acc_p[i][j][v];
-              if (r < n) {
-                const double pa = acc_a[i][j][v], q = (double)a.Q[b * n + r], dq = uq * fabs(q);
-                const uint64_t vrd = abs_bits(fabs(pp + pa + q) + dq), vpx = abs_bits(pp), vat = abs_bits(pa);
-                const uint64_t vq = abs_bits(lower_bound(fabs(q), dq));
-                nb[N_RD] = vrd > nb[N_RD] ? vrd : nb[N_RD];
-                nb[N_PX] = vpx > nb[N_PX] ? vpx : nb[N_PX];
-                nb[N_ATY] = vat > nb[N_ATY] ? vat : nb[N_ATY];
-                nb[N_Q] = vq > nb[N_Q] ? vq : nb[N_Q];
+              const double pv = acc[i][j][v];
+              if (kind < 2) {
+                if (!valid_i || r >= n) continue;
+                R[(long)(mt.off + ti) * n + r] = pv;
+                const uint64_t vb = abs_bits(pv);
+                nb[0] = vb > nb[0] ? vb : nb[0];
               } else {
+                if (!valid_i || r >= L) continue;
                 const double z = (double)a.Z[b * m + (r - n)];
-                const uint64_t vrp = abs_bits(pp - z), vax = abs_bits(pp), vz = abs_bits(z);
-                nb[N_RP] = vrp > nb[N_RP] ? vrp : nb[N_RP];
-                nb[N_AX] = vax > nb[N_AX] ? vax : nb[N_AX];
-                nb[N_Z] = vz > nb[N_Z] ? vz : nb[N_Z];
+                const uint64_t vrp = abs_bits(pv - z), vax = abs_bits(pv), vz = abs_bits(z);
+                nb[0] = vrp > nb[0] ? vrp : nb[0];
+                nb[1] = vax > nb[1] ? vax : nb[1];
+                nb[2] = vz > nb[2] ? vz : nb[2];
               }
             }
             // lanes with the same lane / 16 hold the same instance row: reduce over lane % 16
 #pragma unroll
-            for (int q = 0; q < 7; ++q) {
+            for (int q = 0; q < 3; ++q) {
               uint64_t x = nb[q];
 #pragma unroll
               for (int off = 1; off < 16; off <<= 1) {
@@ -808,9 +828,16 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
               nb[q] = x;
             }
             if (valid_i && (lane % 16) == 0) {
-#pragma unroll
-              for (int q = 0; q < 7; ++q)
-                if (nb[q]) atomicMax(a.norms + b * 8 + q, (unsigned long long)nb[q]);
+              unsigned long long* nm = a.norms + b * 8;
+              if (kind == 0) {
+                if (nb[0]) atomicMax(nm + N_PX, (unsigned long long)nb[0]);
+              } else if (kind == 1) {
+                if (nb[0]) atomicMax(nm + N_ATY, (unsigned long long)nb[0]);
+              } else {
+                if (nb[0]) atomicMax(nm + N_RP, (unsigned long long)nb[0]);
+                if (nb[1]) atomicMax(nm + N_AX, (unsigned long long)nb[1]);
+                if (nb[2]) atomicMax(nm + N_Z, (unsigned long long)nb[2]);
+              }
             }
           }
       }
@@ -825,14 +852,37 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
              __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __syncthreads();
     const bool ab = ab_s != 0;
-    for (long b = gtid; b < B; b += gstride) {
-      if (a.status[b] != ST_RUNNING) continue;
+    // one wave per instance: the dual residual and ||q|| from the P x and A'y rows of the
+    // instance's list position and its q (the handle's FP32 copy: the published r_d adds that
+    // rounding, u |q_i|, and ||q|| drops it, so the test passes only if the FP64 test with the
+    // caller's q does), then lane 0 decides
+    const double uq = 1.01 * 0x1p-24;
+    const long gw = (long)g * (BS / 64) + wave, nw = (long)G * (BS / 64);
+    for (long b = gw; b < B; b += nw) {
+      const auto& a = *fresh(kp);
+      if (a.status[b] != ST_RUNNING) continue;  // the same for every lane of the wave
+      const long pos = a.pos_of[b];
+      uint64_t vrd = 0, vq = 0;
+      for (int r = lane; r < n; r += 64) {
+        const double pp = a.Rpx[pos * n + r], pa = a.Raty[pos * n + r], q = (double)a.Q[b * n + r];
+        const double dq = uq * fabs(q);
+        const uint64_t x1 = abs_bits(fabs(pp + pa + q) + dq), x2 = abs_bits(lower_bound(fabs(q), dq));
+        vrd = x1 > vrd ? x1 : vrd;
+        vq = x2 > vq ? x2 : vq;
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t o1 = __shfl_xor(vrd, off, 64), o2 = __shfl_xor(vq, off, 64);
+        vrd = o1 > vrd ? o1 : vrd;
+        vq = o2 > vq ? o2 : vq;
+      }
+      if (lane != 0) continue;
       unsigned long long* nm = a.norms + b * 8;
       uint64_t bits[7];
       bool nonfinite = false;
 #pragma unroll
       for (int q = 0; q < 7; ++q) {
-        bits[q] = nm[q];
+        bits[q] = q == N_RD ? vrd : (q == N_Q ? vq : (uint64_t)nm[q]);
         nm[q] = 0;
         nonfinite |= bits[q] >= kInfBits;
       }
@@ -873,13 +923,13 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
       }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
-    if (g == 0) build_tiles(a, s_count, ST_RUNNING, -1, -1);
+    if (g == 0) build_tiles(*fresh(kp), s_count, ST_RUNNING, -1, -1);
     if (!grid_barrier(a.bar, ++epoch)) return;
     if (a.mtiles[0] == 0) return;
     if (k == a.steps) break;  // the next launch rebuilds the layer input from the state
 
     // ---- next layer input for the instances still running (penalty may have changed)
-    layer_input<PREC>(a, s_rho, vout);
+    layer_input<PREC>(*fresh(kp), s_rho, vout);
     if (!grid_barrier(a.bar, ++epoch)) return;
   }
   // slots still running carry their iteration count into the next launch
@@ -887,34 +937,38 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a) {
     if (a.status[b] == ST_RUNNING) a.iterations[b] += a.steps;
 }
 
+template <int TNV>
+constexpr size_t kernel_smem() {
+  return LayerGeo<TNV>::SMEM > CheckGeo::SMEM ? LayerGeo<TNV>::SMEM : CheckGeo::SMEM;
+}
+
+}  // namespace
+
+size_t batch_smem(int prec, int tn) {
+  (void)prec;
+  return tn == 256 ? kernel_smem<256>() : tn == 128 ? kernel_smem<128>() : tn == 64 ? kernel_smem<64>() : 0;
+}
+
+namespace {
+const void* batch_fn(int prec, int tn) {
+  if (prec == kBatchBF16x3) {
+    if (tn == 256) return reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 256>);
+    if (tn == 128) return reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 128>);
+    if (tn == 64) return reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 64>);
+  } else if (prec == kBatchF32) {
+    if (tn == 256) return reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 256>);
+    if (tn == 128) return reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 128>);
+    if (tn == 64) return reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 64>);
+  }
+  return nullptr;
+}
 }  // namespace
 
 BatchPlan plan_batch(int prec, int tn) {
   BatchPlan p{nullptr, 0, 0, tn};
-  const void* fn = nullptr;
-  size_t smem = 0;
-  if (prec == kBatchBF16x3 && tn == 128) {
-    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 128>);
-    smem = sizeof(Smem<kBatchBF16x3, 128>);
-  } else if (prec == kBatchBF16x3 && tn == 64) {
-    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 64>);
-    smem = sizeof(Smem<kBatchBF16x3, 64>);
-  } else if (prec == kBatchF32 && tn == 128) {
-    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 128>);
-    smem = sizeof(Smem<kBatchF32, 128>);
-  } else if (prec == kBatchF32 && tn == 64) {
-    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 64>);
-    smem = sizeof(Smem<kBatchF32, 64>);
-  } else if (prec == kBatchBF16x3 && tn == 256) {
-    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchBF16x3, 256>);
-    smem = sizeof(Smem<kBatchBF16x3, 256>);
-  } else if (prec == kBatchF32 && tn == 256) {
-    fn = reinterpret_cast<const void*>(&batch_kernel<kBatchF32, 256>);
-    smem = sizeof(Smem<kBatchF32, 256>);
-  } else {
-    return p;
-  }
-  smem = smem > sizeof(Smem64) ? smem : sizeof(Smem64);
+  const void* fn = batch_fn(prec, tn);
+  const size_t smem = batch_smem(prec, tn);
+  if (!fn || !smem) return p;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return p;
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return p;

@@ -118,7 +118,7 @@ struct relu_qp_handle {
   // batched engine
   bool batched = false;
   int bprec = 0;
-  long ldk = 0, lpad = 0, bpad = 0;
+  long ldk = 0, lpad = 0, cpad = 0, bpad = 0;
   void* bWa = nullptr;
   void* bWb = nullptr;
   double* bCd = nullptr;  // FP64 check matrix, K-blocked
@@ -128,6 +128,8 @@ struct relu_qp_handle {
   void* bVa = nullptr;
   void* bVb = nullptr;
   double* bCVd = nullptr;  // FP64 check operand [x; y], K-blocked
+  double* bRpx = nullptr;  // check scratch: P x and A'y per list position (B x n each, FP64)
+  double* bRaty = nullptr;
   int* bjb = nullptr;
   unsigned long long* bnorms = nullptr;
   int* blists = nullptr;
@@ -160,7 +162,7 @@ void free_handle(relu_qp_handle* h) {
   void* ptrs[] = {h->W,    h->C,    h->q,    h->l,    h->u,     h->eq_d,   h->grid_d,  h->mid_d,
                   h->xs,   h->zs,   h->ys,   h->js,   h->xw,    h->xc,     h->xn,      h->err,  h->xu,  h->xpl, h->axs, h->scl, h->Wp, h->xwp,
                   h->F_d,  h->E_d,  h->lo_d, h->hi_d, h->bWa,   h->bWb,    h->bCd,
-                  h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVd,   h->bjb,
+                  h->bX,   h->bZ,   h->bY,   h->bVa,  h->bVb,   h->bCVd,   h->bRpx, h->bRaty, h->bjb,
                   h->bnorms, h->blists, h->bmtiles, h->bbar, h->bstatus, h->biter, h->bstage, h->bpos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -503,6 +505,10 @@ int alloc_exchange(relu_qp_handle* h) {
 }
 
 
+// Padded rows of the batched engine's FP64 check matrix: its constraint-row tiles (128 rows)
+// start at row n, so rows up to L + 127 are read.
+size_t check_rows(size_t L) { return (L + 127) / 128 * 128 + 128; }
+
 bool is_batched(const relu_qp_settings& s) {
   return s.engine == RQP_ENGINE_BATCH || (s.engine == RQP_ENGINE_AUTO && (s.batch > 1 || s.precision == RQP_BF16X3));
 }
@@ -542,7 +548,7 @@ int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hip
   }
   // the check matrix stays FP64 (the residuals are FP64 evaluations of the iterates)
   HIP_OR_FAIL(rqp::assemble_check<double>(n, m, P_d.d(), A_d.d(), Wd.d(), L, st));
-  HIP_OR_FAIL(rqp::pad_f64(L, L, Wd.d(), L, h->bCd, h->lpad, h->ldk, st));
+  HIP_OR_FAIL(rqp::pad_f64(L, L, Wd.d(), L, h->bCd, h->cpad, h->ldk, st));
   int hinfo = 0;
   HIP_OR_FAIL(hipMemcpyAsync(&hinfo, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_OR_FAIL(hipStreamSynchronize(st));
@@ -563,12 +569,16 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   // stages past the end, into zeros)
   h->ldk = (L + rqp::kTileK - 1) / rqp::kTileK * rqp::kTileK + 4 * rqp::kTileK;
   h->lpad = (L + rqp::kTileN - 1) / rqp::kTileN * rqp::kTileN;
+  h->cpad = check_rows(L);
   // list positions of a tile may run up to kTileM past the last running instance
   h->bpad = ((long)B + rqp::kTileM - 1) / rqp::kTileM * rqp::kTileM + rqp::kTileM;
   h->w_stride = h->lpad * h->ldk;
+  // the kernel forms state and operand offsets in 32 bits
+  if ((double)B * (n > m ? n : m) * 8 >= 4294967296.0 || (double)h->bpad * h->ldk * 8 >= 4294967296.0)
+    return fail(RQP_EINVAL, "batch %d with n=%d, m=%d exceeds the batched engine's 4 GiB arrays", B, n, m);
   const size_t es = h->bprec == rqp::kBatchBF16x3 ? 2 : 4;
   const size_t nr = h->grid.size();
-  const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->w_stride * 8;
+  const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->cpad * h->ldk * 8;
   const size_t vbytes = (size_t)h->bpad * h->ldk * es, cvbytes = (size_t)h->bpad * h->ldk * 8;
   const size_t ntile_max = (size_t)B / rqp::kTileM + nr + 1;
   auto al = [h](void** p, size_t bytes) { return dmalloc(h, p, bytes) == hipSuccess; };
@@ -576,7 +586,8 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   if (!al(&h->bWa, wbytes) || (two && !al(&h->bWb, wbytes)) || !al((void**)&h->bCd, cbytes) ||
       !al((void**)&h->bX, (size_t)B * n * 4) || !al((void**)&h->bZ, (size_t)B * m * 4) ||
       !al((void**)&h->bY, (size_t)B * m * 4) || !al(&h->bVa, 2 * vbytes) || (two && !al(&h->bVb, 2 * vbytes)) ||
-      !al((void**)&h->bCVd, cvbytes) || !al((void**)&h->bjb, (size_t)B * 4) ||
+      !al((void**)&h->bCVd, cvbytes) || !al((void**)&h->bRpx, (size_t)B * n * 8) ||
+      !al((void**)&h->bRaty, (size_t)B * n * 8) || !al((void**)&h->bjb, (size_t)B * 4) ||
       !al((void**)&h->bnorms, (size_t)B * 8 * 8) || !al((void**)&h->blists, (size_t)B * 4) ||
       !al((void**)&h->bpos, (size_t)B * 4) ||
       !al((void**)&h->bmtiles, (1 + 3 * ntile_max) * 4) || !al((void**)&h->bbar, 1024 * 4) ||
@@ -627,6 +638,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.B = B;
   a.ldk = h->ldk;
   a.lpad = h->lpad;
+  a.cpad = h->cpad;
   a.bpad = h->bpad;
   a.prec = h->bprec;
   a.Wa = h->bWa;
@@ -645,7 +657,8 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.eps_abs = h->s.eps_abs;
   a.eps_rel = h->s.eps_rel;
   a.rho_eq_scale = h->s.rho_eq_scale;
-  a.max_iter = h->s.max_iter;
+  // fixed_iters: no instance stops before the launch's last iteration (not even at max_iter)
+  a.max_iter = fixed_iters && steps > h->s.max_iter ? steps : h->s.max_iter;
   a.check_interval = h->s.check_interval;
   a.terminate = !fixed_iters && !(h->s.eps_abs == 0.0 && h->s.eps_rel == 0.0);
   a.j0 = h->j0;
@@ -656,6 +669,8 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.Va = h->bVa;
   a.Vb = h->bVb;
   a.CVd = h->bCVd;
+  a.Rpx = h->bRpx;
+  a.Raty = h->bRaty;
   a.jb = h->bjb;
   a.status = h->bstatus;
   a.iterations = h->biter;
@@ -1647,7 +1662,8 @@ int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* b
     const size_t ntile_max = B / rqp::kTileM + nr + 1;
     const size_t nw = two ? 2 : 1;
     t += nw * (nr * w_stride * es + 2 * vbytes);                   // layer weights, V (two parities)
-    t += w_stride * 8 + bpad * ldk * 8;                            // FP64 check matrix and operand
+    t += check_rows(L) * ldk * 8 + bpad * ldk * 8;                 // FP64 check matrix and operand
+    t += 2 * B * n * 8;                                            // check scratch (P x, A'y)
     t += B * n * 4 + 2 * B * m * 4;                                // x, z, y
     t += B * 4 + B * 64 + B * 4 + B * 4;                           // penalty index, norms, lists, positions
     t += (1 + 3 * ntile_max) * 4 + 1024 * 4;                       // tile lists, barrier words
