@@ -46,6 +46,7 @@ struct LayerArgs {
   const int* abort_flag;  // host-mapped int, polled at checks
   unsigned* err;        // device word: holds the tag of a solve whose exchange timed out
   int lds_rows;         // rows per block kept in LDS (set by launch_layer from the plan)
+  int check_cols;       // columns of the check vector staged in LDS at a time (set likewise)
   // optional in-kernel update from initial states (x0 != null, count x nx): q = F x0,
   // l = lo - E x0, u = hi - E x0, written to q, l, u before each solve starts
   const double* x0;
@@ -124,6 +125,7 @@ constexpr int kMaxCheckRows = kMaxRows + 2;
 struct LaunchPlan {
   const void* fn;
   int reg_rows, lds_rows;
+  int check_cols;  // columns of the check vector staged in LDS at a time
   size_t dyn_bytes;
   int max_grid;  // largest cooperative grid with these resources
 };

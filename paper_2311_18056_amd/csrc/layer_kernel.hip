@@ -227,99 +227,124 @@ __device__ __forceinline__ void load_quad(const double* p, double (&v)[4]) {
   v[3] = t1.y;
 }
 
-// Quads of a chunk of the check vector each lane of a wave takes (4 FP32 or 2 FP64 quads: 16
-// registers of loads in flight; more raise the kernel's register pressure enough to spill
-// loop-invariant values of the iteration loop), and the columns of the vector staged in LDS at a
-// time (4 KB).
+// The residual check's unit of work (an item) is one row of the check matrix over QW = 4 kWave
+// check_quads() columns (1024 FP32 / 512 FP64): each lane loads check_quads() quads of it with
+// 16-byte loads (16 registers of loads in flight; more raise the kernel's register pressure
+// enough to spill loop-invariant values of the iteration loop).
 template <typename T>
 constexpr int check_quads() {
   return sizeof(T) == sizeof(float) ? 4 : 2;
 }
 template <typename T>
-constexpr int check_chunk() {
+constexpr int check_width() {
   return 4 * kWave * check_quads<T>();
 }
+// Items per round of the check: one per wave.
+constexpr int kCheckItems = NWAVE;
 
 // The rows of the residual check: dual rows cb .. cb + nck - 1 (x rows of [P, A'], all L
 // columns) and primal rows pb .. pb + np - 1 (constraint rows, [A, 0]: the first n columns),
-// times [x; y] (cv: this lane's gathered columns tid + BS k). The vector goes through LDS in
-// chunks of check_chunk() columns; each wave takes whole rows (rows w, w + NWAVE, ... of the
-// combined list) and each lane check_quads() quads of the chunk, all loaded at once with
-// 16-byte loads, so the wave has a whole row chunk in flight and reduces only over itself.
-// Row i of the list (dual rows first) leaves in res[i]: the product with the x part (P x, or
-// A x) and with the y part (A'y; zero for a primal row), both with FP64 accumulation of the
-// exact FP64 products, and (FP32 only) the sum of the absolute values of the products,
-// accumulated in FP32 (it only enters the rounding bound). Every thread of the workgroup must
-// call it.
+// times [x; y] (cv: this lane's gathered columns tid + BS k). The vector is staged in LDS
+// (stage, ch columns at a time: the whole vector when the launch has room for it). The rows of
+// a chunk are cut into items (a row over check_width() columns), and every wave takes one item
+// per round, so the loads of a whole round are in flight together and no wave waits on a long
+// row. Each item leaves its partial sums in LDS, and after every round one thread per row adds
+// its row's partials in item order, so the sums do not depend on timing. Row i of the list (dual
+// rows first) leaves in res[i]: the product with the x part (P x, or A x) and with the y part
+// (A'y; zero for a primal row), both with FP64 accumulation of the exact FP64 products, and
+// (FP32 only) the sum of the absolute values of the products, accumulated in FP32 (it only
+// enters the rounding bound). Every thread of the workgroup must call it.
 template <typename T, int NC>
 __device__ __forceinline__ void check_rows(const LayerArgs& a, int cb, int nck, int pb, int np,
-                                           const Cols<T, NC>& cv, double (*res)[3]) {
+                                           const Cols<T, NC>& cv, double (*res)[3], T* stage, int ch) {
   constexpr bool F32 = sizeof(T) == sizeof(float);
-  constexpr int QL = check_quads<T>(), CH = check_chunk<T>();
-  __shared__ __align__(16) T stage[CH];
+  constexpr int QL = check_quads<T>(), QW = check_width<T>();
+  __shared__ double part[kCheckItems][3];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int n = a.n, L = a.L;
   const long ldw = a.ldw;
   const T* Cm = static_cast<const T*>(a.C);
   const int rows = nck + np;
   for (int i = tid; i < 3 * rows; i += BS) res[i / 3][i % 3] = 0.0;
-  for (int c0 = 0; c0 < L; c0 += CH) {
+  for (int c0 = 0; c0 < L; c0 += ch) {
     __syncthreads();  // the previous chunk has been read (and res cleared)
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       const int c = tid + BS * k;
-      if (c >= c0 && c < c0 + CH) stage[c - c0] = c < L ? cv.v[k] : (T)0;
+      if (c >= c0 && c < c0 + ch) stage[c - c0] = c < L ? cv.v[k] : (T)0;
     }
     // columns of the chunk past L are staged as zero
-    if (c0 + CH > L)
-      for (int c = L - c0 + tid; c < CH; c += BS) stage[c] = (T)0;
+    if (c0 + ch > L)
+      for (int c = L - c0 + tid; c < ch; c += BS) stage[c] = (T)0;
     __syncthreads();
-    for (int i = wave; i < rows; i += NWAVE) {
-      const bool dual = i < nck;
-      const int R = dual ? cb + i : pb + (i - nck);
-      const int cl = dual ? L : n;  // columns of this row in the check
-      if (c0 >= cl) continue;
-      const T* row = Cm + (long)R * ldw + c0;
-      T w[QL][4];
+    // items of the chunk: dual rows have pd of them, primal rows pp (columns below n only)
+    const int span = L - c0 < ch ? L - c0 : ch;
+    const int pd = (span + QW - 1) / QW;
+    const int spp = n - c0 < ch ? n - c0 : ch;
+    const int pp = spp > 0 ? (spp + QW - 1) / QW : 0;
+    const int total = nck * pd + np * pp;
+    for (int t0 = 0; t0 < total; t0 += kCheckItems) {
+      const int t = t0 + wave;
+      if (t < total) {
+        const bool dual = t < nck * pd;
+        const int i = dual ? t / pd : nck + (t - nck * pd) / pp;
+        const int q = dual ? t % pd : (t - nck * pd) % pp;
+        const int R = dual ? cb + i : pb + (i - nck);
+        const int cl = dual ? L : n;  // columns of this row in the check
+        const int cs = c0 + q * QW;  // first column of the item
+        const T* row = Cm + (long)R * ldw + cs;
+        T w[QL][4];
 #pragma unroll
-      for (int u = 0; u < QL; ++u) {
-        const int cq = 4 * (lane + kWave * u);
-        if (c0 + cq < cl) {
-          load_quad(row + cq, w[u]);
-        } else {
+        for (int u = 0; u < QL; ++u) {
+          const int cq = 4 * (lane + kWave * u);
+          if (cs + cq < cl) {
+            load_quad(row + cq, w[u]);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) w[u][e] = (T)0;
+            for (int e = 0; e < 4; ++e) w[u][e] = (T)0;
+          }
+        }
+        double p = 0.0, q2 = 0.0;
+        float fa = 0.0f;
+#pragma unroll
+        for (int u = 0; u < QL; ++u) {
+          const int cq = 4 * (lane + kWave * u);
+          T v[4];
+          load_quad(stage + q * QW + cq, v);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = cs + cq + e;
+            const double prod = c < cl ? (double)w[u][e] * (double)v[e] : 0.0;
+            if (c < n)
+              p += prod;
+            else
+              q2 += prod;
+            if constexpr (F32) fa += c < cl ? fabsf(w[u][e] * v[e]) : 0.0f;
+          }
+        }
+        p = wave_sum_to_last(p);
+        q2 = wave_sum_to_last(q2);
+        if constexpr (F32) fa = wave_sum_to_last(fa);
+        if (lane == kLastLane) {
+          part[wave][0] = p;
+          part[wave][1] = q2;
+          part[wave][2] = (double)fa;
         }
       }
-      double p = 0.0, q2 = 0.0;
-      float fa = 0.0f;
-#pragma unroll
-      for (int u = 0; u < QL; ++u) {
-        const int cq = 4 * (lane + kWave * u);
-        T v[4];
-        load_quad(stage + cq, v);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = c0 + cq + e;
-          const double prod = c < cl ? (double)w[u][e] * (double)v[e] : 0.0;
-          if (c < n)
-            p += prod;
-          else
-            q2 += prod;
-          if constexpr (F32) fa += c < cl ? fabsf(w[u][e] * v[e]) : 0.0f;
+      __syncthreads();
+      // one thread per row adds the round's items of its row, in item order
+      if (tid < rows) {
+        const int lo = tid < nck ? tid * pd : nck * pd + (tid - nck) * pp;
+        const int hi = lo + (tid < nck ? pd : pp);
+        for (int u = lo > t0 ? lo : t0; u < hi && u < t0 + kCheckItems && u < total; ++u) {
+          res[tid][0] += part[u - t0][0];
+          res[tid][1] += part[u - t0][1];
+          res[tid][2] += part[u - t0][2];
         }
       }
-      p = wave_sum_to_last(p);
-      q2 = wave_sum_to_last(q2);
-      if constexpr (F32) fa = wave_sum_to_last(fa);
-      if (lane == kLastLane) {
-        res[i][0] += p;
-        res[i][1] += q2;
-        res[i][2] += (double)fa;
-      }
+      __syncthreads();
     }
   }
-  __syncthreads();
 }
 
 // Bound factor of the check in FP32: with the stored matrices and the returned x, z, y rounded
@@ -363,12 +388,12 @@ struct CheckOut {
 template <typename T, int NC, bool XT>
 __device__ __forceinline__ bool check_partials(const LayerArgs& a, const RowState<T>& rs, int r0, int nrows,
                                                int cb, int nck, const T* cq, int k, int nchk, uint32_t tag,
-                                               double (*res)[3], double& ax_out) {
-  __shared__ uint64_t nred[NWAVE][8];
+                                               double (*res)[3], T* stage, double& ax_out) {
+  __shared__ unsigned long long nmax[8];  // the workgroup's partial norms (ordered bit patterns)
   constexpr int NW = LLWords<T>::kWords;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
-  const int lane = tid % kWave, wave = tid / kWave;
   const int L = a.L;
+  if (tid < 8) nmax[tid] = 0ull;  // ordered before the atomics below by check_rows' barriers
 
   // [x; y] to every workgroup
   const uint32_t ctag = tag + (uint32_t)k;
@@ -383,7 +408,7 @@ __device__ __forceinline__ bool check_partials(const LayerArgs& a, const RowStat
   // this workgroup owns, [A, 0] [x; y]
   const int pb = r0 > a.n ? r0 : a.n;
   const int np = r0 + nrows > pb ? r0 + nrows - pb : 0;
-  check_rows<T, NC>(a, cb, nck, pb, np, cv, res);
+  check_rows<T, NC>(a, cb, nck, pb, np, cv, res, stage, a.check_cols);
   if (tid < nck) {
     const double pr = res[tid][0], ar = res[tid][1], d = kappa * res[tid][2];
     const double qv = (double)cq[tid], dq = ut * fabs(qv);
@@ -403,16 +428,16 @@ __device__ __forceinline__ bool check_partials(const LayerArgs& a, const RowStat
     nb[N_Z] = abs_bits(e * lower_bound(fabs(zv), dz));
     ax_out = s;
   }
+  // only the threads of the check and constraint rows hold values: LDS atomics, no wave-wide
+  // reductions
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    const uint64_t v = wave_max_u64(nb[i]);
-    if (lane == 0) nred[wave][i] = v;
-  }
+  for (int i = 0; i < 7; ++i)
+    if (nb[i]) atomicMax(&nmax[i], (unsigned long long)nb[i]);
   __syncthreads();
   if (tid < 8) {
     uint64_t v = 0;
     if (tid < 7) {
-      for (int w = 0; w < NWAVE; ++w) v = nred[w][tid] > v ? nred[w][tid] : v;
+      v = nmax[tid];
     } else {
       // the host-mapped flag costs a PCIe round trip (~13 us measured), so it is read at
       // every kAbortEvery-th check only
@@ -580,14 +605,27 @@ __device__ __forceinline__ void load_lds_rows(const LayerArgs& a, int j, int r0,
 // NRS rows of each block in registers, NLM in LDS, the rest streamed. The loop between two
 // checks is kept free of everything the check needs, and the register rows are reloaded at
 // every check, so the check code does not compete with them for registers.
+// The kernel reads its arguments through the kernarg segment pointer made opaque at the start of
+// each phase (fresh), so a phase loads the fields it uses instead of every field of the whole
+// persistent loop staying in scalar registers (which spills them into vector registers).
+typedef const __attribute__((address_space(4))) LayerArgs* cargs_t;
+__device__ __forceinline__ const LayerArgs& fresh(cargs_t p) {
+  asm volatile("" : "+s"(p));
+  return *(const LayerArgs*)p;
+}
+
 template <typename T, int NC, int NRS, int NLM, bool XT>
-__global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
+__global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a_in) {
+  (void)a_in;
+  const cargs_t kp = (cargs_t)__builtin_amdgcn_kernarg_segment_ptr();
+  const LayerArgs& a = fresh(kp);
   constexpr int NW = LLWords<T>::kWords;
   __shared__ T red[NWAVE][kMaxRows];
   __shared__ int fail_flag;
   __shared__ RhoTable rt;
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   T* wl = reinterpret_cast<T*>(dyn_lds);
+  T* const cstage = wl + NLM * NC * BS;  // the check vector (check_cols entries) after the LDS rows
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid % kWave, wave = tid / kWave;
@@ -622,6 +660,8 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   if (rs.own && !rs.xrow) seq = a.eq[rs.R - n] != 0;
   int j = a.warm ? *a.js : a.j0;
   int lds_j = -1;  // penalty index of the rows now in LDS
+  int wst_j = -1;  // penalty index of the rows now in registers
+  T wst[NRS][NC];
   __shared__ T upd[kMaxRows][2];
   // this workgroup's share of the x rows for the dual side of the check, and their q
   // (split_term, split_row: a running maximum over h <= g, here a prefix maximum over wave 0,
@@ -665,6 +705,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
   const bool closed = XT && a.Ad != nullptr;
 
   for (int sv = 0; sv < a.count; ++sv) {
+    const LayerArgs& a = fresh(kp);
     const uint32_t tag = a.tag + (uint32_t)sv * span;
     const bool warm = sv == 0 ? a.warm != 0 : a.chain != 0;
 
@@ -760,7 +801,7 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       }
       // the constraint rows of the block: [A, 0] [x; y]
       const int pb = r0 > n ? r0 : n;
-      check_rows<T, NC>(a, 0, 0, pb, r0 + nrows > pb ? r0 + nrows - pb : 0, cv, cres);
+      check_rows<T, NC>(a, 0, 0, pb, r0 + nrows > pb ? r0 + nrows - pb : 0, cv, cres, cstage, a.check_cols);
       if (rs.own && !rs.xrow) {
         rs.ax = cres[rs.R - pb][0];
         rs.sz = (T)rs.ax;
@@ -774,14 +815,18 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       if (rs.own) ll_store(a.xw + ((long)L + rs.R) * NW, w1, tag + 1u);
     }
 
-    // the register rows of the active penalty (reloaded at every check while the norms are
-    // exchanged, so that the check's own work does not compete with them for registers)
+    // the register rows of the active penalty: loaded at the start unless the previous solve
+    // left them in place, and at every check while the norms are exchanged (dead during the
+    // check's own work, so they do not compete with it for registers)
+    if (wst_j != j) {
+      load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+      wst_j = j;
+    }
     int k = 0;
     while (true) {
       const int kend = (k / ci + 1) * ci < max_iter ? (k / ci + 1) * ci : max_iter;
       {
-        T wst[NRS][NC];
-        load_stationary<T, NC, NRS>(a, j, r0, nstat, wst);
+        const LayerArgs& a = fresh(kp);
         const T alpha = (T)a.alpha, oma = (T)(1.0 - a.alpha), sigma = (T)a.sigma;
         [[maybe_unused]] const double alpha_d = a.alpha, oma_d = 1.0 - a.alpha;
         uint64_t* xw = a.xw;
@@ -852,11 +897,12 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
         }
       }
 
+      const LayerArgs& ac = fresh(kp);
       // a fixed budget that is not a multiple of the check interval ends without a check
       // (closed loops; they run the XT instantiation)
       if constexpr (XT) {
-        if (!a.final_check && k == max_iter && k % ci != 0) {
-          finish<T, XT>(a, rs, sv, k, ST_MAX_ITER, j, tag, exs);
+        if (!ac.final_check && k == max_iter && k % ci != 0) {
+          finish<T, XT>(ac, rs, sv, k, ST_MAX_ITER, j, tag, exs);
           break;  // next solve of the sequence
         }
       }
@@ -864,28 +910,32 @@ __global__ void __launch_bounds__(BS) layer_kernel(LayerArgs a) {
       // check at iteration k (every check_interval iterations and at max_iter)
       __syncthreads();
       CheckOut co{ST_RUNNING, j, false};
-      if (check_partials<T, NC, XT>(a, rs, r0, nrows, cb, nck, cq, k, nchk, tag, cres, rs.ax)) {
-        co = check_decide<T>(a, rt, k, nchk, j, tag, (long)sv * a.max_checks);
+      if (check_partials<T, NC, XT>(ac, rs, r0, nrows, cb, nck, cq, k, nchk, tag, cres, cstage, rs.ax)) {
+        load_stationary<T, NC, NRS>(ac, j, r0, nstat, wst);  // in flight while the norms are exchanged
+        wst_j = j;
+        co = check_decide<T>(ac, rt, k, nchk, j, tag, (long)sv * ac.max_checks);
       }
       ++nchk;
       if (!co.ok) {
-        if (tid == 0) err_raise(a.err, tag);
-        finish<T, XT>(a, rs, sv, k, ST_INTERNAL, j, tag, exs);
+        if (tid == 0) err_raise(ac.err, tag);
+        finish<T, XT>(ac, rs, sv, k, ST_INTERNAL, j, tag, exs);
         return;
       }
       if (co.status != ST_RUNNING) {
-        finish<T, XT>(a, rs, sv, k, co.status, j, tag, exs);
+        finish<T, XT>(ac, rs, sv, k, co.status, j, tag, exs);
         break;  // next solve of the sequence
       }
       if (co.jn != j) {
         j = co.jn;
-        srho = (T)(rt.grid[j] * (seq ? a.rho_eq_scale : 1.0));
-        load_lds_rows<T, NC, NLM>(a, j, r0, NRS, nlds, wl);
+        srho = (T)(rt.grid[j] * (seq ? ac.rho_eq_scale : 1.0));
+        load_lds_rows<T, NC, NLM>(ac, j, r0, NRS, nlds, wl);
         lds_j = j;
+        load_stationary<T, NC, NRS>(ac, j, r0, nstat, wst);
+        wst_j = j;
       }
-      const T sigma = (T)a.sigma;
+      const T sigma = (T)ac.sigma;
       const T wn = rs.xrow ? sigma * rs.sx - rs.sq : srho * rs.sz - rs.sy;
-      if (rs.own) ll_store(a.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
+      if (rs.own) ll_store(ac.xw + ((long)((k + 1) & 1) * L + rs.R) * NW, wn, tag + (uint32_t)(k + 1));
     }
   }
 
@@ -957,10 +1007,17 @@ LaunchPlan plan_layer(int L, int grid, bool xt) {
   const long row_bytes = (long)kc.nc * BS * sizeof(T);
   const long room = (long)smem_max - (long)fa.sharedSizeBytes;
   const int lds_rows = kc.nlm;  // the kernel always keeps NLM rows (zeros past the block)
-  if ((long)lds_rows * row_bytes > room) return p;
+  // the check vector takes the rest of LDS, whole if it fits, in multiples of a check item
+  const long qw = check_width<T>();
+  const long left = room - (long)lds_rows * row_bytes;
+  const long whole = ((long)L + qw - 1) / qw * qw;
+  long ch = left / (long)sizeof(T) / qw * qw;
+  if (ch > whole) ch = whole;
+  if (ch < qw) return p;
   p.fn = kc.fn;
   p.lds_rows = lds_rows;
-  p.dyn_bytes = (size_t)lds_rows * row_bytes;
+  p.check_cols = (int)ch;
+  p.dyn_bytes = (size_t)lds_rows * row_bytes + (size_t)ch * sizeof(T);
   if (hipFuncSetAttribute(kc.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.dyn_bytes) != hipSuccess) {
     p.fn = nullptr;
     return p;
@@ -980,6 +1037,7 @@ hipError_t launch_layer(const LayerArgs& a, const LaunchPlan& p, int grid, hipSt
   if (!p.fn) return hipErrorInvalidValue;
   LayerArgs copy = a;
   copy.lds_rows = p.lds_rows;
+  copy.check_cols = p.check_cols;
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel(p.fn, dim3(grid), dim3(BS), args, p.dyn_bytes, st);
 }
