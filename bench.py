@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--dense-problems", type=int, default=10, help="dense: problems per size")
     ap.add_argument("--dense-reps", type=int, default=3, help="dense: timed solves per problem")
     ap.add_argument("--dense-precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only one device copy of 256 MiB (the reference for the HBM byte counters) and exit")
     ap.add_argument("--workload", choices=["c0", "c1", "c2", "batch", "serve", "dense", "closed", "forms"],
                     default="c1",
                     help="c1: one instance per solve (the headline, n = m = 1600); c0: the n = m = 20 FP64 "
@@ -268,6 +270,8 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        return copy_calibration()
     if args.steps < 1 or args.warmup < 0:
         raise SystemExit("--steps must be >= 1 and --warmup >= 0")
     if args.workload == "batch":
@@ -288,6 +292,20 @@ def main():
 
     rq.close_all()  # every handle is closed before the interpreter (and a profiler) shuts down
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration():
+    """One device-to-device copy of 256 MiB: what rocprofv3's FETCH_SIZE and WRITE_SIZE read for
+    it, against the 256 MiB each way the copy moves, gives the factors that turn the counters of a
+    kernel into HBM bytes."""
+    import torch
+
+    a = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4}), flush=True)
 
 
 def variants(args):
