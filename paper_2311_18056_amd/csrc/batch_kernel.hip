@@ -862,13 +862,29 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
       const auto& a = *fresh(kp);
       if (a.status[b] != ST_RUNNING) continue;  // the same for every lane of the wave
       const long pos = a.pos_of[b];
+      const double* const px = a.Rpx + pos * n;
+      const double* const pa = a.Raty + pos * n;
+      const float* const qb = a.Q + b * n;
       uint64_t vrd = 0, vq = 0;
-      for (int r = lane; r < n; r += 64) {
-        const double pp = a.Rpx[pos * n + r], pa = a.Raty[pos * n + r], q = (double)a.Q[b * n + r];
-        const double dq = uq * fabs(q);
-        const uint64_t x1 = abs_bits(fabs(pp + pa + q) + dq), x2 = abs_bits(lower_bound(fabs(q), dq));
-        vrd = x1 > vrd ? x1 : vrd;
-        vq = x2 > vq ? x2 : vq;
+      // kDecRows rows per lane and pass, all loads of a pass issued before any use
+      constexpr int kDecRows = 8;
+      for (int r0 = 0; r0 < n; r0 += 64 * kDecRows) {
+        double pv[kDecRows], av[kDecRows], qv[kDecRows];
+#pragma unroll
+        for (int u = 0; u < kDecRows; ++u) {
+          const int r = r0 + lane + 64 * u;
+          const bool in = r < n;
+          pv[u] = in ? px[r] : 0.0;
+          av[u] = in ? pa[r] : 0.0;
+          qv[u] = in ? (double)qb[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kDecRows; ++u) {
+          const double dq = uq * fabs(qv[u]);
+          const uint64_t x1 = abs_bits(fabs(pv[u] + av[u] + qv[u]) + dq), x2 = abs_bits(lower_bound(fabs(qv[u]), dq));
+          vrd = x1 > vrd ? x1 : vrd;
+          vq = x2 > vq ? x2 : vq;
+        }
       }
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
