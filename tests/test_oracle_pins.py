@@ -309,3 +309,52 @@ def test_validation_errors():
     Pn[0, 0] = np.inf
     with pytest.raises(ValueError):
         oracle.solve(Pn, q, A, l, u, admm.Settings())
+
+
+# --------------------------------------------------------------------------- tolerance split
+# The convergence criteria (Sec. III-C, eqs. primal and dual) compare each residual with its
+# own tolerance; the relative part follows OSQP: the primal one scales with max(|Ax|, |z|),
+# the dual one with max(|Px|, |A'y|, |q|). Two exact changes of units pin that split without
+# restating it: scaling the cost by c (P, q, sigma, rho by c) keeps x and z and multiplies y
+# by c; scaling the constraint rows by d (A, l, u by d, rho by 1/d^2) keeps x and multiplies
+# z by d and y by 1/d. With eps_abs = 0 a correct split takes the same decision at every check
+# under both; a split that puts any dual term into the primal tolerance (or the converse), or
+# leaves out the relative part of either, stops at another iteration once c or d is 2^16.
+
+
+def _scaled_solve(P, q, A, l, u, s, c=1.0, d=1.0):
+    from dataclasses import replace
+
+    s2 = replace(s, rho0=s.rho0 * c / (d * d), sigma=s.sigma * c)
+    return oracle.solve(c * P, c * q, d * A, d * l, d * u, s2)
+
+
+@pytest.mark.parametrize("c,d", [(2.0**16, 1.0), (2.0**-16, 1.0), (1.0, 2.0**16), (1.0, 2.0**-16)])
+def test_tolerance_split_is_unit_invariant(c, d):
+    P, q, A, l, u = random_qp(30, 8, 8, seed=5)
+    s = admm.Settings(eps_abs=0.0, eps_rel=1e-5, n_rho=1, rho0=0.1, max_iter=4000)
+    r0 = _scaled_solve(P, q, A, l, u, s)
+    assert r0.status == oracle.SOLVED and r0.iterations >= 100  # several checks decide
+    r1 = _scaled_solve(P, q, A, l, u, s, c, d)
+    assert r1.status == oracle.SOLVED and r1.iterations == r0.iterations
+    np.testing.assert_allclose(r1.x, r0.x, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r1.z / d, r0.z, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(r1.y * d / c, r0.y, rtol=1e-9, atol=1e-12)
+
+
+def test_tolerance_split_mistakes_are_caught(monkeypatch):
+    """The pin above fails for a swapped split (a mistake planted in the oracle, on the CPU)."""
+    P, q, A, l, u = random_qp(30, 8, 8, seed=5)
+    s = admm.Settings(eps_abs=0.0, eps_rel=1e-5, n_rho=1, rho0=0.1, max_iter=4000)
+    true_norms = admm.residual_norms
+
+    def swapped(*args):
+        nm = dict(true_norms(*args))
+        nm["Ax"], nm["z"], nm["Px"], nm["Aty"], nm["q"] = nm["Px"], nm["Aty"], nm["Ax"], nm["z"], 0.0
+        return nm
+
+    monkeypatch.setattr(admm, "residual_norms", swapped)
+    r0 = _scaled_solve(P, q, A, l, u, s)
+    r1 = _scaled_solve(P, q, A, l, u, s, 2.0**16, 1.0)
+    r2 = _scaled_solve(P, q, A, l, u, s, 1.0, 2.0**16)
+    assert r1.iterations != r0.iterations or r2.iterations != r0.iterations
