@@ -87,7 +87,9 @@ typedef struct {
   int scaling;         /* passes of the modified Ruiz equilibration with cost scaling (Algorithm 1
                         * "scale problem", Sec. III-D; OSQP's form): 0 (default) = none, at most
                         * 100. The solve iterates on the scaled problem; termination, residuals
-                        * and outputs are in the original units. Single-instance engine only. */
+                        * and outputs are in the original units. On the batched engine one
+                        * scaling serves the batch (its cost scale from the largest |q| entry
+                        * over the setup instances); closed loops run unscaled. */
 } relu_qp_settings;
 
 typedef struct relu_qp_handle relu_qp_handle; /* opaque, library-owned */

@@ -40,10 +40,16 @@ struct BatchArgs {
   const void* Wa;           // FP32 layer matrices, or BF16 high parts: n_rho blocked lpad x ldk
   const void* Wb;           // BF16 low parts (kBatchBF16x3), else null
   long w_stride;            // elements between penalty matrices
-  const double* Cd;         // check matrix [P, A'; A, 0] in FP64, same format (blocked cpad x ldk)
+  const double* Cd;         // check matrix [P, A'; A, 0] in FP64, same format (blocked cpad x ldk);
+                            // with Ruiz scaling the original (unscaled) P and A
   const float* Q;           // B x n
   const float* Lo;          // B x m
   const float* Up;          // B x m
+  // Ruiz scaling (null: none). The layer runs on the scaled problem (x = D xb, z = zb / E,
+  // y = E yb / c); Q, Lo, Up hold c D q, E l, E u. Layout: c D (n), E (m), 1 / (c D) (n),
+  // 1 / E (m), D (n), E / c (m). The check evaluates the original problem at the unscaled
+  // iterates rounded to FP32 exactly as the outputs are (unscale_outputs).
+  const double* scl;
   const unsigned char* eq;  // m
   const double* grid;
   const double* mid;
@@ -58,7 +64,8 @@ struct BatchArgs {
   // rows are contiguous
   void* Va;                 // layer inputs, 2 parities x blocked bpad x ldk (FP32, or BF16 high)
   void* Vb;                 // BF16 low parts
-  double* CVd;              // check operand [x; y] in FP64 (exact copies of the FP32 iterates), blocked bpad x ldk
+  double* CVd;              // check operand [x; y] in FP64 (exact copies of the FP32 iterates, unscaled
+                            // as the outputs are), blocked bpad x ldk
   double* Rpx;              // B x n: P x of list position p in row p (check scratch)
   double* Raty;             // B x n: A'y likewise
   int* jb;                  // B penalty indices (kept for running and warm-admitted slots)
@@ -93,13 +100,21 @@ hipError_t fill_status(int B, int value, int* status, hipStream_t st);
 // parametric data F, E, lo, hi; or copied from FP64 device rows (a NULL vector is kept).
 hipError_t load_x0_slots(const SlotList& sl, int n, int m, int nx, const double* F, const double* E, const double* lo,
                          const double* hi, const double* x0, float* Q, float* Lo, float* Up, hipStream_t st);
+// With Ruiz scaling (scl != null) the copied rows are scaled on the way (c D q, E l, E u); the
+// parametric data of load_x0_slots is scaled once at set-up instead.
 hipError_t load_slots(const SlotList& sl, int n, int m, const double* q, const double* l, const double* u, float* Q,
-                      float* Lo, float* Up, hipStream_t st);
+                      float* Lo, float* Up, const double* scl, hipStream_t st);
 // Admit the listed slots: cold (src == -1), or warm from slot src's x and y shifted by sx / sy
 // entries (entries shifted in from beyond the end are 0) and its penalty index. The source is
-// first copied to stage (n + m floats and one int); src == -2 reuses what stage holds.
+// first copied to stage (n + m floats and one int); src == -2 reuses what stage holds. With Ruiz
+// scaling (scl != null) a shifted entry moves to another row's units: x_i <- x_{i+sx} D_{i+sx} / D_i,
+// y_i <- y_{i+sy} (E/c)_{i+sy} / (E/c)_i (an unshifted copy stays exact).
 hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m, float* X, float* Y, int* jb,
-                       int* status, float* stage, hipStream_t st);
+                       int* status, float* stage, const double* scl, hipStream_t st);
+// Outputs in original units from the scaled state: x = D xb, z = zb (1 / E), y = yb (E / c), each
+// rounded to FP32 from the FP64 product (the values the check evaluated).
+hipError_t unscale_outputs(int B, int n, int m, const float* X, const float* Z, const float* Y, const double* scl,
+                           float* x, float* z, float* y, hipStream_t st);
 hipError_t launch_batch(const BatchArgs& a, const BatchPlan& p, hipStream_t st);
 
 // FP64 row-major rows x cols -> K-blocked lpad x ldk (zero padded): BF16 high and low parts,

@@ -638,7 +638,8 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
       for (int u = 0; u < kU; ++u) {
         const long el = base + u * gstride;
         if (el >= (long)B * L || st[u] != kSlotAdmitWarm) continue;
-        a.CVd[opidx(a.bpad, ps[u], (int)(el % L))] = (double)xv[u];
+        const int r = (int)(el % L);
+        a.CVd[opidx(a.bpad, ps[u], r)] = (double)xv[u] * (a.scl && r < n ? a.scl[2 * n + 2 * m + r] : 1.0);
       }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
@@ -658,10 +659,11 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
         for (int j = 0; j < 4; ++j) {
           const int r = r0 + acc64_col(wn, j, lane);
           if (r >= L) continue;
+          const double fe = a.scl ? a.scl[r] : 1.0;  // E of constraint row r - n (zb = E A x)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int ti = acc64_row(wm, i, v, lane);
-            if (ti < mt.cnt) a.Z[(long)s_list[ti] * m + (r - n)] = (float)acc[i][j][v];
+            if (ti < mt.cnt) a.Z[(long)s_list[ti] * m + (r - n)] = (float)(acc[i][j][v] * fe);
           }
         }
     }
@@ -727,6 +729,8 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
           // operand index of element v: obase + oo[v] (K-blocked, list position mt.off + ti)
           const unsigned obase = ((unsigned)(r / TK) * (unsigned)ae.bpad + (unsigned)mt.off) * TK + (unsigned)(r % TK);
           if (r < n) {
+            // check operand: x in original units, rounded as the output is
+            const double fx = ae.scl ? ae.scl[2 * n + 2 * m + r] : 1.0;
             float xo[16], qv[16];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -739,13 +743,14 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
               if (!ok[v]) continue;
               at32(ae.X, on[v] + r) = x;
               if (is_check)
-                at32(ae.CVd, obase + oo[v]) = (double)x;
+                at32(ae.CVd, obase + oo[v]) = (double)(float)((double)x * fx);
               else
                 put_operand32<PREC>(vo, vo2, obase + oo[v], sigma * x - qv[v]);
             }
           } else {
             const int ri = r - n;
             const float rho = rho_bar * (ae.eq[ri] ? eqs : 1.0f), rinv = 1.0f / rho;
+            const double fy = ae.scl ? ae.scl[3 * n + 2 * m + ri] : 1.0;
             float zo[16], yo[16], lo[16], up[16];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -763,7 +768,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
               at32(ae.Z, om[v] + ri) = zn;
               at32(ae.Y, om[v] + ri) = yn;
               if (is_check)
-                at32(ae.CVd, obase + oo[v]) = (double)yn;
+                at32(ae.CVd, obase + oo[v]) = (double)(float)((double)yn * fy);
               else
                 put_operand32<PREC>(vo, vo2, obase + oo[v], rho * zn - yn);
             }
@@ -809,7 +814,8 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
                 nb[0] = vb > nb[0] ? vb : nb[0];
               } else {
                 if (!valid_i || r >= L) continue;
-                const double z = (double)a.Z[b * m + (r - n)];
+                // z in original units, rounded as the output is
+                const double z = (double)(float)((double)a.Z[b * m + (r - n)] * (a.scl ? a.scl[n + m + r] : 1.0));
                 const uint64_t vrp = abs_bits(pv - z), vax = abs_bits(pv), vz = abs_bits(z);
                 nb[0] = vrp > nb[0] ? vrp : nb[0];
                 nb[1] = vax > nb[1] ? vax : nb[1];
@@ -865,6 +871,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
       const double* const px = a.Rpx + pos * n;
       const double* const pa = a.Raty + pos * n;
       const float* const qb = a.Q + b * n;
+      const double* const sq = a.scl ? a.scl + n + m : nullptr;  // 1 / (c D): q = qb / (c D)
       uint64_t vrd = 0, vq = 0;
       // kDecRows rows per lane and pass, all loads of a pass issued before any use
       constexpr int kDecRows = 8;
@@ -876,7 +883,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
           const bool in = r < n;
           pv[u] = in ? px[r] : 0.0;
           av[u] = in ? pa[r] : 0.0;
-          qv[u] = in ? (double)qb[r] : 0.0;
+          qv[u] = in ? (double)qb[r] * (sq ? sq[r] : 1.0) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kDecRows; ++u) {
@@ -1018,11 +1025,18 @@ __global__ void stage_kernel(int src, int n, int m, const float* __restrict__ X,
 // one workgroup per listed slot
 __global__ void admit_kernel(SlotList sl, int warm, int sx, int sy, int n, int m, float* __restrict__ X,
                              float* __restrict__ Y, int* __restrict__ jb, int* __restrict__ status,
-                             const float* __restrict__ stage) {
+                             const float* __restrict__ stage, const double* __restrict__ scl) {
   const long s = sl.s[blockIdx.x];
   if (warm) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) X[s * n + i] = i + sx < n ? stage[i + sx] : 0.0f;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) Y[s * m + i] = i + sy < m ? stage[n + i + sy] : 0.0f;
+    // scaled state: a shifted entry changes rows, so it changes units (D for x, E / c for y)
+    const double* fx = scl && sx ? scl + 2 * n + 2 * m : nullptr;
+    const double* fy = scl && sy ? scl + 3 * n + 2 * m : nullptr;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      X[s * n + i] = i + sx >= n ? 0.0f : fx ? (float)((double)stage[i + sx] * fx[i + sx] / fx[i]) : stage[i + sx];
+    for (int i = threadIdx.x; i < m; i += blockDim.x)
+      Y[s * m + i] = i + sy >= m ? 0.0f
+                     : fy ? (float)((double)stage[n + i + sy] * fy[i + sy] / fy[i])
+                          : stage[n + i + sy];
   }
   if (threadIdx.x == 0) {
     if (warm) jb[s] = reinterpret_cast<const int*>(stage)[n + m];
@@ -1053,18 +1067,39 @@ __global__ void __launch_bounds__(256) x0_slots_kernel(SlotList sl, int n, int m
   }
 }
 // q, l, u rows of the listed slots from FP64 device arrays (n_slots x n, n_slots x m)
+// (scaled with Ruiz scaling: c D q, E l, E u)
 __global__ void vec_slots_kernel(SlotList sl, int n, int m, const double* __restrict__ q, const double* __restrict__ l,
                                  const double* __restrict__ u, float* __restrict__ Q, float* __restrict__ Lo,
-                                 float* __restrict__ Up) {
+                                 float* __restrict__ Up, const double* __restrict__ scl) {
   const int i = blockIdx.x;
   const long s = sl.s[i];
   for (int r = threadIdx.x; r < n + m; r += blockDim.x) {
+    const double f = scl ? scl[r] : 1.0;  // c D_r, or E of constraint row r - n
     if (r < n) {
-      if (q) Q[s * n + r] = (float)q[(long)i * n + r];
+      if (q) Q[s * n + r] = (float)(f * q[(long)i * n + r]);
     } else {
-      if (l) Lo[s * m + (r - n)] = (float)l[(long)i * m + (r - n)];
-      if (u) Up[s * m + (r - n)] = (float)u[(long)i * m + (r - n)];
+      if (l) Lo[s * m + (r - n)] = (float)(f * l[(long)i * m + (r - n)]);
+      if (u) Up[s * m + (r - n)] = (float)(f * u[(long)i * m + (r - n)]);
     }
+  }
+}
+// One thread per output element: x = D xb, z = zb (1 / E), y = yb (E / c), each FP32 from the
+// FP64 product (the same operations the check applies to its operands).
+__global__ void unscale_kernel(long B, int n, int m, const float* __restrict__ X, const float* __restrict__ Z,
+                               const float* __restrict__ Y, const double* __restrict__ scl, float* __restrict__ x,
+                               float* __restrict__ z, float* __restrict__ y) {
+  const long per = (long)n + 2L * m, e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * per) return;
+  const long b = e / per;
+  const int r = (int)(e % per);
+  if (r < n) {
+    x[b * n + r] = (float)((double)X[b * n + r] * scl[2 * n + 2 * m + r]);
+  } else if (r < n + m) {
+    const int i = r - n;
+    z[b * m + i] = (float)((double)Z[b * m + i] * scl[2 * n + m + i]);
+  } else {
+    const int i = r - n - m;
+    y[b * m + i] = (float)((double)Y[b * m + i] * scl[3 * n + 2 * m + i]);
   }
 }
 }  // namespace
@@ -1079,9 +1114,18 @@ hipError_t load_x0_slots(const SlotList& sl, int n, int m, int nx, const double*
 }
 
 hipError_t load_slots(const SlotList& sl, int n, int m, const double* q, const double* l, const double* u, float* Q,
-                      float* Lo, float* Up, hipStream_t st) {
+                      float* Lo, float* Up, const double* scl, hipStream_t st) {
   if (sl.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(vec_slots_kernel, dim3((unsigned)sl.n), dim3(256), 0, st, sl, n, m, q, l, u, Q, Lo, Up);
+  hipLaunchKernelGGL(vec_slots_kernel, dim3((unsigned)sl.n), dim3(256), 0, st, sl, n, m, q, l, u, Q, Lo, Up, scl);
+  return hipGetLastError();
+}
+
+hipError_t unscale_outputs(int B, int n, int m, const float* X, const float* Z, const float* Y, const double* scl,
+                           float* x, float* z, float* y, hipStream_t st) {
+  const long total = (long)B * ((long)n + 2L * m);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(unscale_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, (long)B, n, m, X, Z, Y,
+                     scl, x, z, y);
   return hipGetLastError();
 }
 
@@ -1091,7 +1135,7 @@ hipError_t fill_status(int B, int value, int* status, hipStream_t st) {
 }
 
 hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m, float* X, float* Y, int* jb,
-                       int* status, float* stage, hipStream_t st) {
+                       int* status, float* stage, const double* scl, hipStream_t st) {
   if (sl.n <= 0) return hipSuccess;
   if (src >= 0) {
     hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(256), 0, st, src, n, m, X, Y, jb, stage);
@@ -1099,7 +1143,7 @@ hipError_t admit_slots(const SlotList& sl, int src, int sx, int sy, int n, int m
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(admit_kernel, dim3((unsigned)sl.n), dim3(256), 0, st, sl, src != -1 ? 1 : 0, sx, sy, n, m, X, Y,
-                     jb, status, stage);
+                     jb, status, stage, scl);
   return hipGetLastError();
 }
 

@@ -264,7 +264,6 @@ int validate_settings(const relu_qp_settings* s) {
   if (batched && s->precision == RQP_FP64) return fail(RQP_EINVAL, "the batched engine runs FP32 or BF16X3");
   if (!batched && s->precision == RQP_BF16X3) return fail(RQP_EINVAL, "BF16X3 needs the batched engine");
   if (!batched && s->batch != 1) return fail(RQP_EINVAL, "the single-instance engine needs batch == 1");
-  if (batched && s->scaling > 0) return fail(RQP_EINVAL, "Ruiz scaling runs on the single-instance engine");
   return RQP_OK;
 }
 
@@ -279,9 +278,14 @@ double clip_scale(double v) {
   return d < 1e-4 ? 1e-4 : (d > 1e4 ? 1e4 : d);
 }
 
-void ruiz(int n, int m, const double* P0, const double* q0, const double* A0, int passes, std::vector<double>& D,
-          std::vector<double>& E, double& c) {
-  std::vector<double> P(P0, P0 + (size_t)n * n), A(A0, A0 + (size_t)m * n), q(q0, q0 + n);
+// q0 holds nq rows (the instances of a batch): the cost scale takes the largest |q| entry over
+// all of them, so one scaling serves every instance (each pass scales q's entries by positive
+// factors, so the entry-wise largest magnitudes over the rows are all that matters).
+void ruiz(int n, int m, const double* P0, const double* q0, int nq, const double* A0, int passes,
+          std::vector<double>& D, std::vector<double>& E, double& c) {
+  std::vector<double> P(P0, P0 + (size_t)n * n), A(A0, A0 + (size_t)m * n), q(n, 0.0);
+  for (int b = 0; b < nq; ++b)
+    for (int i = 0; i < n; ++i) q[i] = std::max(q[i], std::fabs(q0[(size_t)b * n + i]));
   D.assign(n, 1.0);
   E.assign(m, 1.0);
   c = 1.0;
@@ -515,8 +519,10 @@ bool is_batched(const relu_qp_settings& s) {
 
 int upload_f32(float* dst, const double* src, size_t count) { return upload_vec<float>(dst, src, count); }
 
-// Layer and check matrices for the batched engine, FP32 or BF16 high/low, rows padded to ldk.
-int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hipStream_t st) {
+// Layer matrices for the batched engine (FP32 or BF16 high/low, rows padded to ldk) from P and A,
+// and the FP64 check matrix from P0 and A0 (the original problem when P and A are scaled).
+int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, const double* P0, const double* A0,
+                        hipStream_t st) {
   const int n = h->n, m = h->m, L = h->L;
   DevBuf P_d, A_d, Gw, K, DAt, ADAt, work, omega, info, Wd;
   const size_t nn = (size_t)n * n, mn = (size_t)m * n, mm = (size_t)m * m, LL = (size_t)L * L;
@@ -547,6 +553,8 @@ int build_batch_weights(relu_qp_handle* h, const double* P, const double* A, hip
                                h->ldk, st));
   }
   // the check matrix stays FP64 (the residuals are FP64 evaluations of the iterates)
+  if (P0 != P) HIP_OR_FAIL(hipMemcpyAsync(P_d.p, P0, nn * 8, hipMemcpyHostToDevice, st));
+  if (A0 != A) HIP_OR_FAIL(hipMemcpyAsync(A_d.p, A0, mn * 8, hipMemcpyHostToDevice, st));
   HIP_OR_FAIL(rqp::assemble_check<double>(n, m, P_d.d(), A_d.d(), Wd.d(), L, st));
   HIP_OR_FAIL(rqp::pad_f64(L, L, Wd.d(), L, h->bCd, h->cpad, h->ldk, st));
   int hinfo = 0;
@@ -561,7 +569,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
                    bool fixed_iters = false);
 
 int setup_batched(relu_qp_handle* h, const double* P, const double* q, const double* A, const double* l,
-                  const double* u, hipStream_t st) {
+                  const double* u, const double* P0, const double* A0, hipStream_t st) {
   const int n = h->n, m = h->m, L = h->L, B = h->batch;
   h->batched = true;
   h->bprec = h->s.precision == RQP_BF16X3 ? rqp::kBatchBF16x3 : rqp::kBatchF32;
@@ -614,7 +622,7 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
       (rc = upload_f32(static_cast<float*>(h->l), l, (size_t)B * m)) ||
       (rc = upload_f32(static_cast<float*>(h->u), u, (size_t)B * m)))
     return rc;
-  if ((rc = build_batch_weights(h, P, A, st))) return rc;
+  if ((rc = build_batch_weights(h, P, A, P0, A0, st))) return rc;
   for (int v = 0; v < rqp::kTileShapes; ++v) {
     h->bplans[v] = rqp::plan_batch(h->bprec, rqp::kTileRows[v]);
     if (!h->bplans[v].fn) return fail(RQP_EHIP, "no resources for the batched kernel (%d-row tiles)", rqp::kTileRows[v]);
@@ -648,6 +656,7 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   a.Q = static_cast<const float*>(h->q);
   a.Lo = static_cast<const float*>(h->l);
   a.Up = static_cast<const float*>(h->u);
+  a.scl = h->scl;
   a.eq = h->eq_d;
   a.grid = h->grid_d;
   a.mid = h->mid_d;
@@ -687,9 +696,14 @@ int launch_batched(relu_qp_handle* h, int steps, hipStream_t st, relu_qp_result*
   hipError_t e = rqp::launch_batch(a, h->bplan, st);
   if (e != hipSuccess) return fail(RQP_EHIP, "batched launch failed: %s", hipGetErrorString(e));
   if (!copy_out) return RQP_OK;
-  HIP_OR_FAIL(hipMemcpyAsync(out->x, h->bX, (size_t)B * h->n * 4, hipMemcpyDeviceToDevice, st));
-  HIP_OR_FAIL(hipMemcpyAsync(out->z, h->bZ, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
-  HIP_OR_FAIL(hipMemcpyAsync(out->y, h->bY, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
+  if (h->scl) {
+    HIP_OR_FAIL(rqp::unscale_outputs(B, h->n, h->m, h->bX, h->bZ, h->bY, h->scl, static_cast<float*>(out->x),
+                                     static_cast<float*>(out->z), static_cast<float*>(out->y), st));
+  } else {
+    HIP_OR_FAIL(hipMemcpyAsync(out->x, h->bX, (size_t)B * h->n * 4, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(out->z, h->bZ, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
+    HIP_OR_FAIL(hipMemcpyAsync(out->y, h->bY, (size_t)B * h->m * 4, hipMemcpyDeviceToDevice, st));
+  }
   HIP_OR_FAIL(hipMemcpyAsync(out->rho_index, h->bjb, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
   HIP_OR_FAIL(hipMemcpyAsync(out->status, h->bstatus, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
   HIP_OR_FAIL(hipMemcpyAsync(out->iterations, h->biter, (size_t)B * 4, hipMemcpyDeviceToDevice, st));
@@ -913,32 +927,30 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
       hipMemcpy(h->mid_d, h->mid.data(), h->mid.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(RQP_EHIP, "initial copies failed"));
 
-  if (batched) {
-    if ((rc = setup_batched(h, P, q, A, l, u, st))) return bail(rc);
-    *hp = h;
-    return RQP_OK;
-  }
-
-  // Ruiz scaling: the device holds the scaled problem from here on
+  // Ruiz scaling: the device holds the scaled problem from here on (the batched engine's check
+  // keeps the original P and A)
+  const double *P0 = P, *A0 = A;
   std::vector<double> Ps, As, qs, ls, us;
   if (s->scaling > 0) {
-    ruiz(n, m, P, q, A, s->scaling, h->sD, h->sE, h->sc);
+    ruiz(n, m, P, q, B, A, s->scaling, h->sD, h->sE, h->sc);
     const std::vector<double>& D = h->sD;
     const std::vector<double>& E = h->sE;
     const double c = h->sc;
     Ps.resize((size_t)n * n);
     As.resize((size_t)m * n);
-    qs.resize(n);
-    ls.resize(m);
-    us.resize(m);
+    qs.resize((size_t)B * n);
+    ls.resize((size_t)B * m);
+    us.resize((size_t)B * m);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) Ps[(size_t)i * n + j] = c * (D[i] * P[(size_t)i * n + j] * D[j]);
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < n; ++j) As[(size_t)i * n + j] = E[i] * A[(size_t)i * n + j] * D[j];
-    for (int i = 0; i < n; ++i) qs[i] = c * D[i] * q[i];
-    for (int i = 0; i < m; ++i) {
-      ls[i] = E[i] * l[i];
-      us[i] = E[i] * u[i];
+    for (size_t b = 0; b < (size_t)B; ++b) {
+      for (int i = 0; i < n; ++i) qs[b * n + i] = c * D[i] * q[b * n + i];
+      for (int i = 0; i < m; ++i) {
+        ls[b * m + i] = E[i] * l[b * m + i];
+        us[b * m + i] = E[i] * u[b * m + i];
+      }
     }
     P = Ps.data();
     A = As.data();
@@ -961,6 +973,11 @@ int relu_qp_setup(relu_qp_handle** hp, int n, int m, const double* P, const doub
       (void)hipGetLastError();
       return bail(fail(RQP_ENOMEM, "scaling vectors: device allocation failed"));
     }
+  }
+  if (batched) {
+    if ((rc = setup_batched(h, P, q, A, l, u, P0, A0, st))) return bail(rc);
+    *hp = h;
+    return RQP_OK;
   }
 
   if (dmalloc(h, &h->W, nr * h->w_stride * h->esize) != hipSuccess ||
@@ -1001,6 +1018,26 @@ int relu_qp_update(relu_qp_handle* h, const double* q, const double* l, const do
       }
     }
     int rc;
+    std::vector<double> qv, lv, uv;
+    if (h->scl) {  // to scaled units: c D q, E l, E u
+      if (q) {
+        qv.resize((size_t)B * n);
+        for (size_t b = 0; b < (size_t)B; ++b)
+          for (int i = 0; i < n; ++i) qv[b * n + i] = h->sc * h->sD[i] * q[b * n + i];
+        q = qv.data();
+      }
+      if (l) {
+        lv.resize((size_t)B * m);
+        uv.resize((size_t)B * m);
+        for (size_t b = 0; b < (size_t)B; ++b)
+          for (int i = 0; i < m; ++i) {
+            lv[b * m + i] = h->sE[i] * l[b * m + i];
+            uv[b * m + i] = h->sE[i] * u[b * m + i];
+          }
+        l = lv.data();
+        u = uv.data();
+      }
+    }
     if (q && (rc = upload_f32(static_cast<float*>(h->q), q, (size_t)B * n))) return rc;
     if (l && ((rc = upload_f32(static_cast<float*>(h->l), l, (size_t)B * m)) ||
               (rc = upload_f32(static_cast<float*>(h->u), u, (size_t)B * m))))
@@ -1135,8 +1172,19 @@ int relu_qp_warm_start(relu_qp_handle* h, const double* x, const double* y, int 
   if (rho_index < 0 || rho_index >= (int)h->grid.size()) return fail(RQP_EINVAL, "rho_index out of range");
   int rc;
   if (h->batched) {
-    const int B = h->batch;
-    if ((rc = upload_f32(h->bX, x, (size_t)B * h->n)) || (rc = upload_f32(h->bY, y, (size_t)B * h->m))) return rc;
+    const int B = h->batch, n = h->n, m = h->m;
+    std::vector<double> xv, yv;
+    if (h->scl) {  // to scaled units: xb = x / D, yb = c y / E
+      xv.resize((size_t)B * n);
+      yv.resize((size_t)B * m);
+      for (size_t b = 0; b < (size_t)B; ++b) {
+        for (int i = 0; i < n; ++i) xv[b * n + i] = x[b * n + i] / h->sD[i];
+        for (int i = 0; i < m; ++i) yv[b * m + i] = h->sc * y[b * m + i] / h->sE[i];
+      }
+      x = xv.data();
+      y = yv.data();
+    }
+    if ((rc = upload_f32(h->bX, x, (size_t)B * n)) || (rc = upload_f32(h->bY, y, (size_t)B * m))) return rc;
     std::vector<int> jv(B, rho_index);
     HIP_OR_FAIL(hipMemcpy(h->bjb, jv.data(), (size_t)B * 4, hipMemcpyHostToDevice));
     h->warm_pending = true;
@@ -1479,7 +1527,7 @@ int relu_qp_load_slots(relu_qp_handle* h, const int* slots, int n_slots, const d
     const size_t n = h->n, m = h->m;
     HIP_OR_FAIL(rqp::load_slots(sl, h->n, h->m, q ? q + i0 * n : nullptr, l ? l + i0 * m : nullptr,
                                 u ? u + i0 * m : nullptr, static_cast<float*>(h->q), static_cast<float*>(h->l),
-                                static_cast<float*>(h->u), st));
+                                static_cast<float*>(h->u), h->scl, st));
     return RQP_OK;
   });
 }
@@ -1511,10 +1559,10 @@ int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot
     // the source state is staged once, before any listed slot (which may include it) is written
     if (src_slot >= 0 && !first) {
       HIP_OR_FAIL(rqp::admit_slots(sl, -2, shift_x, shift_y, h->n, h->m, h->bX, h->bY, h->bjb, h->bstatus,
-                                   h->bstage, st));
+                                   h->bstage, h->scl, st));
     } else {
       HIP_OR_FAIL(rqp::admit_slots(sl, src_slot, shift_x, shift_y, h->n, h->m, h->bX, h->bY, h->bjb, h->bstatus,
-                                   h->bstage, st));
+                                   h->bstage, h->scl, st));
     }
     first = false;
     return RQP_OK;
@@ -1669,6 +1717,7 @@ int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* b
     t += (1 + 3 * ntile_max) * 4 + 1024 * 4;                       // tile lists, barrier words
     t += B * n * 4 + 2 * B * m * 4;                                // q, l, u
     t += 2 * B * 4 + (L + 1) * 4;                                  // status, iterations, staging
+    if (s->scaling > 0) t += 3 * L * 8;                            // Ruiz scaling vectors
   } else {
     const size_t es = s->precision == RQP_FP64 ? 8 : 4;
     const size_t ldw = (L + 3) / 4 * 4, w_stride = L * ldw;

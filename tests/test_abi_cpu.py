@@ -143,8 +143,7 @@ def test_setup_rejects_bad_settings():
                      (dict(eps_abs=-1.0), "eps_abs"), (dict(max_iter=0), "max_iter"),
                      (dict(check_interval=0), "check_interval"), (dict(precision=7), "precision"),
                      (dict(engine=9), "engine"), (dict(batch=0), "batch"), (dict(rho_eq_scale=0.0), "rho_eq_scale"),
-                     (dict(scaling=-1), "scaling"), (dict(scaling=101), "scaling"),
-                     (dict(scaling=10, engine=rq._lib.RQP_ENGINE_BATCH), "single-instance")):
+                     (dict(scaling=-1), "scaling"), (dict(scaling=101), "scaling")):
         rc, msg = _setup_rc(2, 2, P, q, A, l, u, **kw)
         assert rc == E and word in msg, (kw, rc, msg)
 

@@ -187,6 +187,7 @@ def test_server_two_families(rq, light):
 @pytest.mark.parametrize("kw", [dict(precision="fp64", engine="single"), dict(precision="fp32", engine="single"),
                                 dict(precision="fp64", engine="single", scaling=10),
                                 dict(precision="fp32", engine="batch", batch=5),
+                                dict(precision="fp32", engine="batch", batch=5, scaling=10),
                                 dict(precision="bf16x3", engine="batch", batch=130)])
 def test_footprint_matches_the_bytes_a_handle_holds(rq, kw):
     """The host-side footprint (used to admit families by memory) equals what setup allocates."""
