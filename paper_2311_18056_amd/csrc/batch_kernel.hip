@@ -340,8 +340,9 @@ __device__ __forceinline__ int acc_col(int wn, int j, int lane) {
 // of a 16 x 4 by 4 x 16 step, and D[l / 16 + 4 v][l % 16] in element v: checked on the device
 // against a host product). A stage is the A rows then the B rows, 256-byte rows, two buffers.
 // Lane group g = l / 16 reads chunk 4 h + g of its row (two doubles, k = 8 h + 2 g + {0, 1}) and
-// feeds component s to the s-th of two products, so one read serves two products. Products of
-// FP64 data with FP32 iterates are exact in FP64, so the sums are FP64 dot products.
+// feeds component s to the s-th of two products, so one read serves two products. Both operands
+// are FP64 (the caller's data and exact copies of the returned FP32 values), so the sums are FP64
+// dot products of what the solve returns.
 constexpr int T64 = 128;
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 struct CheckGeo {
