@@ -77,6 +77,10 @@ __device__ __forceinline__ bool gather(const uint64_t* buf, int L, uint32_t tag,
 #pragma unroll
       for (int q = 0; q < NW; ++q) all &= ll_tag(w[k][q]) == tag;
     if (all) break;
+    // a short pause between polls (about 0.1 us) thins the polling traffic of all workgroups on
+    // the fabric while the producers' stores travel (1 % faster per iteration than polling back
+    // to back; longer pauses lose more to the wake-up delay than they save)
+    __builtin_amdgcn_s_sleep(4);
     // reload every word of the lane (no per-word branches): simple code, few live masks
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -114,6 +118,7 @@ __device__ __forceinline__ bool gather_norms(const uint64_t* buf, int count, uin
   unsigned spins = 0;
   bool ok = true;
   while (ll_tag(w0) != tag || ll_tag(w1) != tag || ll_tag(w2) != tag || ll_tag(w3) != tag) {
+    __builtin_amdgcn_s_sleep(4);  // as in gather
     w0 = e0 < count ? ll_load_word(buf + 2L * e0) : dummy;
     w1 = e0 < count ? ll_load_word(buf + 2L * e0 + 1) : dummy;
     w2 = e1 < count ? ll_load_word(buf + 2L * e1) : dummy;
