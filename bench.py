@@ -462,6 +462,7 @@ def bench_single(args, workload, x0_scale, steps, warmup, probes=True, latency_s
         "traffic_bytes_per_launch": traffic_bytes,
         "traffic_source": traffic_src,
         "kernel": ("layer_kernel<float, 4, 8, 8, false>" if workload == "c1"
+                   else "small_kernel<double, 8, 8>" if small and grid_wg == 1
                    else f"layer_kernel<{'double' if small else 'float'}, ...>"),
         "alg_bytes_per_unit": bytes_per_unit,
         "avg_launch_us": float(np.mean(kern_ms) * 1e3),
