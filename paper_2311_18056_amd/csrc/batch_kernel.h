@@ -64,8 +64,9 @@ struct BatchArgs {
   // rows are contiguous
   void* Va;                 // layer inputs, 2 parities x blocked bpad x ldk (FP32, or BF16 high)
   void* Vb;                 // BF16 low parts
-  double* CVd;              // check operand [x; y] in FP64 (exact copies of the FP32 iterates, unscaled
-                            // as the outputs are), blocked bpad x ldk
+  double* CVd;              // check operands in FP64 (exact copies of the FP32 iterates, unscaled as the
+                            // outputs are), two blocked bpad x ldk arrays: [x; 0], then [0; y] (the
+                            // zeros are never written)
   double* Rpx;              // B x n: P x of list position p in row p (check scratch)
   double* Raty;             // B x n: A'y likewise
   int* jb;                  // B penalty indices (kept for running and warm-admitted slots)

@@ -351,12 +351,13 @@ struct CheckGeo {
   static constexpr int NST = 2;
   static constexpr size_t SMEM = (size_t)NST * STAGE;
 };
-// acc = sum over k in [kb, ke) of A[row][k] B[col][k]; A rows start at list position arow, B rows
-// at matrix row brow (as / bs: elements per K block). Operand entries with k outside [kb, ke)
-// count as zero (the A side is masked, so a non-finite iterate outside the range does not leak
-// in through a zero matrix entry).
+// acc = sum over the K stages [s0, s1) of A[row][k] B[col][k]; A rows start at list position arow,
+// B rows at matrix row brow (as / bs: elements per K block). No masking: the A operands hold
+// zeros wherever a tile's K range must not contribute (the x part and the y part of the check
+// operand are separate, zero-padded arrays), so a non-finite iterate cannot leak in through a
+// zero matrix entry and the stage loop is the same for every stage.
 __device__ __forceinline__ void check_tile(unsigned char* lds, const double* A, const double* Bm, long arow, long brow,
-                                           long as, long bs, int kb, int ke, doublex4 (&acc)[4][4]) {
+                                           long as, long bs, int s0, int s1, doublex4 (&acc)[4][4]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -364,25 +365,21 @@ __device__ __forceinline__ void check_tile(unsigned char* lds, const double* A, 
   const int lane = threadIdx.x % 64;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), wm = wave / 2, wn = wave % 2;
   kloop<CheckGeo::NST, CheckGeo::LOADS>(
-      kb / TK, (ke + TK - 1) / TK, lds, CheckGeo::STAGE,
+      s0, s1, lds, CheckGeo::STAGE,
       [&](int s, unsigned char* buf) {
         dma_panel<T64, 16>(reinterpret_cast<const unsigned char*>(A + (long)s * as + arow * TK), buf, wave);
         dma_panel<T64, 16>(reinterpret_cast<const unsigned char*>(Bm + (long)s * bs + brow * TK), buf + T64 * 256,
                            wave);
       },
-      [&](int s, const unsigned char* buf) {
+      [&](int, const unsigned char* buf) {
         const unsigned char *pa = buf, *pb = buf + T64 * 256;
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-          const int c = 4 * h + lane / 16, k0 = s * TK + 2 * c;
-          const bool m0 = k0 >= kb && k0 < ke, m1 = k0 + 1 >= kb && k0 + 1 < ke;
+          const int c = 4 * h + lane / 16;
           double2 fa[4], fb[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
+          for (int i = 0; i < 4; ++i)
             fa[i] = *reinterpret_cast<const double2*>(frag_at<16>(pa, wm * 64 + i * 16 + lane % 16, c));
-            fa[i].x = m0 ? fa[i].x : 0.0;
-            fa[i].y = m1 ? fa[i].y : 0.0;
-          }
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             fb[j] = *reinterpret_cast<const double2*>(frag_at<16>(pb, wn * 64 + j * 16 + lane % 16, c));
@@ -576,6 +573,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
   const int n = a.n, m = a.m, L = a.L, B = a.B;
   const long ldk = a.ldk;
   const long vpar = a.bpad * ldk;  // elements per parity of V
+  const long cvy = a.bpad * ldk;   // the y part of the check operand follows the x part
   // elements per K block of the operands, the layer matrices and the check matrix
   const long as = a.bpad * TK, bs = a.lpad * TK, cs = a.cpad * TK;
   const int NX = (n + T64 - 1) / T64, NC = (m + T64 - 1) / T64;  // check row tiles: x rows, constraint rows
@@ -640,7 +638,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
         const long el = base + u * gstride;
         if (el >= (long)B * L || st[u] != kSlotAdmitWarm) continue;
         const int r = (int)(el % L);
-        a.CVd[opidx(a.bpad, ps[u], r)] = (double)xv[u] * (a.scl && r < n ? a.scl[2 * n + 2 * m + r] : 1.0);
+        if (r < n) a.CVd[opidx(a.bpad, ps[u], r)] = (double)xv[u] * (a.scl ? a.scl[2 * n + 2 * m + r] : 1.0);
       }
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
@@ -653,7 +651,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
       const int r0 = n + tw.nt(t) * T64;
       load_list(a.lists, mt);
       doublex4 acc[4][4];
-      check_tile(lds, a.CVd, a.Cd, mt.off, r0, as, cs, 0, n, acc);
+      check_tile(lds, a.CVd, a.Cd, mt.off, r0, as, cs, 0, (n + TK - 1) / TK, acc);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -769,7 +767,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
               at32(ae.Z, om[v] + ri) = zn;
               at32(ae.Y, om[v] + ri) = yn;
               if (is_check)
-                at32(ae.CVd, obase + oo[v]) = (double)(float)((double)yn * fy);
+                at32(ae.CVd + cvy, obase + oo[v]) = (double)(float)((double)yn * fy);
               else
                 put_operand32<PREC>(vo, vo2, obase + oo[v], rho * zn - yn);
             }
@@ -794,7 +792,8 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
         const int r0 = kind == 2 ? n + (u - 2 * NX) * T64 : (u - kind * NX) * T64;
         load_list(a.lists, mt);
         doublex4 acc[4][4];
-        check_tile(lds, a.CVd, a.Cd, mt.off, r0, as, cs, kind == 1 ? n : 0, kind == 1 ? L : n, acc);
+        check_tile(lds, kind == 1 ? a.CVd + cvy : a.CVd, a.Cd, mt.off, r0, as, cs, kind == 1 ? n / TK : 0,
+                   kind == 1 ? (L + TK - 1) / TK : (n + TK - 1) / TK, acc);
         double* const R = kind == 0 ? a.Rpx : a.Raty;
 #pragma unroll
         for (int i = 0; i < 4; ++i)

@@ -127,7 +127,7 @@ struct relu_qp_handle {
   float* bY = nullptr;
   void* bVa = nullptr;
   void* bVb = nullptr;
-  double* bCVd = nullptr;  // FP64 check operand [x; y], K-blocked
+  double* bCVd = nullptr;  // FP64 check operands [x; 0] and [0; y], K-blocked
   double* bRpx = nullptr;  // check scratch: P x and A'y per list position (B x n each, FP64)
   double* bRaty = nullptr;
   int* bjb = nullptr;
@@ -587,7 +587,7 @@ int setup_batched(relu_qp_handle* h, const double* P, const double* q, const dou
   const size_t es = h->bprec == rqp::kBatchBF16x3 ? 2 : 4;
   const size_t nr = h->grid.size();
   const size_t wbytes = nr * (size_t)h->w_stride * es, cbytes = (size_t)h->cpad * h->ldk * 8;
-  const size_t vbytes = (size_t)h->bpad * h->ldk * es, cvbytes = (size_t)h->bpad * h->ldk * 8;
+  const size_t vbytes = (size_t)h->bpad * h->ldk * es, cvbytes = 2 * (size_t)h->bpad * h->ldk * 8;
   const size_t ntile_max = (size_t)B / rqp::kTileM + nr + 1;
   auto al = [h](void** p, size_t bytes) { return dmalloc(h, p, bytes) == hipSuccess; };
   const bool two = h->bprec == rqp::kBatchBF16x3;
@@ -1710,7 +1710,7 @@ int relu_qp_footprint(int n, int m, const relu_qp_settings* s, int nx, size_t* b
     const size_t ntile_max = B / rqp::kTileM + nr + 1;
     const size_t nw = two ? 2 : 1;
     t += nw * (nr * w_stride * es + 2 * vbytes);                   // layer weights, V (two parities)
-    t += check_rows(L) * ldk * 8 + bpad * ldk * 8;                 // FP64 check matrix and operand
+    t += check_rows(L) * ldk * 8 + 2 * bpad * ldk * 8;             // FP64 check matrix and operands
     t += 2 * B * n * 8;                                            // check scratch (P x, A'y)
     t += B * n * 4 + 2 * B * m * 4;                                // x, z, y
     t += B * 4 + B * 64 + B * 4 + B * 4;                           // penalty index, norms, lists, positions
