@@ -451,6 +451,26 @@ def test_wide_rows_streamed_fp32(rq):
     assert np.max(dy[eq]) <= 1e-4 * rho_eq * max(np.max(np.abs(ref.z)), 1.0)
 
 
+def test_maximum_size_fp32(rq):
+    """n + m = 8192, the largest problem the single-instance engine accepts (n = 4096, 96
+    equality and 4000 inequality rows): 25 iterations and one check against the oracle with the
+    schedule replayed, and one row past the limit rejected at setup."""
+    P, q, A, l, u = random_qp(4096, 96, 4000, seed=17)
+    res = _fixed_run(rq, P, q, A, l, u, "fp32", 25, n_rho=8)
+    ref = oracle.solve(P, q, A, l, u, _oracle_settings(eps_abs=0.0, eps_rel=0.0, max_iter=25, n_rho=8),
+                       rho_replay=res["rho_hist"])
+    _close(res["x"], ref.x, 1e-4, "x")
+    _close(res["z"], ref.z, 1e-4, "z")
+    eq = l == u
+    dy = np.abs(res["y"] - ref.y)
+    assert np.max(dy[~eq]) <= 1e-4 * max(np.max(np.abs(ref.y)), 1.0)
+    rho_eq = max(admm.rho_grid(_oracle_settings(n_rho=8))[j] for j in res["rho_hist"] + [2]) * 1e3
+    assert np.max(dy[eq]) <= 1e-4 * rho_eq * max(np.max(np.abs(ref.z)), 1.0)
+    A1 = np.vstack([A, A[:1]])
+    with pytest.raises(rq.ReluQPError):
+        rq.Solver(P, q, A1, np.append(l, l[0] - 1.0), np.append(u, u[0] + 1.0), precision="fp32")
+
+
 def test_c2_humanoid_shape_fp32(rq):
     """Configuration 2 (n = 600 controls, m = 1800: control limits and condensed state limits),
     FP32: 100 fixed iterations against the oracle with the GPU's schedule replayed, and a solve
