@@ -406,40 +406,50 @@ struct MTile {
 // Workgroup g runs on XCD g % 8 (consecutive workgroups of a launch go round-robin over the
 // eight XCDs); each XCD takes a contiguous range of M tiles (of N tiles when there are fewer M
 // tiles than XCDs) and walks it with the M index fastest, so that the workgroups of one XCD
-// work on a compact block of tiles at a time and share operand stages through its L2.
+// work on a compact block of tiles at a time and share operand stages through its L2. When the
+// M tiles do not split evenly over the XCDs, the XCD with the most of them can need more rounds
+// of its workgroups than an even share of the pairs would (29 M tiles x 25 N tiles: 4 rounds
+// where 3 suffice); then each XCD takes an equal contiguous range of the pairs in M-fastest
+// order instead (balanced), which costs L2 locality, so only when it saves a round and only for
+// the layer GEMM (may_balance): the FP64 check tiles read twice the operand bytes of a layer tile and
+// measured no faster balanced.
 struct TileWalk {
-  int per, count, mx, m0, n0, nmt;
-  bool by_m;
-  __device__ __forceinline__ TileWalk(int nmt_, int n_begin, int n_end) : nmt(nmt_) {
+  int per, count, mx, m0, n0, p0;  // pair j of this XCD: M tile m0 + (p0 + j) % mx, N tile n0 + (p0 + j) / mx
+  __device__ __forceinline__ TileWalk(int nmt, int n_begin, int n_end, bool may_balance = false) {
     const int G = gridDim.x, x = blockIdx.x % 8, nn = n_end - n_begin;
+    p0 = 0;
+    m0 = 0;
+    mx = nmt;
+    n0 = n_begin;
     if (G % 8 != 0) {  // no XCD structure assumed: plain round robin
       per = G;
-      by_m = true;
-      m0 = 0;
-      mx = nmt;
-      n0 = n_begin;
       count = nmt * nn;
       return;
     }
     per = G / 8;
-    by_m = nmt >= 8;
-    if (by_m) {
+    bool bal = false;
+    if (may_balance && nmt >= 8) {
+      const int most = (nmt + 7) / 8 * nn, even = (nmt * nn + 7) / 8;  // pairs of the busiest XCD
+      bal = (even + per - 1) / per < (most + per - 1) / per;
+    }
+    if (bal) {
+      const int T = nmt * nn;
+      p0 = x * T / 8;
+      count = (x + 1) * T / 8 - p0;
+    } else if (nmt >= 8) {
       m0 = x * nmt / 8;
       mx = (x + 1) * nmt / 8 - m0;
-      n0 = n_begin;
       count = mx * nn;
     } else {
       const int nb = n_begin + x * nn / 8, ne = n_begin + (x + 1) * nn / 8;
-      m0 = 0;
-      mx = nmt;
       n0 = nb;
       count = nmt * (ne - nb);
     }
   }
   // workgroup l of an XCD takes tiles l, l + per, ...
   __device__ int first() const { return gridDim.x % 8 != 0 ? blockIdx.x : blockIdx.x / 8; }
-  __device__ int mt(int j) const { return m0 + j % mx; }
-  __device__ int nt(int j) const { return n0 + j / mx; }
+  __device__ int mt(int j) const { return m0 + (p0 + j) % mx; }
+  __device__ int nt(int j) const { return n0 + (p0 + j) / mx; }
 };
 
 // Bucket sort of the slots in state `want` by penalty index into lists[] and the M-tile table
@@ -682,7 +692,7 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
     const int nmt = a.mtiles[0];
     const MTile* mts = reinterpret_cast<const MTile*>(a.mtiles + 1);
     const long vin = (long)(k & 1) * vpar, vout = (long)((k + 1) & 1) * vpar;
-    const TileWalk tw(nmt, 0, ntiles_n);
+    const TileWalk tw(nmt, 0, ntiles_n, true);
 
     // ---- layer GEMM + fused update
     for (int t = tw.first(); t < tw.count; t += tw.per) {

@@ -133,6 +133,42 @@ def test_alone_equals_in_the_mix(rq, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_balanced_tile_walk(rq, prec):
+    """9 instance tiles x 24 row tiles (n + m = 1500, 64-row tiles) do not split evenly over the
+    eight XCDs: by whole instance tiles one XCD would run 2 x 24 tiles in two rounds of its 32
+    workgroups, so the layer GEMM walks an even share of the pairs per XCD instead (one round).
+    Sampled instances match the oracle with their schedules replayed, and alone (one tile on
+    one XCD) equals in the mix bit for bit."""
+    P, q0, A, l0, u0 = random_qp(900, 0, 600, seed=43)
+    B = 9 * 128
+    rng = np.random.default_rng(9)
+    q = q0[None, :] + 0.5 * rng.standard_normal((B, 900))
+    l = np.repeat(l0[None, :], B, axis=0)
+    u = np.repeat(u0[None, :], B, axis=0)
+    kw = dict(precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=50)
+    sol = rq.Solver(P, q, A, l, u, **kw)
+    sol.set_tile(64)
+    sol.solve()
+    res = sol.result()
+    sol.close()
+    tol = 1e-4 if prec == "fp32" else 5e-3
+    for b in (0, 600, B - 1):
+        ref = oracle.solve(P, q[b], A, l[b], u[b], _os(n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=50),
+                           rho_replay=res["rho_hist"][b][:2].tolist())
+        for name in ("x", "z", "y"):
+            assert _rel(res[name][b], getattr(ref, name)) <= tol, (prec, b, name)
+    for b in (5, B - 2):
+        one = rq.Solver(P, q[b:b + 1], A, l[b:b + 1], u[b:b + 1], **kw)
+        one.set_tile(64)
+        one.solve()
+        r1 = one.result(0)
+        one.close()
+        assert r1["iterations"] == res["iterations"][b] and r1["status"] == res["status"][b]
+        for name in ("x", "z", "y"):
+            assert np.array_equal(r1[name], res[name][b]), (prec, b, name)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_batch_solves_to_tolerance(rq, prec):
     prob = make_config("c0")
     B = 64
