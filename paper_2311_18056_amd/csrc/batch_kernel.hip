@@ -571,7 +571,6 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
   (void)a_in;
   const cargs_t kp = (cargs_t)__builtin_amdgcn_kernarg_segment_ptr();
   const auto& a = *fresh(kp);
-  constexpr int BJ = TNV / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned char* const lds = smem_raw;  // operand stages of the layer and check GEMMs
   __shared__ int s_count[64];
@@ -587,7 +586,16 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
   // elements per K block of the operands, the layer matrices and the check matrix
   const long as = a.bpad * TK, bs = a.lpad * TK, cs = a.cpad * TK;
   const int NX = (n + T64 - 1) / T64, NC = (m + T64 - 1) / T64;  // check row tiles: x rows, constraint rows
-  const int ntiles_n = (L + TNV - 1) / TNV;
+  // Row tiles of the layer GEMM: TNV rows each, except that the last TNV rows (or fewer) go in
+  // tiles of TNS = TNV / 2 rows. The walks take row tiles in increasing order, so these come in
+  // the last round of workgroups, which otherwise costs a whole round of TNV-row tiles however
+  // few of them it holds (4096 instances x 3200 rows at 128 rows: 800 tiles, 32 in the fourth
+  // round of 256 workgroups). Which rows a tile shape covers depends only on L and TNV, so an
+  // instance's arithmetic is the same alone and in any batch.
+  constexpr int TNS = TNV >= 128 ? TNV / 2 : TNV;
+  static_assert(LayerGeo<TNS>::SMEM <= LayerGeo<TNV>::SMEM, "the small row tiles fit the large ones' LDS");
+  const int nbig = TNV >= 128 ? (L - 1) / TNV : (L + TNV - 1) / TNV;
+  const int ntiles_n = nbig + (L - nbig * TNV + TNS - 1) / TNS;
   const float alpha = (float)a.alpha, oma = (float)(1.0 - a.alpha), sigma = (float)a.sigma;
   const float eqs = (float)a.rho_eq_scale;
   unsigned epoch = 0;
@@ -694,19 +702,19 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
     const long vin = (long)(k & 1) * vpar, vout = (long)((k + 1) & 1) * vpar;
     const TileWalk tw(nmt, 0, ntiles_n, true);
 
-    // ---- layer GEMM + fused update
-    for (int t = tw.first(); t < tw.count; t += tw.per) {
+    // ---- layer GEMM + fused update: one tile of TR rows starting at matrix row r0
+    auto layer_step = [&](auto TRc, int mti, int r0) __attribute__((always_inline)) {
+      constexpr int TR = decltype(TRc)::value, BJR = TR / 64;
       const auto& a = *fresh(kp);
-      const MTile mt = mts[tw.mt(t)];
-      const int nt = tw.nt(t);
+      const MTile mt = mts[mti];
       load_list(a.lists, mt);
       constexpr long es = PREC == kBatchBF16x3 ? 2 : 4;
       const unsigned char* Aa = static_cast<const unsigned char*>(a.Va) + vin * es;
       const unsigned char* Ab = a.Vb ? static_cast<const unsigned char*>(a.Vb) + vin * es : nullptr;
       const unsigned char* Ba = static_cast<const unsigned char*>(a.Wa) + (long)mt.j * a.w_stride * es;
       const unsigned char* Bb = a.Wb ? static_cast<const unsigned char*>(a.Wb) + (long)mt.j * a.w_stride * es : nullptr;
-      floatx16 acc[2][BJ];
-      layer_tile<PREC, TNV>(lds, Aa, Ab, Ba, Bb, mt.off, (long)nt * TNV, as, bs, L, acc);
+      floatx16 acc[2][BJR];
+      layer_tile<PREC, TR>(lds, Aa, Ab, Ba, Bb, mt.off, (long)r0, as, bs, L, acc);
       const float rho_bar = s_rho[mt.j];
       // epilogue, one 32 x 32 block at a time (block indices are compile-time constants, so the
       // accumulators stay in registers). A lane's 16 elements of a block share its column r (one
@@ -731,9 +739,9 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
           oo[v] = (unsigned)ti * TK;
           ok[v] = ti < mt.cnt;
         }
-        static_for<0, BJ>([&](auto J) {
+        static_for<0, BJR>([&](auto J) {
           constexpr int j = decltype(J)::value;
-          const int r = nt * TNV + acc_col<TNV>(wn, j, lane);
+          const int r = r0 + acc_col<TR>(wn, j, lane);
           if (r >= L) return;
           // operand index of element v: obase + oo[v] (K-blocked, list position mt.off + ti)
           const unsigned obase = ((unsigned)(r / TK) * (unsigned)ae.bpad + (unsigned)mt.off) * TK + (unsigned)(r % TK);
@@ -784,6 +792,13 @@ __global__ void __launch_bounds__(BS) batch_kernel(BatchArgs a_in) {
           }
         });
       });
+    };
+    for (int t = tw.first(); t < tw.count; t += tw.per) {
+      const int nt = tw.nt(t);
+      if (nt < nbig)
+        layer_step(std::integral_constant<int, TNV>{}, tw.mt(t), nt * TNV);
+      else
+        layer_step(std::integral_constant<int, TNS>{}, tw.mt(t), nbig * TNV + (nt - nbig) * TNS);
     }
     if (!grid_barrier(a.bar, ++epoch)) return;
     if (!is_check) continue;
