@@ -731,11 +731,13 @@ struct TileChoice {
 std::mutex g_tile_mu;
 std::map<TileKey, TileChoice> g_tile_cache;
 
-// The shape with the fewest microseconds per iteration (ties to the earlier candidate).
+// The shape with the fewest microseconds per iteration; a later candidate must be faster by more
+// than 1 % (about the spread of repeated timings) to replace an earlier one, so near-ties go to
+// the earlier shape in the candidate order (128, 64, 256 rows).
 int best_tile(const relu_qp_handle* h) {
   int best = 0;
   for (int v = 1; v < rqp::kTileShapes; ++v)
-    if (h->tile_us[v] < h->tile_us[best]) best = v;
+    if (h->tile_us[v] < 0.99 * h->tile_us[best]) best = v;
   return best;
 }
 

@@ -261,7 +261,8 @@ def test_batch_ragged_tiles_mixed_statuses(rq):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
-    """The autotuner times every tile shape at setup and keeps the fastest; each shape, forced,
+    """The autotuner times every tile shape at setup and keeps the fastest (a later candidate only
+    if more than 1 % faster); each shape, forced,
     matches the oracle with its own schedule replayed. (The shapes agree to rounding only: the
     matrix cores are fed the same products per element, but in another interleaving.)"""
     P, q0, A, l0, u0 = random_qp(150, 0, 80, seed=41)
@@ -273,7 +274,12 @@ def test_tile_shapes_autotuned_and_both_match_the_oracle(rq, prec):
     sol = rq.Solver(P, q, A, l, u, precision=prec, engine="batch", n_rho=8, eps_abs=0.0, eps_rel=0.0, max_iter=60)
     tn, us = sol.tile()
     assert tn in (64, 128, 256) and all(us[k] > 0 for k in (64, 128, 256))
-    assert us[tn] == min(us.values())
+    # the candidates in order 128, 64, 256; a later one wins only if more than 1 % faster
+    pick = 128
+    for k in (64, 256):
+        if us[k] < 0.99 * us[pick]:
+            pick = k
+    assert tn == pick and 0.99 * us[tn] <= min(us.values())
     tol = 1e-4 if prec == "fp32" else 5e-3
     for shape in (128, 64, 256):
         sol.set_tile(shape)
