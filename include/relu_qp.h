@@ -246,10 +246,12 @@ int relu_qp_admit(relu_qp_handle* h, const int* slots, int n_slots, int src_slot
  * Needs max_iter % check_interval == 0 (RQP_EINVAL otherwise). */
 int relu_qp_step(relu_qp_handle* h, int n_checks, void* stream, relu_qp_result* out);
 
-/* Tile shape of the batched engine's GEMM: 128, 64 or 256 matrix rows per tile (x 128 instances).
+/* Tile shape of the batched engine's GEMM: 128, 64 or 256 matrix rows per tile (x 128 instances);
+ * with 128 or 256, the last that many rows of the layer go in tiles of half the rows, run last.
  * relu_qp_setup of a batched handle runs an autotuner: every shape runs two check intervals of
- * all slots on the handle's own data, timed on the device, and the faster is kept (slots are
- * idle and the state zero afterwards). The choice and timings are cached for the rest of the
+ * all slots on the handle's own data, timed on the device, and the fastest is kept, where a
+ * shape later in the order 128, 64, 256 must be more than 1 % faster than an earlier one (slots
+ * are idle and the state zero afterwards). The choice and timings are cached for the rest of the
  * process per device and problem shape (n, m, batch, precision, number of penalties): a later
  * handle of the same shape (a family loaded again) takes them without timing. The shapes
  * agree to rounding (the same products per element, issued to the matrix cores in another
