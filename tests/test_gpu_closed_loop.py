@@ -2,7 +2,9 @@
 the applied control and the plant step in one launch) against the FP64 closed-loop oracle.
 
 Tolerances per trajectory (||a - b||_inf <= tol * max(||b||_inf, 1)): 1e-9 in FP64, 1e-4 in
-FP32, for the plant states, the applied controls and every step's x, z, y.
+FP32, for the plant states, the applied controls and every step's x, z, y. In FP32 the dual of
+an equality row, y = rho_eq (t - z) with rho_eq = 1000 rho, carries the rounding of t times
+rho_eq: those entries are compared at 1e-4 * rho_eq * max(||z||_inf, 1).
 """
 
 import numpy as np
@@ -41,6 +43,7 @@ def _run(rq, prob, x0, steps, prec, **settings):
     sol.set_parametric(prob.F, prob.E, prob.lo, prob.hi)
     out = sol.closed_loop(_dev(x0), steps, _dev(prob.A_dyn), _dev(prob.B), prob.nu)
     res = {k: v.cpu().numpy() for k, v in out.items() if k != "_result"}
+    res["_grid"] = np.asarray(sol.rho_grid(), dtype=np.float64)
     sol.close()
     return res
 
@@ -84,9 +87,17 @@ def test_closed_loop_fp32_full_size(rq):
     xs, us, res = _oracle(prob, x0, steps, **kw)
     _close(g["traj_x"], xs, 1e-4, "plant states")
     _close(g["traj_u"], us, 1e-4, "controls")
-    for s in (0, steps // 2, steps - 1):
+    eq = prob.lo == prob.hi
+    for s in range(steps):
         for name in ("x", "z"):
             _close(g[name][s], getattr(res[s], name), 1e-4, f"step {s} {name}")
+        dy = np.abs(g["y"][s] - res[s].y)
+        scale = max(np.max(np.abs(res[s].y)), 1.0)
+        assert np.max(dy[~eq]) <= 1e-4 * scale, f"step {s} y (inequality rows)"
+        if eq.any():
+            rho_eq = g["_grid"][g["rho_index"][s]] * 1e3
+            e = np.max(dy[eq]) / (rho_eq * max(np.max(np.abs(res[s].z)), 1.0))
+            assert e <= 1e-4, f"step {s} y (equality rows) / rho_eq: {e:.3e}"
     assert np.max(np.abs(us)) > 0.99  # the limits bind
     assert np.max(np.abs(g["traj_u"])) <= 1.0 + 1e-6
 
